@@ -1,0 +1,242 @@
+/*
+ * frnn.h — C ABI of libfrnn, exact fixed-radius nearest-neighbour search on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Sec. 1, Eq. 1): for query x_i and reference points x_j,
+ *
+ *     N_r(i) = { j : ||x_i - x_j||_2 <= r }
+ *
+ * optionally keeping at most K neighbours in distance order (Sec. 1, the
+ * sentence after Eq. 1).  Membership is decided in float32 exactly as follows
+ * (the paper requires float32 membership to be reproduced exactly, Sec. 4.2):
+ *
+ *     r2      = fl32(r * r)                          one rounded multiply
+ *     s(i,j)  = +0; for d = 0..D-1: t = fl32(q_d - x_d); u = fl32(t*t);
+ *               s = fl32(s + u)                      no fused multiply-add
+ *     j is a neighbour of i  <=>  s(i,j) <= r2      inclusive boundary
+ *
+ * Each row is ordered by (s, j) ascending (s as a float, j as an integer) and,
+ * when K > 0, cut to its first min(|row|, K) entries.  Subnormals are kept.
+ * The result is unique; the GPU output is bit-identical to a brute force.
+ *
+ * Conventions for every call:
+ *  - Point arrays are row-major [n][D] float32.  Pointers marked "device" are
+ *    HIP device pointers owned by the caller; the library only reads them,
+ *    and only during the call's stream work.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work of a call is ordered on that stream.  Calls that must learn
+ *    a size (the number of output pairs) synchronise that stream once.
+ *  - Every call returns a status and never aborts; no C++ exception crosses
+ *    this boundary.  On error, outputs are zeroed and frnn_last_error()
+ *    (thread-local) holds a message.
+ *  - Output CSR buffers are device memory owned by the library until
+ *    frnn_csr_release().  offsets are int64 [M+1], indices int32 [nnz]
+ *    (reference ids local to their event, 0-based), dist2 float32 [nnz].
+ *  - Sizes: 1 <= D <= 32; N, M < 2^31; r finite and >= 0.
+ */
+#ifndef FRNN_H
+#define FRNN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FRNN_OK = 0,
+    FRNN_ERR_INVALID_ARG = 1, /* bad size, pointer, radius or flag */
+    FRNN_ERR_NONFINITE = 2,   /* a coordinate is NaN or infinite */
+    FRNN_ERR_OOM = 3,         /* device allocation failed */
+    FRNN_ERR_BUDGET = 4,      /* request larger than the server's HBM budget */
+    FRNN_ERR_RADIUS = 5,      /* query radius larger than the index radius */
+    FRNN_ERR_HIP = 6,         /* a HIP runtime call failed */
+    FRNN_ERR_INTERNAL = 7,    /* an internal consistency check failed */
+    FRNN_ERR_NOT_READY = 8    /* server ticket still in flight (poll only) */
+} frnn_status;
+
+/* Query flags. */
+enum {
+    FRNN_WANT_DIST2 = 1,   /* also return dist2 (the s values) */
+    FRNN_SELF_QUERY = 2,   /* queries are the indexed points (queries = NULL) */
+    FRNN_EXCLUDE_SELF = 4  /* with FRNN_SELF_QUERY: leave j == i out of row i */
+};
+
+typedef struct frnn_index_s *frnn_index;   /* opaque, immutable after build */
+typedef struct frnn_server_s *frnn_server; /* opaque */
+
+/* CSR neighbour lists.  Device pointers; library-owned until released. */
+typedef struct {
+    int64_t M;        /* number of rows (queries) */
+    int64_t nnz;      /* number of (query, reference) pairs */
+    int64_t *offsets; /* [M+1], offsets[0] = 0, row i is [offsets[i], offsets[i+1]) */
+    int32_t *indices; /* [nnz] reference ids, each row ordered by (dist2, id) */
+    float *dist2;     /* [nnz] s(i, j), or NULL without FRNN_WANT_DIST2 */
+    void *owner_;     /* library-private */
+} frnn_csr;
+
+/* Kernel and grid parameters.  Every setting gives the same output; they
+ * only change speed.  Fill with frnn_opts_default() and override fields. */
+typedef struct {
+    int32_t grid_axes_max;    /* most coordinates the cell grid may use (0..6) */
+    float cells_per_point;    /* cap on grid cells per indexed point */
+    int32_t cell_multiple;    /* m: cell width about r/m, reach +-m cells (1..3) */
+    int32_t cells_per_item;   /* grid cells along the first grid axis per work item (1..8) */
+    int32_t queries_per_item; /* queries evaluated per work item (1..64) */
+    int32_t persistent;       /* 1: persistent kernel draining a device work queue */
+    int32_t blocks_per_cu;    /* persistent grid size = 256 CUs x this (1..16) */
+    int32_t row_cap_lds;      /* rows longer than this sort in global memory (1..512) */
+} frnn_opts;
+
+void frnn_opts_default(frnn_opts *opts);
+
+/* Build an index (cell grid, sorted copy of the points) over N points of
+ * dimension D for queries of radius at most r.  points: device [N][D].
+ * Grid cell keys are computed in float64 with cell width above r, so that no
+ * pair whose float32 s is <= fl32(r*r) can lie in non-adjacent cells (the
+ * "roundoff-safe grid" of Sec. 4.2).  opts may be NULL.  Synchronises the
+ * stream once (to report non-finite input).
+ * Errors: INVALID_ARG, NONFINITE, OOM, HIP. */
+frnn_status frnn_build(const float *points, int64_t N, int32_t D, float r,
+                       const frnn_opts *opts, void *stream, frnn_index *out);
+
+/* Query an index.  queries: device [M][D], or NULL with FRNN_SELF_QUERY (then
+ * M must equal N).  r <= the build radius (else FRNN_ERR_RADIUS).  K <= 0:
+ * every neighbour; K > 0: the first min(deg, K) of each row.  Counting pass,
+ * exact-size allocation, then fill (the count-first allocation of Sec. 4.2).
+ * Synchronises the stream once (to learn nnz).
+ * Errors: INVALID_ARG, NONFINITE, RADIUS, OOM, HIP. */
+frnn_status frnn_query(frnn_index idx, const float *queries, int64_t M, float r,
+                       int32_t K, uint32_t flags, void *stream, frnn_csr *out);
+
+void frnn_index_destroy(frnn_index idx);
+
+/* Grid chosen for an index (for reports and tests). */
+typedef struct {
+    int64_t N;
+    int32_t D;
+    int32_t grid_axes;        /* G */
+    int32_t axis[8];          /* coordinate used by each grid axis */
+    int32_t cells_per_axis[8];
+    int64_t cells;            /* product of cells_per_axis */
+    double cell_width;
+    int32_t cell_multiple;
+} frnn_index_info;
+
+frnn_status frnn_index_get_info(frnn_index idx, frnn_index_info *info);
+
+/* One event of a batch: its own reference points and, unless the batch is a
+ * self-query, its own queries.  Device pointers. */
+typedef struct {
+    const float *points;
+    int64_t N;
+    const float *queries; /* NULL with FRNN_SELF_QUERY */
+    int64_t M;            /* ignored with FRNN_SELF_QUERY */
+} frnn_event;
+
+/* Many independent events, one pipeline: the events are binned, counted and
+ * filled by single launches (a persistent kernel drains (event, cell block)
+ * work items), the fixed pipeline is replayed as a HIP graph when the same
+ * capacity recurs, and outs[e] is bit-identical to querying event e alone.
+ * All events share D, r, K and flags.  Synchronises the stream once.
+ * The outs[] share one allocation; release each of them.
+ * Errors: INVALID_ARG, NONFINITE, OOM, HIP. */
+frnn_status frnn_query_batch(const frnn_event *events, int32_t E, int32_t D,
+                             float r, int32_t K, uint32_t flags,
+                             const frnn_opts *opts, void *stream, frnn_csr *outs);
+
+/* Copy a CSR into caller buffers (device, or host when to_host != 0); any of
+ * the three destinations may be NULL to skip it.  Synchronous when to_host. */
+frnn_status frnn_csr_copy(const frnn_csr *csr, int64_t *offsets, int32_t *indices,
+                          float *dist2, int32_t to_host, void *stream);
+
+/* Return a CSR's buffers to the library's pool; the struct is zeroed. */
+void frnn_csr_release(frnn_csr *csr);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop on its own host thread and streams.  Submitted events are
+ * admitted against an HBM budget, batched with whatever else is queued into
+ * the batched pipeline, and their results stay in device memory.  Batches
+ * overlap on the device: a new batch is binned and counted while earlier
+ * ones are still being filled.  Each result is bit-identical to the same
+ * event queried alone. */
+typedef struct {
+    int32_t D;
+    float r;
+    int32_t K;
+    uint32_t flags;            /* FRNN_SELF_QUERY is implied */
+    int64_t hbm_budget_bytes;  /* device bytes the server may hold at once */
+    int32_t max_batch_events;  /* cap on events per batch (1..1024) */
+    int32_t max_inflight;      /* batches on the device at once (1..8) */
+    frnn_opts opts;
+} frnn_server_opts;
+
+typedef struct {
+    double submit_s;    /* host clock, seconds: submission */
+    double admit_s;     /* admitted against the budget */
+    double start_s;     /* its batch was launched */
+    double done_s;      /* result complete on the device and observed */
+    int32_t batch_id;
+    int32_t batch_events;
+} frnn_timing;
+
+void frnn_server_opts_default(frnn_server_opts *o);
+frnn_status frnn_server_create(const frnn_server_opts *o, frnn_server *out);
+/* points: host [N][D] float32, copied before the call returns. */
+frnn_status frnn_server_submit(frnn_server s, const float *points, int64_t N,
+                               uint64_t *ticket);
+/* Blocks until the ticket completes (timeout_s < 0: forever; 0: poll and
+ * return FRNN_ERR_NOT_READY).  Hands the result to the caller (release it). */
+frnn_status frnn_server_wait(frnn_server s, uint64_t ticket, double timeout_s,
+                             frnn_csr *out, frnn_timing *timing);
+void frnn_server_destroy(frnn_server s);
+
+/* ---------------------------------------------------------------- tuning
+ * Times candidate frnn_opts on the given input (a self-query with K) and
+ * returns the fastest whose output is bit-identical to the default's.  The
+ * result is cached per (device, D, density class, K) in the JSON file named
+ * by FRNN_TUNE_CACHE, if set.  Errors as frnn_query. */
+typedef struct {
+    int32_t candidates_tried;
+    int32_t candidates_rejected; /* output differed from the default's */
+    double best_ms;
+    double default_ms;
+} frnn_tune_report;
+
+frnn_status frnn_tune(const float *points, int64_t N, int32_t D, float r, int32_t K,
+                      uint32_t flags, void *stream, frnn_opts *best,
+                      frnn_tune_report *report);
+
+/* ------------------------------------------------------- instrumentation
+ * When enabled, every launch is bracketed by HIP events on its own stream and
+ * per-kernel totals accumulate until read. */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} frnn_kernel_time;
+
+void frnn_profile_enable(int32_t on);
+int32_t frnn_profile_read(frnn_kernel_time *out, int32_t cap, int32_t reset);
+
+/* Work counters of the most recent query or batch on this thread. */
+typedef struct {
+    int64_t candidates;   /* (query, reference) pairs whose distance was evaluated */
+    int64_t work_items;
+    int64_t pairs;        /* output pairs (after the cap) */
+    int64_t long_row_keys; /* keys of rows sorted by the global-memory path */
+} frnn_stats;
+
+frnn_status frnn_last_stats(frnn_stats *out);
+
+/* Device bytes held by the pools (current and peak). */
+void frnn_memory_stats(int64_t *current_bytes, int64_t *peak_bytes);
+
+const char *frnn_status_str(frnn_status s);
+const char *frnn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRNN_H */

@@ -1,0 +1,445 @@
+// Batched pipeline with HIP-graph replay (see frnn_batch.h).
+#include "frnn_batch.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "frnn_launch.h"
+
+namespace frnn {
+
+static int64_t round_class(int64_t n) {
+    // 2^k x {1, 1.25, 1.5, 1.75}, at least 4096
+    int64_t p = 4096;
+    if (n <= p) return p;
+    while (p * 2 <= n) p *= 2;
+    for (int q = 0; q <= 4; ++q) {
+        int64_t c = p + p * q / 4;
+        if (c >= n) return c;
+    }
+    return 2 * p;
+}
+
+static int next_pow2(int n) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+bool BatchContext::Shape::operator==(const Shape &x) const {
+    return D == x.D && flags == x.flags && K == x.K && r == x.r && E_cap == x.E_cap &&
+           pts_cap == x.pts_cap && q_cap == x.q_cap && cells_cap == x.cells_cap &&
+           pch_cap == x.pch_cap && qch_cap == x.qch_cap && std::memcmp(&o, &x.o, sizeof(o)) == 0;
+}
+
+BatchContext::Shape BatchContext::shape_for(const frnn_event *ev, int E, int D, float r, int K,
+                                            uint32_t flags, const Opts &o) {
+    Shape sh{};
+    sh.D = D;
+    sh.flags = flags;
+    sh.K = K;
+    sh.r = r;
+    sh.o = o.o;
+    const bool selfq = flags & FRNN_SELF_QUERY;
+    int64_t tp = 0, tq = 0;
+    for (int e = 0; e < E; ++e) {
+        tp += ev[e].N;
+        tq += selfq ? ev[e].N : ev[e].M;
+    }
+    sh.E_cap = next_pow2(E);
+    sh.pts_cap = round_class(tp);
+    sh.q_cap = selfq ? sh.pts_cap : round_class(tq);
+    sh.cells_cap = (int64_t)std::ceil((double)o.o.cells_per_point * (double)sh.pts_cap) + sh.E_cap;
+    sh.pch_cap = (int)(sh.pts_cap / kChunkRows + sh.E_cap);
+    sh.qch_cap = (int)(sh.q_cap / kChunkRows + sh.E_cap);
+    return sh;
+}
+
+bool BatchContext::fits(const Shape &n) const {
+    return sh_.D == n.D && sh_.flags == n.flags && sh_.K == n.K && sh_.r == n.r &&
+           std::memcmp(&sh_.o, &n.o, sizeof(n.o)) == 0 && sh_.E_cap >= n.E_cap &&
+           sh_.pts_cap >= n.pts_cap && sh_.q_cap >= n.q_cap && sh_.cells_cap >= n.cells_cap &&
+           sh_.pch_cap >= n.pch_cap && sh_.qch_cap >= n.qch_cap;
+}
+
+BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
+    const int D = sh.D;
+    Dp_ = (D + 3) & ~3;
+    const bool selfq = sh.flags & FRNN_SELF_QUERY;
+    const int Ec = sh.E_cap;
+    bd_b.reset(sizeof(BatchDesc), s);
+    ev_b.reset(sizeof(EventDev) * Ec, s);
+    pch.reset(sizeof(Chunk) * sh.pch_cap, s);
+    qch.reset(sizeof(Chunk) * sh.qch_cap, s);
+    ctr_b.reset(sizeof(Counters), s);
+    hv.reset(sizeof(Counters) + sizeof(int64_t) * (Ec + 1), s);
+    grid.reset(sizeof(GridDesc) * Ec, s);
+    cell_off.reset(sizeof(int64_t) * (Ec + 1), s);
+    ext.reset(sizeof(uint32_t) * 2 * Ec * D, s);
+    xs.reset(sizeof(float) * sh.pts_cap * Dp_, s);
+    perm.reset(sizeof(int32_t) * sh.pts_cap, s);
+    key.reset(sizeof(uint32_t) * sh.pts_cap, s);
+    rank.reset(sizeof(uint32_t) * sh.pts_cap, s);
+    skey.reset(sizeof(uint32_t) * sh.pts_cap, s);
+    cells.reset(sizeof(uint32_t) * (sh.cells_cap + 1), s);
+    if (!selfq) {
+        qs.reset(sizeof(float) * sh.q_cap * Dp_, s);
+        qperm.reset(sizeof(int32_t) * sh.q_cap, s);
+        qkey.reset(sizeof(uint32_t) * sh.q_cap, s);
+        qrank.reset(sizeof(uint32_t) * sh.q_cap, s);
+        sqkey.reset(sizeof(uint32_t) * sh.q_cap, s);
+        qcells.reset(sizeof(uint32_t) * (sh.cells_cap + 1), s);
+    }
+    items.reset(sizeof(Item) * sh.q_cap, s);
+    deg.reset(sizeof(uint32_t) * sh.q_cap, s);
+    offs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
+    lofs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
+    lrows.reset(sizeof(uint32_t) * sh.q_cap, s);
+    part.reset(sizeof(uint64_t) * 2 * kScanBlocks, s);
+    outd.reset(sizeof(OutDesc), s);
+
+    Bufs b{};
+    b.bd = bd_b.as<BatchDesc>();
+    b.ev = ev_b.as<EventDev>();
+    b.pchunks = pch.as<Chunk>();
+    b.qchunks = qch.as<Chunk>();
+    b.grid = grid.as<GridDesc>();
+    b.cell_off = cell_off.as<int64_t>();
+    b.ext = ext.as<uint32_t>();
+    b.xs = xs.as<float>();
+    b.perm = perm.as<int32_t>();
+    b.key = key.as<uint32_t>();
+    b.rank = rank.as<uint32_t>();
+    b.skey = skey.as<uint32_t>();
+    b.cells = cells.as<uint32_t>();
+    b.qs = selfq ? xs.as<float>() : qs.as<float>();
+    b.qperm = selfq ? perm.as<int32_t>() : qperm.as<int32_t>();
+    b.qkey = qkey.as<uint32_t>();
+    b.qrank = qrank.as<uint32_t>();
+    b.sqkey = selfq ? skey.as<uint32_t>() : sqkey.as<uint32_t>();
+    b.qcells = selfq ? cells.as<uint32_t>() : qcells.as<uint32_t>();
+    b.items = items.as<Item>();
+    b.deg = deg.as<uint32_t>();
+    b.offs = offs.as<int64_t>();
+    b.lofs = lofs.as<int64_t>();
+    b.long_rows = lrows.as<uint32_t>();
+    b.scan_part = part.as<uint64_t>();
+    b.out = outd.as<OutDesc>();
+    b.bases = reinterpret_cast<int64_t *>(hv.as<char>() + sizeof(Counters));
+    bb_ = b;
+    bb_.ctr = ctr_b.as<Counters>();
+    bq_ = b;
+    bq_.ctr = hv.as<Counters>();
+
+    kn_.r2 = r2_of(sh.r);
+    kn_.K = sh.K;
+    kn_.self_query = selfq;
+    kn_.exclude_self = selfq && (sh.flags & FRNN_EXCLUDE_SELF);
+    kn_.queries_per_item = sh.o.queries_per_item;
+    kn_.cells_per_item = sh.o.cells_per_item;
+    kn_.long_cap = sh.o.row_cap_lds;
+    kn_.persistent = sh.o.persistent;
+}
+
+BatchContext::~BatchContext() {
+    if (ga_) (void)hipGraphExecDestroy(ga_);
+    if (gb_) (void)hipGraphExecDestroy(gb_);
+    if (gra_) (void)hipGraphDestroy(gra_);
+    if (grb_) (void)hipGraphDestroy(grb_);
+}
+
+void BatchContext::set_inputs(const frnn_event *ev, int E, hipStream_t s) {
+    const bool selfq = sh_.flags & FRNN_SELF_QUERY;
+    E_ = E;
+    std::vector<int64_t> np(E), poff(E);
+    nq_.assign(E, 0);
+    qoff_.assign(E, 0);
+    int64_t tp = 0, tq = 0;
+    std::vector<EventDev> evh(E);
+    for (int e = 0; e < E; ++e) {
+        np[e] = ev[e].N;
+        poff[e] = tp;
+        nq_[e] = selfq ? ev[e].N : ev[e].M;
+        qoff_[e] = tq;
+        double c = std::floor((double)sh_.o.cells_per_point * (double)std::max<int64_t>(np[e], 1));
+        c = std::max(1.0, std::min(c, (double)(1 << 30)));
+        evh[e] = EventDev{ev[e].points, selfq ? nullptr : ev[e].queries, np[e], tp, nq_[e], tq, (int64_t)c};
+        tp += np[e];
+        tq += nq_[e];
+    }
+    totq_ = tq;
+    std::vector<Chunk> pc, qc;
+    for (int e = 0; e < E; ++e) {
+        for (int64_t r = 0; r < np[e]; r += kChunkRows)
+            pc.push_back(Chunk{e, 0, poff[e] + r, poff[e] + std::min<int64_t>(np[e], r + kChunkRows)});
+        for (int64_t r = 0; r < nq_[e]; r += kChunkRows)
+            qc.push_back(Chunk{e, 0, qoff_[e] + r, qoff_[e] + std::min<int64_t>(nq_[e], r + kChunkRows)});
+    }
+    if ((int64_t)pc.size() > sh_.pch_cap || (int64_t)qc.size() > sh_.qch_cap || tp > sh_.pts_cap ||
+        tq > sh_.q_cap || E > sh_.E_cap)
+        throw Fail{FRNN_ERR_INTERNAL, "batch does not fit its context"};
+    BatchDesc bd{};
+    bd.E = E;
+    bd.D = sh_.D;
+    bd.Dp = Dp_;
+    bd.n_pchunks = (int)pc.size();
+    bd.n_qchunks = (int)qc.size();
+    bd.grid_axes_max = sh_.o.grid_axes_max;
+    bd.cell_multiple = sh_.o.cell_multiple;
+    bd.cells_per_point = sh_.o.cells_per_point;
+    bd.r_build = sh_.r;
+    bd.total_pts = tp;
+    bd.total_q = tq;
+    const size_t o_ev = 256, o_pc = o_ev + sizeof(EventDev) * E;
+    const size_t o_qc = o_pc + sizeof(Chunk) * pc.size();
+    char *h = (char *)stage_.ensure(o_qc + sizeof(Chunk) * qc.size() + 16);
+    std::memcpy(h, &bd, sizeof(bd));
+    std::memcpy(h + o_ev, evh.data(), sizeof(EventDev) * E);
+    if (!pc.empty()) std::memcpy(h + o_pc, pc.data(), sizeof(Chunk) * pc.size());
+    if (!qc.empty()) std::memcpy(h + o_qc, qc.data(), sizeof(Chunk) * qc.size());
+    FRNN_HIP(hipMemcpyAsync(bd_b.get(), h, sizeof(bd), hipMemcpyHostToDevice, s));
+    FRNN_HIP(hipMemcpyAsync(ev_b.get(), h + o_ev, sizeof(EventDev) * E, hipMemcpyHostToDevice, s));
+    if (!pc.empty())
+        FRNN_HIP(hipMemcpyAsync(pch.get(), h + o_pc, sizeof(Chunk) * pc.size(), hipMemcpyHostToDevice, s));
+    if (!qc.empty())
+        FRNN_HIP(hipMemcpyAsync(qch.get(), h + o_qc, sizeof(Chunk) * qc.size(), hipMemcpyHostToDevice, s));
+}
+
+static int qblocks_for(const frnn_opts &o, int64_t q_cap) {
+    int64_t cap = (int64_t)256 * o.blocks_per_cu;
+    int64_t need = (q_cap + kWavesPerBlock - 1) / kWavesPerBlock;
+    return (int)std::max<int64_t>(1, std::min(cap, need));
+}
+
+void BatchContext::launch_a(hipStream_t s) {
+    const bool selfq = sh_.flags & FRNN_SELF_QUERY;
+    const int D = sh_.D;
+    LAUNCH("init", s, launch_init(bb_, sh_.E_cap, D, true, s));
+    LAUNCH("extent", s, launch_extent(bb_, sh_.pch_cap, false, s));
+    LAUNCH("plan", s, launch_plan(bb_, s));
+    LAUNCH("zero_cells", s, launch_zero_cells(bb_, sh_.cells_cap, false, s));
+    LAUNCH("keys", s, launch_keys(bb_, sh_.pch_cap, false, s));
+    LAUNCH("scan_cells", s, launch_scan_cells(bb_, sh_.cells_cap, false, s));
+    LAUNCH("scatter", s, launch_scatter(bb_, sh_.pch_cap, false, s));
+    LAUNCH("init", s, launch_init(bq_, sh_.E_cap, D, false, s));
+    if (!selfq) {
+        LAUNCH("extent_q", s, launch_extent(bq_, sh_.qch_cap, true, s));
+        LAUNCH("zero_cells_q", s, launch_zero_cells(bq_, sh_.cells_cap, true, s));
+        LAUNCH("keys_q", s, launch_keys(bq_, sh_.qch_cap, true, s));
+        LAUNCH("scan_cells_q", s, launch_scan_cells(bq_, sh_.cells_cap, true, s));
+        LAUNCH("scatter_q", s, launch_scatter(bq_, sh_.qch_cap, true, s));
+    }
+    LAUNCH("items", s, launch_items(bq_, kn_, sh_.qch_cap, s));
+    LAUNCH("count", s, launch_count(bq_, kn_, D, qblocks_for(sh_.o, sh_.q_cap), s));
+    LAUNCH("scan_rows", s, launch_scan_rows(bq_, kn_, sh_.q_cap, s));
+    LAUNCH("bases", s, launch_bases(bq_, sh_.E_cap, s));
+}
+
+void BatchContext::launch_b(hipStream_t s) {
+    LAUNCH("fill", s, launch_fill(bq_, kn_, sh_.D, qblocks_for(sh_.o, sh_.q_cap), s));
+    LAUNCH("long_sort", s, launch_long_sort(bq_, kn_, 256, s));
+    LAUNCH("finalize", s, launch_finalize(bq_, sh_.qch_cap, s));
+}
+
+static bool capture(hipStream_t s, hipGraph_t *g, hipGraphExec_t *ge, void (*fn)(void *, hipStream_t),
+                    void *arg) {
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    set_capturing(true);
+    bool ok = true;
+    try {
+        fn(arg, s);
+    } catch (...) {
+        ok = false;
+    }
+    set_capturing(false);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (!ok || e != hipSuccess || !graph) {
+        (void)hipGetLastError();
+        if (graph) (void)hipGraphDestroy(graph);
+        return false;
+    }
+    if (hipGraphInstantiate(ge, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(graph);
+        *ge = nullptr;
+        return false;
+    }
+    *g = graph;
+    return true;
+}
+
+void BatchContext::phase_a(hipStream_t s) {
+    if (graphs_enabled && !prof_enabled()) {
+        if (!ga_ &&
+            !capture(s, &gra_, &ga_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_a(st); }, this))
+            graphs_enabled = false;
+        if (ga_) {
+            FRNN_HIP(hipGraphLaunch(ga_, s));
+            ++replays;
+            return;
+        }
+    }
+    launch_a(s);
+}
+
+BatchCounts BatchContext::read_counts(hipStream_t s) {
+    const size_t hvb = sizeof(Counters) + sizeof(int64_t) * (E_ + 1);
+    char *p = (char *)back_.ensure(hvb + sizeof(Counters));
+    FRNN_HIP(hipMemcpyAsync(p, hv.get(), hvb, hipMemcpyDeviceToHost, s));
+    FRNN_HIP(hipMemcpyAsync(p + hvb, ctr_b.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
+    FRNN_HIP(hipStreamSynchronize(s));
+    BatchCounts c;
+    std::memcpy(&c.ctr, p, sizeof(Counters));
+    Counters cb;
+    std::memcpy(&cb, p + hvb, sizeof(Counters));
+    c.build_status = cb.status;
+    c.bases.resize(E_ + 1);
+    std::memcpy(c.bases.data(), p + sizeof(Counters), sizeof(int64_t) * (E_ + 1));
+    return c;
+}
+
+void BatchContext::phase_b(const OutDesc &od, hipStream_t s) {
+    LAUNCH("set_out", s, launch_set_out(bq_.out, od, s));
+    if (graphs_enabled && !prof_enabled()) {
+        if (!gb_ &&
+            !capture(s, &grb_, &gb_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_b(st); }, this)) {
+            launch_b(s);
+            return;
+        }
+        if (gb_) {
+            FRNN_HIP(hipGraphLaunch(gb_, s));
+            return;
+        }
+    }
+    launch_b(s);
+}
+
+// ---------------------------------------------------------------- cache
+namespace {
+struct Cached {
+    std::unique_ptr<BatchContext> ctx;
+    hipEvent_t done;
+};
+std::mutex g_cache_mu;
+std::vector<Cached> g_cache;
+constexpr size_t kCacheMax = 8;
+}  // namespace
+
+std::unique_ptr<BatchContext> acquire_context(const BatchContext::Shape &need, hipStream_t s) {
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        int best = -1;
+        for (size_t i = 0; i < g_cache.size(); ++i) {
+            if (!g_cache[i].ctx->fits(need)) continue;
+            if (best < 0 || g_cache[i].ctx->shape().pts_cap < g_cache[best].ctx->shape().pts_cap) best = (int)i;
+        }
+        if (best >= 0) {
+            Cached c = std::move(g_cache[best]);
+            g_cache.erase(g_cache.begin() + best);
+            // the previous run of this context may still be on another stream
+            FRNN_HIP(hipStreamWaitEvent(s, c.done, 0));
+            (void)hipEventDestroy(c.done);
+            return std::move(c.ctx);
+        }
+    }
+    return std::unique_ptr<BatchContext>(new BatchContext(need, s));
+}
+
+void return_context(std::unique_ptr<BatchContext> ctx, hipStream_t s) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        if (ev) (void)hipEventDestroy(ev);
+        return;  // drop the context
+    }
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    g_cache.push_back(Cached{std::move(ctx), ev});
+    if (g_cache.size() > kCacheMax) {
+        Cached old = std::move(g_cache.front());
+        g_cache.erase(g_cache.begin());
+        (void)hipEventSynchronize(old.done);
+        (void)hipEventDestroy(old.done);
+    }
+}
+
+BatchOutput alloc_output(const BatchContext &ctx, const BatchCounts &c, bool want_d2, hipStream_t s) {
+    BatchOutput bo;
+    const int E = ctx.E();
+    const int64_t nnz = (int64_t)c.ctr.nnz;
+    const size_t b_off = sizeof(int64_t) * (ctx.total_q() + E);
+    const size_t b_idx = (sizeof(int32_t) * nnz + 255) / 256 * 256;
+    const size_t b_d2 = want_d2 ? sizeof(float) * nnz : 0;
+    std::unique_ptr<OutputOwner> own(new OutputOwner());
+    own->buf.reset(b_off + b_idx + b_d2, s);
+    bo.long_keys.reset(sizeof(uint64_t) * std::max<uint64_t>(1, c.ctr.long_total), s);
+    char *ob = own->buf.as<char>();
+    bo.od = OutDesc{reinterpret_cast<int64_t *>(ob), reinterpret_cast<int32_t *>(ob + b_off),
+                    want_d2 ? reinterpret_cast<float *>(ob + b_off + b_idx) : nullptr,
+                    bo.long_keys.as<uint64_t>()};
+    bo.own = own.release();
+    return bo;
+}
+
+void hand_out(const BatchContext &ctx, const BatchCounts &c, BatchOutput &bo, frnn_csr *outs) {
+    const int E = ctx.E();
+    bo.own->refs = E;
+    for (int e = 0; e < E; ++e) {
+        frnn_csr &o = outs[e];
+        o.M = ctx.n_q()[e];
+        o.nnz = c.bases[e + 1] - c.bases[e];
+        o.offsets = bo.od.offsets + ctx.q_off()[e] + e;
+        o.indices = bo.od.indices + c.bases[e];
+        o.dist2 = bo.od.dist2 ? bo.od.dist2 + c.bases[e] : nullptr;
+        o.owner_ = bo.own;
+    }
+    bo.own = nullptr;
+}
+
+frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32_t flags,
+                      const Opts &o, hipStream_t s, frnn_csr *outs) {
+    BatchContext::Shape need = BatchContext::shape_for(ev, E, D, r, K, flags, o);
+    std::unique_ptr<BatchContext> ctx = acquire_context(need, s);
+    frnn_status st = FRNN_OK;
+    try {
+        ctx->set_inputs(ev, E, s);
+        ctx->phase_a(s);
+        BatchCounts c = ctx->read_counts(s);
+        if (c.build_status & kStatusNonfinitePts) {
+            st = fail(FRNN_ERR_NONFINITE, "non-finite coordinate in the points");
+        } else if (c.ctr.status & kStatusNonfiniteQry) {
+            st = fail(FRNN_ERR_NONFINITE, "non-finite coordinate in the queries");
+        } else if (c.bases[E] != (int64_t)c.ctr.nnz) {
+            st = fail(FRNN_ERR_INTERNAL, "pair count mismatch");
+        } else {
+            BatchOutput bo = alloc_output(*ctx, c, flags & FRNN_WANT_DIST2, s);
+            try {
+                ctx->phase_b(bo.od, s);
+            } catch (...) {
+                delete bo.own;
+                throw;
+            }
+            hand_out(*ctx, c, bo, outs);
+            frnn_stats stt{};
+            stt.candidates = (int64_t)c.ctr.candidates;
+            stt.work_items = c.ctr.n_items;
+            stt.pairs = (int64_t)c.ctr.nnz;
+            stt.long_row_keys = (int64_t)c.ctr.long_total;
+            record_stats(stt);
+        }
+    } catch (...) {
+        return_context(std::move(ctx), s);
+        throw;
+    }
+    return_context(std::move(ctx), s);
+    return st;
+}
+
+}  // namespace frnn

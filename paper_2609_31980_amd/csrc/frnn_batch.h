@@ -1,0 +1,103 @@
+// Batched pipeline: many events through one launch sequence.
+//
+// A BatchContext owns device buffers sized for a capacity class (events,
+// points, queries, cells, chunks; rounded up so that similar batches share a
+// class).  Its launch sequence has fixed grid sizes and reads every actual
+// size from device memory, so it is captured once as two HIP graphs and
+// replayed for any batch of its class:
+//   graph A: bin the points of every event, count every query's neighbours,
+//            scan the capped counts        (then one 8-byte-per-event read-back)
+//   graph B: fill, sort long rows, per-event offsets
+// The count and fill kernels are persistent: a grid of resident workgroups
+// drains one device work queue of (event, cell block) items.
+#pragma once
+
+#include <condition_variable>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "frnn_runtime.h"
+
+namespace frnn {
+
+struct BatchCounts {
+    Counters ctr;
+    uint32_t build_status;
+    std::vector<int64_t> bases;  // [E+1]
+};
+
+class BatchContext {
+public:
+    struct Shape {
+        int D;
+        uint32_t flags;
+        int K;
+        float r;
+        int E_cap;
+        int64_t pts_cap, q_cap, cells_cap;
+        int pch_cap, qch_cap;
+        frnn_opts o;
+        bool operator==(const Shape &x) const;
+    };
+
+    BatchContext(const Shape &sh, hipStream_t s);
+    ~BatchContext();
+    const Shape &shape() const { return sh_; }
+    static Shape shape_for(const frnn_event *ev, int E, int D, float r, int K, uint32_t flags,
+                           const Opts &o);
+    bool fits(const Shape &need) const;
+
+    // 1. descriptors of this batch (host -> device, on stream s)
+    void set_inputs(const frnn_event *ev, int E, hipStream_t s);
+    // 2. bin + count + scan (graph A)
+    void phase_a(hipStream_t s);
+    // 3. wait for phase A and read the counters
+    BatchCounts read_counts(hipStream_t s);
+    // 4. fill into the given output (graph B)
+    void phase_b(const OutDesc &od, hipStream_t s);
+
+    int E() const { return E_; }
+    const std::vector<int64_t> &q_off() const { return qoff_; }
+    const std::vector<int64_t> &n_q() const { return nq_; }
+    int64_t total_q() const { return totq_; }
+    bool graphs_enabled = true;
+    int replays = 0;
+
+private:
+    void launch_a(hipStream_t s);
+    void launch_b(hipStream_t s);
+    Shape sh_;
+    int Dp_ = 0;
+    int E_ = 0;
+    int64_t totq_ = 0;
+    std::vector<int64_t> qoff_, nq_;
+    Knobs kn_{};
+    Bufs bb_{}, bq_{};  // build run and query run
+    DevBuf bd_b, bd_q, ev_b, ev_q, pch, qch, ctr_b, hv, grid, cell_off, ext, xs, perm, key, rank,
+        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, items, deg, offs, lofs, lrows, part, outd;
+    Pinned stage_, back_;
+    hipGraphExec_t ga_ = nullptr, gb_ = nullptr;
+    hipGraph_t gra_ = nullptr, grb_ = nullptr;
+};
+
+// Check a context of a fitting class out of the shared cache (or make one);
+// give it back when done.  Contexts are never used by two runs at once.
+std::unique_ptr<BatchContext> acquire_context(const BatchContext::Shape &need, hipStream_t s);
+void return_context(std::unique_ptr<BatchContext> ctx, hipStream_t s);
+
+// One batch end to end: acquire, run, hand out per-event CSRs.
+frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32_t flags,
+                      const Opts &o, hipStream_t s, frnn_csr *outs);
+
+// Output allocation of a batch (offsets | indices | dist2 | long scratch).
+struct BatchOutput {
+    OutputOwner *own = nullptr;
+    OutDesc od{};
+    DevBuf long_keys;
+};
+BatchOutput alloc_output(const BatchContext &ctx, const BatchCounts &c, bool want_d2, hipStream_t s);
+void hand_out(const BatchContext &ctx, const BatchCounts &c, BatchOutput &bo, frnn_csr *outs);
+
+}  // namespace frnn

@@ -1,0 +1,149 @@
+// Shared layout of the device-resident descriptors of one pipeline run.
+//
+// A run processes E independent events.  Every size a kernel needs is read
+// from device memory (the batch descriptor, the chunk tables and the
+// counters), never baked into a launch, so one launch sequence serves any
+// batch that fits the buffers and can be replayed as a HIP graph.
+#pragma once
+
+#include <stdint.h>
+
+namespace frnn {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kGMax = 6;         // most grid axes
+constexpr int kDMax = 32;        // most coordinates per point
+constexpr int kRunsMax = 256;    // neighbour runs per work item (LDS table size)
+constexpr int kCandLds = 512;    // candidate positions listed in LDS per work item
+constexpr int kRowLds = 512;     // longest row collected and sorted on chip
+constexpr int kChunkRows = 1024; // rows per chunk of the per-point kernels
+constexpr int kWavesPerBlock = 4;
+
+// Cell grid of one event, chosen on the device from the event's extent.
+// A point x has grid coordinates c_a = clamp(floor((x[axis[a]] - lo[a]) *
+// inv_h), 0, n[a]-1) and cell key sum_a c_a * stride[a] (stride[0] = 1, so
+// cells adjacent along grid axis 0 have adjacent keys).
+struct GridDesc {
+    int32_t G;             // grid axes in use (0 = one cell)
+    int32_t m;             // reach in cells: neighbours lie within +-m cells
+    int32_t runs;          // (2m+1)^(G-1): key runs scanned per work item
+    uint32_t C;            // cells
+    int32_t axis[kGMax];
+    int32_t n[kGMax];
+    uint32_t stride[kGMax];
+    double lo[kGMax];
+    double inv_h;
+    double h;
+};
+
+// Host-written description of one event.
+struct EventDev {
+    const float *pts;      // caller's [n_pts][D]
+    const float *qry;      // caller's [n_q][D] (unused for self-queries)
+    int64_t n_pts, pt_off; // rows, offset in the concatenated point arrays
+    int64_t n_q, q_off;    // queries, offset in the concatenated query arrays
+    int64_t cell_cap;      // most cells the plan may give this event
+};
+
+// Rows [r0, r1) of the concatenated point (or query) arrays, all in event ev.
+struct Chunk {
+    int32_t ev;
+    int32_t pad;
+    int64_t r0, r1;
+};
+
+// Host-written scalars of a run.
+struct BatchDesc {
+    int32_t E;
+    int32_t D, Dp;         // dimension and padded row length (multiple of 4)
+    int32_t n_pchunks, n_qchunks;
+    int32_t grid_axes_max, cell_multiple;
+    float cells_per_point;
+    float r_build;
+    int32_t pad0;
+    int64_t total_pts, total_q;
+};
+
+// Device-written counters, copied to the host once per run.
+struct Counters {
+    uint64_t total_cells;  // sum of the events' cell counts
+    uint64_t nnz;          // output pairs (after the cap)
+    uint64_t long_total;   // keys of rows sorted in global memory
+    uint64_t candidates;   // distance evaluations of the count pass
+    uint32_t n_items;      // work items
+    uint32_t head_count;   // work-queue heads
+    uint32_t head_fill;
+    uint32_t n_long;       // rows sorted in global memory
+    uint32_t status;       // kStatus* bits
+    uint32_t pad[7];
+};
+
+constexpr uint32_t kStatusNonfinitePts = 1u;
+constexpr uint32_t kStatusNonfiniteQry = 2u;
+constexpr uint32_t kStatusInternal = 4u;
+
+// Where the fill pass writes (device-resident so graphs need not change).
+struct OutDesc {
+    int64_t *offsets;      // per-event offsets, event e at q_off + e
+    int32_t *indices;
+    float *dist2;          // may be null
+    uint64_t *long_keys;   // scratch of the rows sorted in global memory
+};
+
+// Per-run scalars passed by value.
+struct Knobs {
+    float r2;              // fl32(r*r), computed on the host
+    int32_t K;             // <= 0: no cap
+    int32_t self_query;    // queries are the sorted points
+    int32_t exclude_self;
+    int32_t queries_per_item;
+    int32_t cells_per_item;
+    int32_t long_cap;      // rows longer than this sort in global memory
+    int32_t persistent;
+};
+
+// A work item: queries sorted slots [qpos, qpos + nq) of event ev, all in
+// the block of cells that starts with cell key `key`'s block.
+struct alignas(16) Item {
+    int32_t qpos;
+    int32_t nq;
+    int32_t ev;
+    uint32_t key;
+};
+
+// Device buffers of a run.
+struct Bufs {
+    const BatchDesc *bd;
+    const EventDev *ev;
+    const Chunk *pchunks;
+    const Chunk *qchunks;
+    Counters *ctr;
+    int64_t *bases;        // [E+1] first output pair of each event
+    GridDesc *grid;        // [E]
+    int64_t *cell_off;     // [E+1]
+    uint32_t *ext;         // [E][2][D] order-preserving min / max bits
+    // points, concatenated over events
+    float *xs;             // [total_pts][Dp] sorted by cell
+    int32_t *perm;         // sorted slot -> local original index
+    uint32_t *key, *rank;  // per original point
+    uint32_t *skey;        // per sorted slot
+    uint32_t *cells;       // [total_cells+1] counts, then exclusive scan
+    // queries (for self-queries these alias the point arrays)
+    float *qs;
+    int32_t *qperm;
+    uint32_t *qkey, *qrank, *sqkey, *qcells;
+    // work and rows
+    Item *items;
+    uint32_t *deg;         // in-radius count per query (global row)
+    int64_t *offs;         // [total_q+1] exclusive scan of capped counts
+    int64_t *lofs;         // [total_q+1] exclusive scan of long-row lengths
+    uint32_t *long_rows;
+    uint64_t *scan_part;   // scan block partials (2 x kScanBlocks)
+    OutDesc *out;
+};
+
+constexpr int kScanBlocks = 1024;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+
+}  // namespace frnn

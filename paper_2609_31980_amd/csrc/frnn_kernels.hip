@@ -1,0 +1,1094 @@
+// HIP kernels of the exact fixed-radius neighbour pipeline, written for
+// gfx950 (CDNA4, 64-lane wavefronts).
+//
+// Pipeline (every size is read from device memory, see frnn_device.h):
+//   binning    k_init, k_extent, k_plan, k_zero_cells, k_keys, scan, k_scatter
+//   work items k_items                       one item = queries of a cell block
+//   counting   k_query<count>, scan of the capped counts, k_bases
+//   filling    k_query<fill>, k_long_sort, k_finalize
+//
+// Exactness: the squared distance is computed in float32 as
+//   s = +0; for d in 0..D-1: t = q_d - x_d; u = t*t; s = s + u
+// with every operation rounded on its own.  The file is compiled with
+// -ffp-contract=off and the pragma below, so no fused multiply-add can
+// replace t*t followed by s+u (a reassociated or fused sum changes float32
+// membership near the radius, Sec. 4.2).  Subnormals are not flushed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "frnn_device.h"
+#include "frnn_launch.h"
+
+#pragma clang fp contract(off)
+
+namespace frnn {
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Orders LDS writes of a wave before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t t = (uint32_t)__shfl_up((int)v, o);
+        if (l >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int mask) {
+    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask);
+    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
+
+// Float bits mapped so that unsigned order is float order (for atomics).
+__device__ __forceinline__ uint32_t f2ord(float f) {
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t o) {
+    uint32_t b = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    return __uint_as_float(b);
+}
+
+__device__ __forceinline__ bool finite32(float f) {
+    return (__float_as_uint(f) & 0x7f800000u) != 0x7f800000u;
+}
+
+// Sorts 64*KS keys held as v[s] at element s*64 + lane, ascending, with the
+// bitonic network in its all-ascending form (merge step: compare element i
+// with its mirror i ^ (k-1), then half-cleaners i ^ j).  Partners within a
+// slot are other lanes (cross-lane shuffles); partners across slots are the
+// same lane (register compare-exchange).
+template <int KS>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&v)[KS], int lane) {
+    constexpr int N = 64 * KS;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+        if (k <= 64) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                uint64_t o = shfl_xor64(v[s], k - 1);
+                bool lower = (lane & (k >> 1)) == 0;
+                v[s] = lower ? umin64(v[s], o) : umax64(v[s], o);
+            }
+        } else {
+            const int sm = k / 64 - 1;
+            uint64_t o[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) o[s] = shfl_xor64(v[s ^ sm], 63);
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                bool lower = (s & (k / 128)) == 0;
+                v[s] = lower ? umin64(v[s], o[s]) : umax64(v[s], o[s]);
+            }
+        }
+#pragma unroll
+        for (int j = k >> 2; j >= 1; j >>= 1) {
+            if (j >= 64) {
+                const int sj = j / 64;
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    if ((s & sj) == 0) {
+                        uint64_t a = v[s], c = v[s | sj];
+                        v[s] = umin64(a, c);
+                        v[s | sj] = umax64(a, c);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    uint64_t o = shfl_xor64(v[s], j);
+                    bool lower = (lane & j) == 0;
+                    v[s] = lower ? umin64(v[s], o) : umax64(v[s], o);
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ init
+__global__ void k_init(Bufs b, int32_t init_ext) {
+    const BatchDesc bd = *b.bd;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    if (tid < (int64_t)(sizeof(Counters) / 4)) reinterpret_cast<uint32_t *>(b.ctr)[tid] = 0u;
+    if (init_ext) {
+        const int64_t ne = (int64_t)bd.E * 2 * bd.D;
+        for (int64_t i = tid; i < ne; i += nthr) {
+            int64_t w = (i / bd.D) % 2;  // 0: min, 1: max
+            b.ext[i] = w == 0 ? 0xffffffffu : 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- extent
+// Per-event per-axis min / max of the points and a finiteness check
+// (queries: finiteness only).  Thread t of a block always reads axis t % D.
+__global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries) {
+    __shared__ uint32_t smin[kDMax], smax[kDMax];
+    __shared__ int sbad;
+    const BatchDesc bd = *b.bd;
+    const int D = bd.D;
+    const int nch = queries ? bd.n_qchunks : bd.n_pchunks;
+    const Chunk *chunks = queries ? b.qchunks : b.pchunks;
+    const int stride = (256 / D) * D;
+    const int t = threadIdx.x;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = chunks[c];
+        const EventDev ev = b.ev[ch.ev];
+        const float *src = queries ? ev.qry : ev.pts;
+        const int64_t off = queries ? ev.q_off : ev.pt_off;
+        if (t < kDMax) {
+            smin[t] = 0xffffffffu;
+            smax[t] = 0u;
+        }
+        if (t == 0) sbad = 0;
+        __syncthreads();
+        uint32_t mn = 0xffffffffu, mx = 0u;
+        bool bad = false;
+        if (t < stride) {
+            const int64_t f0 = (ch.r0 - off) * D, f1 = (ch.r1 - off) * D;
+            for (int64_t f = f0 + t; f < f1; f += stride) {
+                float x = src[f];
+                bad |= !finite32(x);
+                uint32_t o = f2ord(x);
+                mn = o < mn ? o : mn;
+                mx = o > mx ? o : mx;
+            }
+            if (!queries) {
+                atomicMin(&smin[t % D], mn);
+                atomicMax(&smax[t % D], mx);
+            }
+        }
+        if (bad) sbad = 1;
+        __syncthreads();
+        if (!queries && t < D) {
+            atomicMin(&b.ext[((int64_t)ch.ev * 2 + 0) * D + t], smin[t]);
+            atomicMax(&b.ext[((int64_t)ch.ev * 2 + 1) * D + t], smax[t]);
+        }
+        if (t == 0 && sbad)
+            atomicOr(&b.ctr->status, queries ? kStatusNonfiniteQry : kStatusNonfinitePts);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ plan
+// One block.  For every event: grid axes = the coordinates of largest
+// extent; cell width h = r_h / m with r_h = r (1 + 2^-16) + 2^-60 (float64);
+// the most axes (up to the limit) whose cell count stays within the cap.
+//
+// Why no neighbour is lost (the roundoff-safe grid): float32 rounding is
+// monotone and every u_d is >= 0, so s <= r2 implies fl32(t_a^2) <= r2 on
+// each axis a, hence |x_a - y_a| <= r (1 + 2^-21) + 2^-73 in real numbers.
+// Cell coordinates v = fl64(fl64(x - lo) * inv_h) carry a relative error
+// below 2^-51, far less than the 2^-16 margin in h, so |v(x) - v(y)| < m and
+// the floors differ by at most m; clamping to [0, n-1] cannot widen the gap.
+__global__ void __launch_bounds__(256) k_plan(Bufs b) {
+    __shared__ int64_t ssum[256];
+    const BatchDesc bd = *b.bd;
+    const int E = bd.E, D = bd.D;
+    const int per = (E + 255) / 256;
+    const int e0 = threadIdx.x * per;
+    const int e1 = min(E, e0 + per);
+    int64_t local = 0;
+    for (int e = e0; e < e1; ++e) {
+        const EventDev ev = b.ev[e];
+        GridDesc g;
+        for (int a = 0; a < kGMax; ++a) {
+            g.axis[a] = 0;
+            g.n[a] = 1;
+            g.stride[a] = 0;
+            g.lo[a] = 0.0;
+        }
+        const int m = bd.cell_multiple;
+        g.m = m;
+        const double rh = (double)bd.r_build * (1.0 + 0x1p-16) + 0x1p-60;
+        double inv_h = 1.0 / (rh / (double)m);
+        int64_t cap = (int64_t)((double)bd.cells_per_point * (double)(ev.n_pts > 0 ? ev.n_pts : 1));
+        if (cap < 1) cap = 1;
+        if (cap > ((int64_t)1 << 30)) cap = (int64_t)1 << 30;
+        if (cap > ev.cell_cap) cap = ev.cell_cap;
+        const int gmax = min(bd.grid_axes_max, min(D, kGMax));
+        // axes by decreasing extent (ties: lower coordinate first)
+        double cext[kGMax];
+        uint32_t used = 0;
+        for (int a = 0; a < gmax; ++a) {
+            int best = -1;
+            double bext = -1.0;
+            for (int d = 0; d < D; ++d) {
+                if (used & (1u << d)) continue;
+                float lo = ord2f(b.ext[((int64_t)e * 2 + 0) * D + d]);
+                float hi = ord2f(b.ext[((int64_t)e * 2 + 1) * D + d]);
+                double x = ev.n_pts > 0 ? (double)hi - (double)lo : 0.0;
+                // non-finite input (reported to the host as an error) must
+                // still give an in-bounds grid: treat its extent as empty
+                if (!(x >= 0.0 && x <= 1.0e39)) x = 0.0;
+                if (x > bext) {
+                    bext = x;
+                    best = d;
+                }
+            }
+            used |= 1u << best;
+            g.axis[a] = best;
+            cext[a] = bext;
+            double lo = ev.n_pts > 0 ? (double)ord2f(b.ext[((int64_t)e * 2 + 0) * D + best]) : 0.0;
+            g.lo[a] = (lo >= -3.5e38 && lo <= 3.5e38) ? lo : 0.0;
+        }
+        int G = 0;
+        const int W = 2 * m + 1;
+        for (int gg = gmax; gg >= 1; --gg) {
+            int64_t runs = 1;
+            for (int a = 1; a < gg; ++a) runs *= W;
+            if (runs > kRunsMax) continue;
+            double C = 1.0;
+            for (int a = 0; a < gg; ++a) C *= floor(cext[a] * inv_h) + 1.0;
+            if (C <= (double)cap) {
+                G = gg;
+                break;
+            }
+        }
+        if (G == 0 && gmax >= 1) {
+            // even one axis at width r_h/m has too many cells: widen the
+            // cells (wider cells never lose a neighbour)
+            G = 1;
+            if (cext[0] > 0.0) {
+                double w = (double)(cap - 1) / cext[0];
+                inv_h = w < inv_h ? w : inv_h;
+            }
+        }
+        g.G = G;
+        g.inv_h = inv_h;
+        g.h = inv_h > 0.0 ? 1.0 / inv_h : 0.0;
+        uint32_t C = 1;
+        int runs = 1;
+        for (int a = 0; a < G; ++a) {
+            double na = floor(cext[a] * inv_h) + 1.0;
+            if (na > (double)cap) na = (double)cap;
+            g.n[a] = (int32_t)na;
+            g.stride[a] = C;
+            C *= (uint32_t)g.n[a];
+            if (a >= 1) runs *= W;
+        }
+        g.C = C;
+        g.runs = runs;
+        b.grid[e] = g;
+        local += C;
+    }
+    // exclusive scan of the cell counts over events -> cell offsets
+    ssum[threadIdx.x] = local;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        int64_t v = threadIdx.x >= (unsigned)o ? ssum[threadIdx.x - o] : 0;
+        __syncthreads();
+        ssum[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = ssum[threadIdx.x] - local;
+    for (int e = e0; e < e1; ++e) {
+        b.cell_off[e] = run;
+        run += b.grid[e].C;
+    }
+    if (threadIdx.x == 255) {
+        b.cell_off[E] = ssum[255];
+        b.ctr->total_cells = (uint64_t)ssum[255];
+    }
+}
+
+// Clears the cell histogram (cells 0..total, the last one is the sentinel
+// the exclusive scan turns into the total).
+__global__ void k_zero_cells(Bufs b, int32_t queries) {
+    const BatchDesc bd = *b.bd;
+    const int64_t n = b.cell_off[bd.E] + 1;
+    uint32_t *cells = queries ? b.qcells : b.cells;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        cells[i] = 0u;
+}
+
+// ------------------------------------------------------------------ keys
+__device__ __forceinline__ uint32_t cell_key(const GridDesc &g, const float *row) {
+    uint32_t key = 0;
+    for (int a = 0; a < g.G; ++a) {
+        double v = ((double)row[g.axis[a]] - g.lo[a]) * g.inv_h;
+        v = v > 0.0 ? v : 0.0;
+        double top = (double)(g.n[a] - 1);
+        v = v < top ? v : top;
+        key += (uint32_t)v * g.stride[a];
+    }
+    return key;
+}
+
+__global__ void __launch_bounds__(256) k_keys(Bufs b, int32_t queries) {
+    __shared__ GridDesc sg;
+    const BatchDesc bd = *b.bd;
+    const int D = bd.D;
+    const int nch = queries ? bd.n_qchunks : bd.n_pchunks;
+    const Chunk *chunks = queries ? b.qchunks : b.pchunks;
+    uint32_t *cells = queries ? b.qcells : b.cells;
+    uint32_t *keys = queries ? b.qkey : b.key;
+    uint32_t *ranks = queries ? b.qrank : b.rank;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = chunks[c];
+        __syncthreads();
+        if (threadIdx.x == 0) sg = b.grid[ch.ev];
+        __syncthreads();
+        const EventDev ev = b.ev[ch.ev];
+        const float *src = queries ? ev.qry : ev.pts;
+        const int64_t off = queries ? ev.q_off : ev.pt_off;
+        const int64_t coff = b.cell_off[ch.ev];
+        for (int64_t i = ch.r0 + threadIdx.x; i < ch.r1; i += blockDim.x) {
+            uint32_t k = cell_key(sg, src + (i - off) * D);
+            keys[i] = k;
+            ranks[i] = atomicAdd(&cells[coff + k], 1u);
+        }
+    }
+}
+
+// Sorted slot of every point: start of its cell plus its rank in the cell.
+// Rows are stored padded to Dp floats (zeros), 16-byte aligned.
+__global__ void __launch_bounds__(256) k_scatter(Bufs b, int32_t queries) {
+    const BatchDesc bd = *b.bd;
+    const int D = bd.D, Dp = bd.Dp;
+    const int nch = queries ? bd.n_qchunks : bd.n_pchunks;
+    const Chunk *chunks = queries ? b.qchunks : b.pchunks;
+    const uint32_t *cells = queries ? b.qcells : b.cells;
+    const uint32_t *keys = queries ? b.qkey : b.key;
+    const uint32_t *ranks = queries ? b.qrank : b.rank;
+    float *dst = queries ? b.qs : b.xs;
+    int32_t *perm = queries ? b.qperm : b.perm;
+    uint32_t *skey = queries ? b.sqkey : b.skey;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = chunks[c];
+        const EventDev ev = b.ev[ch.ev];
+        const float *src = queries ? ev.qry : ev.pts;
+        const int64_t off = queries ? ev.q_off : ev.pt_off;
+        const int64_t coff = b.cell_off[ch.ev];
+        for (int64_t i = ch.r0 + threadIdx.x; i < ch.r1; i += blockDim.x) {
+            const uint32_t k = keys[i];
+            const uint32_t p = cells[coff + k] + ranks[i];
+            const float *row = src + (i - off) * D;
+            float4 *out = reinterpret_cast<float4 *>(dst + (int64_t)p * Dp);
+            for (int d4 = 0; d4 < Dp; d4 += 4) {
+                float4 v;
+                v.x = d4 + 0 < D ? row[d4 + 0] : 0.0f;
+                v.y = d4 + 1 < D ? row[d4 + 1] : 0.0f;
+                v.z = d4 + 2 < D ? row[d4 + 2] : 0.0f;
+                v.w = d4 + 3 < D ? row[d4 + 3] : 0.0f;
+                out[d4 / 4] = v;
+            }
+            perm[p] = (int32_t)(i - off);
+            skey[p] = k;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive scan of pairs of 64-bit values in three launches with a fixed
+// grid (block partials, scan of the partials, apply).  Modes:
+//   0: point cells   (in place, 32-bit)
+//   1: query cells   (in place, 32-bit)
+//   2: row offsets   deg -> (min(deg, K), deg if the row is long else 0)
+enum { kScanCells = 0, kScanQCells = 1, kScanRows = 2 };
+
+template <int MODE>
+__device__ __forceinline__ uint64_t scan_n(const Bufs &b) {
+    if (MODE == kScanRows) return (uint64_t)b.bd->total_q + 1;
+    return (uint64_t)b.cell_off[b.bd->E] + 1;
+}
+
+template <int MODE>
+__device__ __forceinline__ ulonglong2 scan_load(const Bufs &b, const Knobs &kn, uint64_t i,
+                                                uint64_t n) {
+    ulonglong2 v;
+    v.x = 0;
+    v.y = 0;
+    if (i >= n) return v;
+    if (MODE == kScanCells) {
+        v.x = b.cells[i];
+    } else if (MODE == kScanQCells) {
+        v.x = b.qcells[i];
+    } else {
+        if (i + 1 < n) {
+            uint32_t d = b.deg[i];
+            v.x = (kn.K > 0 && d > (uint32_t)kn.K) ? (uint32_t)kn.K : d;
+            v.y = d > (uint32_t)kn.long_cap ? d : 0;
+        }
+    }
+    return v;
+}
+
+template <int MODE>
+__device__ __forceinline__ void scan_store(const Bufs &b, uint64_t i, ulonglong2 v) {
+    if (MODE == kScanCells) {
+        b.cells[i] = (uint32_t)v.x;
+    } else if (MODE == kScanQCells) {
+        b.qcells[i] = (uint32_t)v.x;
+    } else {
+        b.offs[i] = (int64_t)v.x;
+        b.lofs[i] = (int64_t)v.y;
+    }
+}
+
+__device__ __forceinline__ ulonglong2 add2(ulonglong2 a, ulonglong2 c) {
+    ulonglong2 r;
+    r.x = a.x + c.x;
+    r.y = a.y + c.y;
+    return r;
+}
+
+__device__ __forceinline__ ulonglong2 shfl_up2(ulonglong2 v, int o) {
+    ulonglong2 r;
+    r.x = (unsigned long long)__shfl_up((long long)v.x, o);
+    r.y = (unsigned long long)__shfl_up((long long)v.y, o);
+    return r;
+}
+
+// Block-wide exclusive scan over blockDim.x (<= 1024) threads; returns the
+// exclusive prefix and writes the block total.
+__device__ ulonglong2 block_excl_scan(ulonglong2 v, ulonglong2 *total) {
+    __shared__ ulonglong2 swave[17];  // 16 wave prefixes + the total
+    const int l = lane_id(), w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    ulonglong2 inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        ulonglong2 t = shfl_up2(inc, o);
+        if (l >= o) inc = add2(inc, t);
+    }
+    if (l == 63) swave[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ulonglong2 run;
+        run.x = 0;
+        run.y = 0;
+        for (int i = 0; i < nw; ++i) {
+            ulonglong2 t = swave[i];
+            swave[i] = run;
+            run = add2(run, t);
+        }
+        swave[16] = run;
+    }
+    __syncthreads();
+    ulonglong2 base = swave[w];
+    *total = swave[16];
+    __syncthreads();
+    ulonglong2 ex;
+    ex.x = base.x + inc.x - v.x;
+    ex.y = base.y + inc.y - v.y;
+    return ex;
+}
+
+template <int MODE>
+__device__ __forceinline__ void scan_range(const Bufs &b, uint64_t n, uint64_t *lo, uint64_t *hi) {
+    const uint64_t tile = (uint64_t)kScanThreads * kScanItems;
+    uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+    per = (per + tile - 1) / tile * tile;
+    *lo = per * blockIdx.x;
+    *hi = *lo + per < n ? *lo + per : n;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Bufs b, Knobs kn) {
+    const uint64_t n = scan_n<MODE>(b);
+    uint64_t lo, hi;
+    scan_range<MODE>(b, n, &lo, &hi);
+    ulonglong2 s;
+    s.x = 0;
+    s.y = 0;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s = add2(s, scan_load<MODE>(b, kn, i, n));
+    ulonglong2 tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) {
+        b.scan_part[2 * blockIdx.x] = tot.x;
+        b.scan_part[2 * blockIdx.x + 1] = tot.y;
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(1024) k_scan_parts(Bufs b, int32_t nparts) {
+    ulonglong2 v;
+    v.x = 0;
+    v.y = 0;
+    if ((int)threadIdx.x < nparts) {
+        v.x = b.scan_part[2 * threadIdx.x];
+        v.y = b.scan_part[2 * threadIdx.x + 1];
+    }
+    ulonglong2 tot;
+    ulonglong2 ex = block_excl_scan(v, &tot);
+    if ((int)threadIdx.x < nparts) {
+        b.scan_part[2 * threadIdx.x] = ex.x;
+        b.scan_part[2 * threadIdx.x + 1] = ex.y;
+    }
+    if (MODE == kScanRows && threadIdx.x == 0) {
+        b.ctr->nnz = tot.x;
+        b.ctr->long_total = tot.y;
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(Bufs b, Knobs kn) {
+    const uint64_t n = scan_n<MODE>(b);
+    uint64_t lo, hi;
+    scan_range<MODE>(b, n, &lo, &hi);
+    ulonglong2 run;
+    run.x = b.scan_part[2 * blockIdx.x];
+    run.y = b.scan_part[2 * blockIdx.x + 1];
+    for (uint64_t t0 = lo; t0 < hi; t0 += (uint64_t)kScanThreads * kScanItems) {
+        const uint64_t i0 = t0 + (uint64_t)threadIdx.x * kScanItems;
+        ulonglong2 v[kScanItems];
+        ulonglong2 s;
+        s.x = 0;
+        s.y = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = (i0 + k < hi) ? scan_load<MODE>(b, kn, i0 + k, n) : ulonglong2{0, 0};
+            s = add2(s, v[k]);
+        }
+        ulonglong2 tot;
+        ulonglong2 ex = block_excl_scan(s, &tot);
+        ex = add2(ex, run);
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (i0 + k < hi) scan_store<MODE>(b, i0 + k, ex);
+            ex = add2(ex, v[k]);
+        }
+        run = add2(run, tot);
+    }
+}
+
+// ----------------------------------------------------------- work items
+// A work item is a run of at most queries_per_item sorted queries whose
+// cells lie in one block of cells_per_item cells along grid axis 0 (same
+// coordinates on the other grid axes), so all of them share one set of
+// neighbour key runs.
+__global__ void __launch_bounds__(256) k_items(Bufs b, Knobs kn) {
+    const BatchDesc bd = *b.bd;
+    const int QB = kn.queries_per_item, R = kn.cells_per_item;
+    const uint32_t *qcells = kn.self_query ? b.cells : b.qcells;
+    const uint32_t *sqkey = kn.self_query ? b.skey : b.sqkey;
+    const int l = lane_id();
+    for (int c = blockIdx.x; c < bd.n_qchunks; c += gridDim.x) {
+        const Chunk ch = b.qchunks[c];
+        const GridDesc &g = b.grid[ch.ev];
+        const int G = g.G;
+        const int n0 = G > 0 ? g.n[0] : 1;
+        const int64_t coff = b.cell_off[ch.ev];
+        for (int64_t base = ch.r0; base < ch.r1; base += blockDim.x) {
+            const int64_t p = base + threadIdx.x;
+            bool start = false;
+            Item it{0, 0, 0, 0u};
+            if (p < ch.r1) {
+                const uint32_t k = sqkey[p];
+                const uint32_t c0 = G > 0 ? k % (uint32_t)n0 : 0u;
+                const uint32_t b0 = (c0 / R) * R;
+                const uint32_t b1 = min(b0 + R - 1, (uint32_t)n0 - 1);
+                const uint32_t kf = k - c0 + b0, kl = k - c0 + b1;
+                const int64_t rs = qcells[coff + kf], re = qcells[coff + kl + 1];
+                if ((p - rs) % QB == 0) {
+                    start = true;
+                    it = Item{(int32_t)p, (int32_t)min((int64_t)QB, re - p), ch.ev, k};
+                }
+            }
+            const uint64_t m = ballot(start);
+            if (m) {
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                uint32_t at = 0;
+                if (l == leader) at = atomicAdd(&b.ctr->n_items, (uint32_t)__popcll(m));
+                at = (uint32_t)__shfl((int)at, leader);
+                if (start) b.items[at + lanes_below(m)] = it;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------- count and fill pass
+template <int DT>
+struct QueryRow {
+    float q[DT];
+};
+
+// Squared distance in the canonical order: three rounded operations per
+// axis, axes 0..D-1, starting from +0.  x is a padded row in global memory.
+template <int DT, bool EXACT_D>
+__device__ __forceinline__ float dist2_row(const QueryRow<DT> &qr, const float *xrow, int D) {
+    constexpr int DP = (DT + 3) & ~3;
+    float x[DP];
+#pragma unroll
+    for (int d4 = 0; d4 < DP; d4 += 4) {
+        if (EXACT_D || d4 < D) {
+            float4 v = *reinterpret_cast<const float4 *>(xrow + d4);
+            x[d4] = v.x;
+            x[d4 + 1] = v.y;
+            x[d4 + 2] = v.z;
+            x[d4 + 3] = v.w;
+        }
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int d = 0; d < DT; ++d) {
+        if (EXACT_D || d < D) {
+            float t = qr.q[d] - x[d];
+            float u = t * t;
+            s = s + u;
+        }
+    }
+    return s;
+}
+
+struct WaveLds {
+    uint32_t run_base[kRunsMax];
+    uint32_t run_pref[kRunsMax + 1];
+    uint32_t cand[kCandLds];
+};
+
+// Position of candidate v (0 <= v < L) among the item's concatenated runs.
+__device__ __forceinline__ uint32_t locate(const WaveLds &s, int nruns, uint32_t v) {
+    int lo = 0, hi = nruns - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (s.run_pref[mid] <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return s.run_base[lo] + (v - s.run_pref[lo]);
+}
+
+template <int KS>
+__device__ __forceinline__ void sort_and_write(const uint64_t *hits, uint32_t n, uint32_t keep,
+                                               int32_t *idx, float *d2, int lane) {
+    uint64_t v[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        uint32_t e = s * 64 + lane;
+        v[s] = e < n ? hits[e] : ~0ull;
+    }
+    bitonic_sort<KS>(v, lane);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        uint32_t e = s * 64 + lane;
+        if (e < keep) {
+            idx[e] = (int32_t)(uint32_t)v[s];
+            if (d2) d2[e] = __uint_as_float((uint32_t)(v[s] >> 32));
+        }
+    }
+}
+
+// One wave per work item.  The wave lists the item's neighbour key runs
+// (contiguous ranges of sorted points: for each offset of the grid axes
+// 1..G-1 within +-m, the cells along axis 0 from the block start - m to the
+// block end + m), then evaluates each query of the item against every
+// candidate, 64 candidates per step, one per lane.
+// Count pass: number of hits per query.  Fill pass: the hit keys
+// (dist2 bits << 32 | reference id) gathered in LDS, sorted by the register
+// bitonic network and cut to K; rows longer than long_cap go to global
+// memory for k_long_sort.
+template <int DT, bool EXACT_D, bool FILL>
+__global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
+    __shared__ WaveLds slds[kWavesPerBlock];
+    __shared__ uint64_t shits[FILL ? kWavesPerBlock : 1][FILL ? kRowLds : 1];
+    constexpr int DP = (DT + 3) & ~3;
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    WaveLds &L = slds[w];
+    const BatchDesc &bd = *b.bd;
+    const int D = EXACT_D ? DT : bd.D;
+    const int Dp = EXACT_D ? DP : bd.Dp;
+    const uint32_t n_items = uniform(b.ctr->n_items);
+    const float r2 = kn.r2;
+    const uint32_t *cells = b.cells;
+    const float *qs = kn.self_query ? b.xs : b.qs;
+    const int32_t *qperm = kn.self_query ? b.perm : b.qperm;
+    int32_t *out_idx = nullptr;
+    float *out_d2 = nullptr;
+    if (FILL) {
+        out_idx = b.out->indices;
+        out_d2 = b.out->dist2;
+    }
+    uint64_t my_cand = 0;
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    uint32_t it = blockIdx.x * kWavesPerBlock + w;
+    for (;;) {
+        if (kn.persistent) {
+            uint32_t v = 0;
+            if (lane == 0) v = atomicAdd(FILL ? &b.ctr->head_fill : &b.ctr->head_count, 1u);
+            it = uniform((uint32_t)__shfl((int)v, 0));
+        }
+        if (it >= n_items) break;
+        const Item item = b.items[it];
+        if (!kn.persistent) it += nwaves;
+        const uint32_t qp0 = uniform((uint32_t)item.qpos);
+        const int nq = (int)uniform((uint32_t)item.nq);
+        const int e = (int)uniform((uint32_t)item.ev);
+        const uint32_t key = uniform(item.key);
+        const GridDesc &g = b.grid[e];
+        const int G = g.G, m = g.m, W = 2 * m + 1, runs = g.runs;
+        const int64_t coff = b.cell_off[e];
+        const int64_t q_off = b.ev[e].q_off;
+        // grid coordinates of the item's first cell
+        int c[kGMax] = {0, 0, 0, 0, 0, 0};
+        {
+            uint32_t rem = key;
+#pragma unroll
+            for (int a = 0; a < kGMax; ++a) {
+                if (a < G) {
+                    c[a] = (int)(rem % (uint32_t)g.n[a]);
+                    rem /= (uint32_t)g.n[a];
+                }
+            }
+        }
+        int lo0 = 0, hi0 = 0;
+        if (G > 0) {
+            const int R = kn.cells_per_item;
+            const int b0 = (c[0] / R) * R;
+            lo0 = max(b0 - m, 0);
+            hi0 = min(b0 + R - 1 + m, g.n[0] - 1);
+        }
+        // neighbour key runs, empty ones dropped
+        uint32_t total = 0;
+        int nruns = 0;
+        for (int s0 = 0; s0 < runs; s0 += 64) {
+            const int s = s0 + lane;
+            uint32_t start = 0, len = 0;
+            if (s < runs) {
+                int t = s;
+                bool ok = true;
+                uint32_t kk = 0;
+#pragma unroll
+                for (int a = 1; a < kGMax; ++a) {
+                    if (a < G) {
+                        const int ca = c[a] + (t % W) - m;
+                        t /= W;
+                        ok = ok && ca >= 0 && ca < g.n[a];
+                        kk += (uint32_t)ca * g.stride[a];
+                    }
+                }
+                if (ok) {
+                    start = cells[coff + kk + lo0];
+                    len = cells[coff + kk + hi0 + 1] - start;
+                }
+            }
+            const uint64_t nz = ballot(len > 0);
+            const uint32_t inc = wave_incl_scan(len);
+            if (len > 0) {
+                const int at = nruns + (int)lanes_below(nz);
+                L.run_base[at] = start;
+                L.run_pref[at] = total + inc - len;
+            }
+            total += uniform((uint32_t)__shfl((int)inc, 63));
+            nruns += __popcll(nz);
+        }
+        if (lane == 0) L.run_pref[nruns] = total;
+        wave_lds_sync();
+        const bool listed = total <= (uint32_t)kCandLds;
+        if (listed) {
+            for (uint32_t v = lane; v < total; v += 64) L.cand[v] = locate(L, nruns, v);
+            wave_lds_sync();
+        }
+        for (int t = 0; t < nq; ++t) {
+            const uint32_t qp = qp0 + t;
+            QueryRow<DT> qr;
+            const float *qrow = qs + (int64_t)qp * Dp;
+#pragma unroll
+            for (int d = 0; d < DT; ++d) qr.q[d] = (EXACT_D || d < D) ? qrow[d] : 0.0f;
+            const int64_t qid = q_off + qperm[qp];
+            if (!FILL) {
+                uint32_t cnt = 0;
+                for (uint32_t v0 = 0; v0 < total; v0 += 64) {
+                    const uint32_t v = v0 + lane;
+                    const bool valid = v < total;
+                    const uint32_t pos = valid ? (listed ? L.cand[v] : locate(L, nruns, v)) : 0u;
+                    const float s = dist2_row<DT, EXACT_D>(qr, b.xs + (int64_t)pos * Dp, D);
+                    const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == qp);
+                    cnt += (uint32_t)__popcll(ballot(hit));
+                }
+                if (lane == 0) b.deg[qid] = cnt;
+                my_cand += total;
+            } else {
+                const uint32_t dq = b.deg[qid];
+                if (dq == 0) continue;
+                const int64_t off = b.offs[qid];
+                const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
+                const bool lng = dq > (uint32_t)kn.long_cap;
+                uint64_t *dst = lng ? b.out->long_keys + b.lofs[qid] : &shits[w][0];
+                uint32_t nh = 0;
+                for (uint32_t v0 = 0; v0 < total; v0 += 64) {
+                    const uint32_t v = v0 + lane;
+                    const bool valid = v < total;
+                    const uint32_t pos = valid ? (listed ? L.cand[v] : locate(L, nruns, v)) : 0u;
+                    const float s = dist2_row<DT, EXACT_D>(qr, b.xs + (int64_t)pos * Dp, D);
+                    const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == qp);
+                    const uint64_t hm = ballot(hit);
+                    if (hit) {
+                        const uint32_t slot = nh + lanes_below(hm);
+                        const uint32_t j = (uint32_t)b.perm[pos];  // original id, hits only
+                        if (slot < dq) dst[slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                    }
+                    nh += (uint32_t)__popcll(hm);
+                }
+                if (nh != dq && lane == 0) atomicOr(&b.ctr->status, kStatusInternal);
+                if (lng) {
+                    if (lane == 0) {
+                        const uint32_t li = atomicAdd(&b.ctr->n_long, 1u);
+                        b.long_rows[li] = (uint32_t)qid;
+                    }
+                    continue;
+                }
+                wave_lds_sync();
+                int32_t *oi = out_idx + off;
+                float *od = out_d2 ? out_d2 + off : nullptr;
+                if (dq <= 64)
+                    sort_and_write<1>(&shits[w][0], dq, keep, oi, od, lane);
+                else if (dq <= 128)
+                    sort_and_write<2>(&shits[w][0], dq, keep, oi, od, lane);
+                else if (dq <= 256)
+                    sort_and_write<4>(&shits[w][0], dq, keep, oi, od, lane);
+                else
+                    sort_and_write<8>(&shits[w][0], dq, keep, oi, od, lane);
+                wave_lds_sync();
+            }
+        }
+        wave_lds_sync();
+    }
+    if (!FILL && lane == 0 && my_cand) atomicAdd((unsigned long long *)&b.ctr->candidates, (unsigned long long)my_cand);
+}
+
+// ------------------------------------------------------------ long rows
+// One block per long row: sort its keys in place in global memory with the
+// all-ascending bitonic network (absent elements past n act as +infinity and
+// never move), then write the first min(n, K).
+__global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
+    const uint32_t n_long = b.ctr->n_long;
+    for (uint32_t li = blockIdx.x; li < n_long; li += gridDim.x) {
+        const uint32_t qid = b.long_rows[li];
+        const uint64_t n = b.deg[qid];
+        uint64_t *a = b.out->long_keys + b.lofs[qid];
+        uint64_t P = 1;
+        while (P < n) P <<= 1;
+        for (uint64_t k = 2; k <= P; k <<= 1) {
+            const uint64_t half = k >> 1;
+            for (uint64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const uint64_t lo = (t / half) * k + (t % half);
+                const uint64_t hi = lo ^ (k - 1);
+                if (hi < n) {
+                    uint64_t x = a[lo], y = a[hi];
+                    if (y < x) {
+                        a[lo] = y;
+                        a[hi] = x;
+                    }
+                }
+            }
+            __syncthreads();
+            for (uint64_t j = k >> 2; j >= 1; j >>= 1) {
+                for (uint64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                    const uint64_t lo = (t / j) * 2 * j + (t % j);
+                    const uint64_t hi = lo + j;
+                    if (hi < n) {
+                        uint64_t x = a[lo], y = a[hi];
+                        if (y < x) {
+                            a[lo] = y;
+                            a[hi] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        const uint64_t keep = (kn.K > 0 && n > (uint64_t)kn.K) ? (uint64_t)kn.K : n;
+        const int64_t off = b.offs[qid];
+        for (uint64_t e = threadIdx.x; e < keep; e += blockDim.x) {
+            b.out->indices[off + e] = (int32_t)(uint32_t)a[e];
+            if (b.out->dist2) b.out->dist2[off + e] = __uint_as_float((uint32_t)(a[e] >> 32));
+        }
+        __syncthreads();
+    }
+}
+
+// First output pair of every event (the host reads these with the counters).
+__global__ void k_bases(Bufs b) {
+    const BatchDesc bd = *b.bd;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e <= bd.E; e += gridDim.x * blockDim.x) {
+        const int64_t q = e < bd.E ? b.ev[e].q_off : bd.total_q;
+        b.bases[e] = b.offs[q];
+    }
+}
+
+// Per-event offsets: event e's rows start at offsets[q_off + e] = 0.
+__global__ void __launch_bounds__(256) k_finalize(Bufs b) {
+    const BatchDesc bd = *b.bd;
+    int64_t *eo = b.out->offsets;
+    if (blockIdx.x == 0)
+        for (int e = threadIdx.x; e < bd.E; e += blockDim.x) eo[b.ev[e].q_off + e] = 0;
+    for (int c = blockIdx.x; c < bd.n_qchunks; c += gridDim.x) {
+        const Chunk ch = b.qchunks[c];
+        const int64_t base = b.bases[ch.ev];
+        for (int64_t g = ch.r0 + threadIdx.x; g < ch.r1; g += blockDim.x)
+            eo[g + ch.ev + 1] = b.offs[g + 1] - base;
+    }
+}
+
+// Writes the output descriptor from kernel arguments (so the values are
+// captured at launch time, unlike a copy from host memory).
+__global__ void k_set_out(OutDesc *dst, OutDesc v) {
+    if (threadIdx.x == 0) *dst = v;
+}
+
+// --------------------------------------------------------------- launches
+#define FRNN_CHECK_LAUNCH() \
+    do {                    \
+        hipError_t e_ = hipGetLastError(); \
+        if (e_ != hipSuccess) return e_;   \
+    } while (0)
+
+hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s) {
+    int64_t n = std::max<int64_t>((int64_t)E * 2 * D, sizeof(Counters) / 4);
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, b, (int32_t)init_ext);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_extent, dim3(std::min(nchunks, 8192)), dim3(256), 0, s, b, (int32_t)queries);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_plan(const Bufs &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(256), 0, s, b);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_zero_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s) {
+    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((cells_cap + 1 + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_zero_cells, dim3(blocks), dim3(256), 0, s, b, (int32_t)queries);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_keys(const Bufs &b, int nchunks, bool queries, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys, dim3(std::min(nchunks, 8192)), dim3(256), 0, s, b, (int32_t)queries);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3(std::min(nchunks, 8192)), dim3(256), 0, s, b, (int32_t)queries);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+static int scan_blocks(int64_t n_cap) {
+    int64_t nb = (n_cap + 4095) / 4096;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, kScanBlocks));
+}
+
+template <int MODE>
+static hipError_t launch_scan_mode(const Bufs &b, const Knobs &kn, int64_t n_cap, hipStream_t s) {
+    const int nb = scan_blocks(n_cap);
+    hipLaunchKernelGGL(k_scan_reduce<MODE>, dim3(nb), dim3(kScanThreads), 0, s, b, kn);
+    FRNN_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan_parts<MODE>, dim3(1), dim3(1024), 0, s, b, (int32_t)nb);
+    FRNN_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan_apply<MODE>, dim3(nb), dim3(kScanThreads), 0, s, b, kn);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_scan_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s) {
+    Knobs kn{};
+    return queries ? launch_scan_mode<kScanQCells>(b, kn, cells_cap + 1, s)
+                   : launch_scan_mode<kScanCells>(b, kn, cells_cap + 1, s);
+}
+
+hipError_t launch_scan_rows(const Bufs &b, const Knobs &kn, int64_t total_q, hipStream_t s) {
+    return launch_scan_mode<kScanRows>(b, kn, total_q + 1, s);
+}
+
+hipError_t launch_items(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s) {
+    if (nqchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_items, dim3(std::min(nqchunks, 8192)), dim3(256), 0, s, b, kn);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <bool FILL>
+static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
+    dim3 grid(blocks), block(64 * kWavesPerBlock);
+    switch (D) {
+    case 3: hipLaunchKernelGGL((k_query<3, true, FILL>), grid, block, 0, s, b, kn); break;
+    case 8: hipLaunchKernelGGL((k_query<8, true, FILL>), grid, block, 0, s, b, kn); break;
+    case 12: hipLaunchKernelGGL((k_query<12, true, FILL>), grid, block, 0, s, b, kn); break;
+    default:
+        if (D <= 4)
+            hipLaunchKernelGGL((k_query<4, false, FILL>), grid, block, 0, s, b, kn);
+        else if (D <= 16)
+            hipLaunchKernelGGL((k_query<16, false, FILL>), grid, block, 0, s, b, kn);
+        else
+            hipLaunchKernelGGL((k_query<32, false, FILL>), grid, block, 0, s, b, kn);
+    }
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_count(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
+    return launch_query_t<false>(b, kn, D, blocks, s);
+}
+
+hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
+    return launch_query_t<true>(b, kn, D, blocks, s);
+}
+
+hipError_t launch_bases(const Bufs &b, int E, hipStream_t s) {
+    int blocks = std::max(1, std::min((E + 1 + 255) / 256, 64));
+    hipLaunchKernelGGL(k_bases, dim3(blocks), dim3(256), 0, s, b);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_long_sort, dim3(std::max(1, blocks)), dim3(256), 0, s, b, kn);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_set_out(OutDesc *dst, const OutDesc &v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_out, dim3(1), dim3(64), 0, s, dst, v);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_finalize(const Bufs &b, int nqchunks, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(std::max(1, std::min(nqchunks, 8192))), dim3(256), 0, s, b);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+}  // namespace frnn

@@ -1,0 +1,28 @@
+// Host-side launchers of the pipeline kernels (frnn_kernels.hip).  Each
+// returns the launch error, if any; grid sizes are capacities, the kernels
+// read the actual sizes from device memory.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "frnn_device.h"
+
+namespace frnn {
+
+hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s);
+hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, hipStream_t s);
+hipError_t launch_plan(const Bufs &b, hipStream_t s);
+hipError_t launch_zero_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s);
+hipError_t launch_keys(const Bufs &b, int nchunks, bool queries, hipStream_t s);
+hipError_t launch_scan_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s);
+hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t s);
+hipError_t launch_items(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s);
+hipError_t launch_count(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
+hipError_t launch_scan_rows(const Bufs &b, const Knobs &kn, int64_t total_q, hipStream_t s);
+hipError_t launch_bases(const Bufs &b, int E, hipStream_t s);
+hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
+hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStream_t s);
+hipError_t launch_finalize(const Bufs &b, int nqchunks, hipStream_t s);
+hipError_t launch_set_out(OutDesc *dst, const OutDesc &v, hipStream_t s);
+
+}  // namespace frnn

@@ -1,0 +1,200 @@
+// Host runtime of libfrnn: device memory pool, pipeline runs, instrumentation.
+// Shared by the C ABI, the batcher, the server and the tuner.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <atomic>
+#include <functional>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/frnn.h"
+#include "frnn_device.h"
+
+namespace frnn {
+
+// ----------------------------------------------------------------- errors
+struct Fail {
+    frnn_status st;
+    std::string msg;
+};
+
+void set_error(const std::string &msg);
+frnn_status fail(frnn_status st, const std::string &msg);
+
+#define FRNN_HIP(call)                                                              \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            throw ::frnn::Fail{FRNN_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+// ------------------------------------------------------------------- pool
+// Caching device allocator.  Blocks are kept in size classes (2^k times
+// 1, 1.25, 1.5, 1.75) and reused; a block freed on one stream and handed out
+// on another makes the new stream wait for the free point (stream-ordered
+// reuse without host synchronisation).
+class Pool {
+public:
+    static Pool &get();
+    void *alloc(size_t bytes, hipStream_t s);
+    void free(void *p, hipStream_t s);
+    void trim();
+    int64_t held() const { return held_.load(); }
+    int64_t in_use() const { return in_use_.load(); }
+    int64_t peak() const { return peak_.load(); }
+    // test hook: the k-th allocation from now fails (0 = off)
+    void fail_after(int64_t k) { fail_at_ = k; }
+
+private:
+    struct Block {
+        void *p;
+        size_t cls;
+        hipEvent_t ready;   // recorded at free
+        hipStream_t stream; // stream of the free
+    };
+    static size_t size_class(size_t bytes);
+    std::mutex mu_;
+    std::vector<Block> free_;
+    std::vector<std::pair<void *, size_t>> live_;
+    std::atomic<int64_t> held_{0}, in_use_{0}, peak_{0};
+    std::atomic<int64_t> fail_at_{0};
+};
+
+// Owner of one pool block, returned on the stream it was last used on.
+class DevBuf {
+public:
+    DevBuf() = default;
+    DevBuf(size_t bytes, hipStream_t s) { reset(bytes, s); }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            p_ = o.p_;
+            bytes_ = o.bytes_;
+            s_ = o.s_;
+            o.p_ = nullptr;
+            o.bytes_ = 0;
+        }
+        return *this;
+    }
+    void reset(size_t bytes, hipStream_t s) {
+        release();
+        s_ = s;
+        bytes_ = bytes;
+        p_ = Pool::get().alloc(bytes ? bytes : 16, s);
+    }
+    void release() {
+        if (p_) Pool::get().free(p_, s_);
+        p_ = nullptr;
+        bytes_ = 0;
+    }
+    void set_stream(hipStream_t s) { s_ = s; }
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(p_); }
+    void *get() const { return p_; }
+    size_t bytes() const { return bytes_; }
+
+private:
+    void *p_ = nullptr;
+    size_t bytes_ = 0;
+    hipStream_t s_ = nullptr;
+};
+
+// Pinned host staging buffer (grows, never shrinks).
+class Pinned {
+public:
+    ~Pinned();
+    void *ensure(size_t bytes);
+    template <class T>
+    T *as() { return reinterpret_cast<T *>(p_); }
+
+private:
+    void *p_ = nullptr;
+    size_t bytes_ = 0;
+};
+
+// ---------------------------------------------------------- instrumentation
+void prof_begin(const char *name, hipStream_t s, bool capturing);
+void prof_end(hipStream_t s, bool capturing);
+bool prof_enabled();
+
+// ------------------------------------------------------------- pipeline
+struct Opts {
+    frnn_opts o;
+    static Opts from(const frnn_opts *p);
+    frnn_status validate(std::string *why) const;
+};
+
+// Reference points of E events, binned (device-resident, immutable).
+struct Index {
+    int E = 0, D = 0, Dp = 0;
+    float r = 0.f;
+    Opts opts;
+    int64_t total_pts = 0, cells_cap = 0;
+    int n_pchunks = 0;
+    std::vector<int64_t> n_pts, pt_off;
+    std::vector<const float *> pts;
+    DevBuf bd, ev, pchunks, grid, cell_off, ext, xs, perm, skey, cells, ctr;
+    std::vector<GridDesc> grid_host;  // valid after a synchronised build
+    Pinned stage;                     // descriptor staging of the build copies
+    hipStream_t stream = nullptr;
+};
+
+struct OutputOwner {
+    DevBuf buf;                     // offsets | indices | dist2
+    std::atomic<int> refs{0};
+    std::function<void()> on_release;  // e.g. return the bytes to a budget
+    ~OutputOwner() {
+        if (on_release) on_release();
+    }
+};
+
+// Build an index over E events (points[e] is device [n[e]][D]).  With sync,
+// waits for the build and reports non-finite input; without, the status is
+// checked by the first query run on the same stream.
+frnn_status build_index(Index &ix, const float *const *points, const int64_t *n, int E, int D,
+                        float r, const Opts &opts, hipStream_t s, bool sync);
+
+// Query an index: queries[e] device [m[e]][D], or the indexed points when
+// self_query.  Produces E CSRs sharing one allocation.
+struct QueryArgs {
+    const float *const *queries = nullptr;
+    const int64_t *m = nullptr;
+    float r = 0.f;
+    int K = 0;
+    uint32_t flags = 0;
+};
+frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *outs,
+                      frnn_stats *stats);
+
+// Last run's counters (thread-local).
+void record_stats(const frnn_stats &st);
+frnn_stats last_stats();
+const char *last_error_cstr();
+void prof_set(bool on);
+int prof_read(frnn_kernel_time *out, int cap, bool reset);
+
+float r2_of(float r);
+
+// Graph capture in progress on this thread (per-launch timing is skipped).
+void set_capturing(bool on);
+bool capturing();
+
+#define LAUNCH(name, stream, call)                                                     \
+    do {                                                                               \
+        ::frnn::prof_begin(name, stream, ::frnn::capturing());                         \
+        hipError_t e_ = (call);                                                        \
+        ::frnn::prof_end(stream, ::frnn::capturing());                                 \
+        if (e_ != hipSuccess)                                                          \
+            throw ::frnn::Fail{FRNN_ERR_HIP, std::string("launch ") + name + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+}  // namespace frnn

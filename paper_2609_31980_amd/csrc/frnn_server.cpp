@@ -1,0 +1,326 @@
+// Serving loop: continuous batching of arriving events under an HBM budget.
+//
+// Submissions are copied to host memory and queued.  A dispatcher inside
+// each of max_inflight worker threads (each with its own HIP stream) takes
+// whatever is queued, admits events while their pre-count footprint fits the
+// budget, and runs them as one batch through the batched pipeline.  Because
+// several workers run at once, a new batch is binned and counted on one
+// stream while earlier batches are still being filled on others.  After the
+// count pass the batch's exact output size is known; it is reserved against
+// the budget (waiting for releases if needed) before the fill.  Output bytes
+// stay charged until the client releases the result.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "frnn_batch.h"
+#include "frnn_runtime.h"
+
+using namespace frnn;
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Budget {
+    std::mutex mu;
+    std::condition_variable cv;
+    int64_t limit = 0, used = 0, peak = 0;
+    void add(int64_t b) {
+        std::lock_guard<std::mutex> g(mu);
+        used += b;
+        peak = std::max(peak, used);
+    }
+    void sub(int64_t b) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            used -= b;
+        }
+        cv.notify_all();
+    }
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    int64_t N = 0;
+    std::vector<float> host;   // submitted points
+    int64_t precount = 0;      // bytes reserved at admission
+    frnn_timing tm{};
+    frnn_csr out{};
+    frnn_status st = FRNN_OK;
+    std::string err;
+    bool done = false;
+};
+
+}  // namespace
+
+struct frnn_server_s {
+    frnn_server_opts o{};
+    Opts opts;
+    std::shared_ptr<Budget> budget = std::make_shared<Budget>();
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Request>> queue;
+    std::map<uint64_t, std::shared_ptr<Request>> live;
+    std::vector<std::thread> workers;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    int next_batch = 0;
+
+    int64_t precount_bytes(int64_t N) const {
+        const int64_t D = o.D, Dp = (o.D + 3) & ~3;
+        const double cpp = opts.o.cells_per_point;
+        // input + sorted rows + 4 per-point arrays + cells + per-query work
+        return N * (4 * D + 4 * Dp + 16 + 40) + (int64_t)(4.0 * cpp * (double)N) + 4096;
+    }
+    void worker(int id);
+};
+
+void frnn_server_s::worker(int id) {
+    (void)id;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+    const bool want_d2 = o.flags & FRNN_WANT_DIST2;
+    for (;;) {
+        std::vector<std::shared_ptr<Request>> batch;
+        int bid = 0;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+            if (stop && queue.empty()) break;
+            // admit in arrival order while the pre-count footprint fits
+            while (!queue.empty() && (int)batch.size() < o.max_batch_events) {
+                auto &r = queue.front();
+                std::unique_lock<std::mutex> bl(budget->mu);
+                if (budget->used + r->precount > budget->limit) break;
+                budget->used += r->precount;
+                budget->peak = std::max(budget->peak, budget->used);
+                bl.unlock();
+                r->tm.admit_s = now_s();
+                batch.push_back(r);
+                queue.pop_front();
+            }
+            if (batch.empty()) {
+                // over budget: wait for a release, then try again
+                lk.unlock();
+                std::unique_lock<std::mutex> bl(budget->mu);
+                budget->cv.wait_for(bl, std::chrono::milliseconds(2));
+                continue;
+            }
+            bid = next_batch++;
+            if (!queue.empty()) cv_work.notify_one();
+        }
+        const int E = (int)batch.size();
+        const double t0 = now_s();
+        for (auto &r : batch) {
+            r->tm.start_s = t0;
+            r->tm.batch_id = bid;
+            r->tm.batch_events = E;
+        }
+        frnn_status st = FRNN_OK;
+        std::string err;
+        std::vector<frnn_csr> outs(E);
+        try {
+            std::vector<DevBuf> inputs(E);
+            std::vector<frnn_event> ev(E);
+            for (int e = 0; e < E; ++e) {
+                const size_t bytes = sizeof(float) * std::max<int64_t>(1, batch[e]->N) * o.D;
+                inputs[e].reset(bytes, s);
+                if (batch[e]->N)
+                    FRNN_HIP(hipMemcpyAsync(inputs[e].get(), batch[e]->host.data(),
+                                            sizeof(float) * batch[e]->N * o.D, hipMemcpyHostToDevice, s));
+                ev[e] = frnn_event{inputs[e].as<float>(), batch[e]->N, nullptr, 0};
+            }
+            auto need = BatchContext::shape_for(ev.data(), E, o.D, o.r, o.K, o.flags, opts);
+            std::unique_ptr<BatchContext> ctx = acquire_context(need, s);
+            try {
+                ctx->set_inputs(ev.data(), E, s);
+                ctx->phase_a(s);
+                BatchCounts c = ctx->read_counts(s);
+                if (c.build_status & kStatusNonfinitePts)
+                    throw Fail{FRNN_ERR_NONFINITE, "non-finite coordinate in the points"};
+                // post-count reservation of the exact output
+                const int64_t outb = (int64_t)sizeof(int64_t) * (ctx->total_q() + E) +
+                                     (int64_t)c.ctr.nnz * (want_d2 ? 8 : 4) +
+                                     (int64_t)c.ctr.long_total * 8 + 512;
+                {
+                    std::unique_lock<std::mutex> bl(budget->mu);
+                    if (outb > budget->limit) throw Fail{FRNN_ERR_BUDGET, "batch output exceeds the budget"};
+                    const bool ok = budget->cv.wait_for(bl, std::chrono::seconds(30), [&] {
+                        return budget->used + outb <= budget->limit;
+                    });
+                    if (!ok) throw Fail{FRNN_ERR_BUDGET, "timed out waiting for budget"};
+                    budget->used += outb;
+                    budget->peak = std::max(budget->peak, budget->used);
+                }
+                BatchOutput bo = alloc_output(*ctx, c, want_d2, s);
+                std::shared_ptr<Budget> bud = budget;
+                bo.own->on_release = [bud, outb]() { bud->sub(outb); };
+                ctx->phase_b(bo.od, s);
+                hand_out(*ctx, c, bo, outs.data());
+            } catch (...) {
+                return_context(std::move(ctx), s);
+                throw;
+            }
+            return_context(std::move(ctx), s);
+            FRNN_HIP(hipStreamSynchronize(s));  // results complete on the device
+        } catch (const Fail &f) {
+            st = f.st;
+            err = f.msg;
+        } catch (const std::exception &x) {
+            st = FRNN_ERR_INTERNAL;
+            err = x.what();
+        }
+        const double t1 = now_s();
+        int64_t pre = 0;
+        for (auto &r : batch) pre += r->precount;
+        budget->sub(pre);
+        {
+            std::lock_guard<std::mutex> g(mu);
+            for (int e = 0; e < E; ++e) {
+                auto &r = batch[e];
+                r->tm.done_s = t1;
+                r->st = st;
+                r->err = err;
+                if (st == FRNN_OK) r->out = outs[e];
+                r->host.clear();
+                r->host.shrink_to_fit();
+                r->done = true;
+            }
+        }
+        if (st != FRNN_OK)
+            for (auto &oc : outs) frnn_csr_release(&oc);
+        cv_done.notify_all();
+    }
+    (void)hipStreamDestroy(s);
+}
+
+extern "C" {
+
+void frnn_server_opts_default(frnn_server_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->D = 8;
+    o->r = 0.1f;
+    o->K = 0;
+    o->flags = FRNN_WANT_DIST2 | FRNN_SELF_QUERY;
+    o->hbm_budget_bytes = (int64_t)64 << 30;
+    o->max_batch_events = 64;
+    o->max_inflight = 2;
+    frnn_opts_default(&o->opts);
+}
+
+frnn_status frnn_server_create(const frnn_server_opts *o, frnn_server *out) {
+    if (out) *out = nullptr;
+    try {
+        if (!o || !out) return fail(FRNN_ERR_INVALID_ARG, "null argument");
+        if (o->D < 1 || o->D > kDMax) return fail(FRNN_ERR_INVALID_ARG, "D must be in 1..32");
+        if (!(o->r >= 0.f) || !std::isfinite(o->r)) return fail(FRNN_ERR_INVALID_ARG, "bad radius");
+        if (o->hbm_budget_bytes <= 0) return fail(FRNN_ERR_INVALID_ARG, "budget must be positive");
+        if (o->max_batch_events < 1 || o->max_batch_events > 1024)
+            return fail(FRNN_ERR_INVALID_ARG, "max_batch_events out of 1..1024");
+        if (o->max_inflight < 1 || o->max_inflight > 8) return fail(FRNN_ERR_INVALID_ARG, "max_inflight out of 1..8");
+        if (o->flags & ~(uint32_t)(FRNN_WANT_DIST2 | FRNN_SELF_QUERY | FRNN_EXCLUDE_SELF))
+            return fail(FRNN_ERR_INVALID_ARG, "unknown flag");
+        auto *s = new frnn_server_s();
+        s->o = *o;
+        s->o.flags |= FRNN_SELF_QUERY;
+        s->opts = Opts::from(&o->opts);
+        std::string why;
+        frnn_status st = s->opts.validate(&why);
+        if (st) {
+            delete s;
+            return fail(st, why);
+        }
+        s->budget->limit = o->hbm_budget_bytes;
+        for (int i = 0; i < o->max_inflight; ++i) s->workers.emplace_back([s, i] { s->worker(i); });
+        *out = s;
+        return FRNN_OK;
+    } catch (const std::exception &x) {
+        return fail(FRNN_ERR_INTERNAL, x.what());
+    }
+}
+
+frnn_status frnn_server_submit(frnn_server s, const float *points, int64_t N, uint64_t *ticket) {
+    if (ticket) *ticket = 0;
+    try {
+        if (!s || !ticket || N < 0 || N >= ((int64_t)1 << 31) || (N > 0 && !points))
+            return fail(FRNN_ERR_INVALID_ARG, "bad submission");
+        auto r = std::make_shared<Request>();
+        r->N = N;
+        r->precount = s->precount_bytes(N);
+        if (r->precount > s->budget->limit) return fail(FRNN_ERR_BUDGET, "event larger than the whole budget");
+        r->host.assign(points, points + N * (int64_t)s->o.D);
+        r->tm.submit_s = now_s();
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            if (s->stop) return fail(FRNN_ERR_INVALID_ARG, "server is stopping");
+            r->ticket = s->next_ticket++;
+            s->live[r->ticket] = r;
+            s->queue.push_back(r);
+        }
+        s->cv_work.notify_one();
+        *ticket = r->ticket;
+        return FRNN_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FRNN_ERR_OOM, "host allocation failed");
+    } catch (const std::exception &x) {
+        return fail(FRNN_ERR_INTERNAL, x.what());
+    }
+}
+
+frnn_status frnn_server_wait(frnn_server s, uint64_t ticket, double timeout_s, frnn_csr *out,
+                             frnn_timing *timing) {
+    if (out) std::memset(out, 0, sizeof(*out));
+    try {
+        if (!s || !out) return fail(FRNN_ERR_INVALID_ARG, "null argument");
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->live.find(ticket);
+        if (it == s->live.end()) return fail(FRNN_ERR_INVALID_ARG, "unknown ticket");
+        std::shared_ptr<Request> r = it->second;
+        auto ready = [&] { return r->done; };
+        if (timeout_s < 0) {
+            s->cv_done.wait(lk, ready);
+        } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
+            return fail(FRNN_ERR_NOT_READY, "ticket still in flight");
+        }
+        s->live.erase(ticket);
+        if (timing) *timing = r->tm;
+        if (r->st != FRNN_OK) return fail(r->st, r->err);
+        *out = r->out;
+        r->out = frnn_csr{};
+        return FRNN_OK;
+    } catch (const std::exception &x) {
+        return fail(FRNN_ERR_INTERNAL, x.what());
+    }
+}
+
+void frnn_server_destroy(frnn_server s) {
+    if (!s) return;
+    try {
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->stop = true;
+        }
+        s->cv_work.notify_all();
+        for (auto &t : s->workers) t.join();
+        for (auto &kv : s->live) frnn_csr_release(&kv.second->out);
+        delete s;
+    } catch (...) {
+    }
+}
+
+}  // extern "C"
