@@ -77,6 +77,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     ctr_b.reset(sizeof(Counters), s);
     hv.reset(sizeof(Counters) + sizeof(int64_t) * (Ec + 1), s);
     grid.reset(sizeof(GridDesc) * Ec, s);
+    runs.reset(sizeof(RunEntry) * kRunsMax * Ec, s);
     cell_off.reset(sizeof(int64_t) * (Ec + 1), s);
     ext.reset(sizeof(uint32_t) * 2 * Ec * D, s);
     xs.reset(sizeof(float) * sh.pts_cap * Dp_, s);
@@ -93,11 +94,11 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
         sqkey.reset(sizeof(uint32_t) * sh.q_cap, s);
         qcells.reset(sizeof(uint32_t) * (sh.cells_cap + 1), s);
     }
-    items.reset(sizeof(Item) * sh.q_cap, s);
     deg.reset(sizeof(uint32_t) * sh.q_cap, s);
     offs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
     lofs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
     lrows.reset(sizeof(uint32_t) * sh.q_cap, s);
+    stash.reset(sizeof(uint64_t) * sh.q_cap * std::max(1, sh.o.stash_cap), s);
     part.reset(sizeof(uint64_t) * 2 * kScanBlocks, s);
     outd.reset(sizeof(OutDesc), s);
 
@@ -107,6 +108,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     b.pchunks = pch.as<Chunk>();
     b.qchunks = qch.as<Chunk>();
     b.grid = grid.as<GridDesc>();
+    b.runs = runs.as<RunEntry>();
     b.cell_off = cell_off.as<int64_t>();
     b.ext = ext.as<uint32_t>();
     b.xs = xs.as<float>();
@@ -121,11 +123,11 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     b.qrank = qrank.as<uint32_t>();
     b.sqkey = selfq ? skey.as<uint32_t>() : sqkey.as<uint32_t>();
     b.qcells = selfq ? cells.as<uint32_t>() : qcells.as<uint32_t>();
-    b.items = items.as<Item>();
     b.deg = deg.as<uint32_t>();
     b.offs = offs.as<int64_t>();
     b.lofs = lofs.as<int64_t>();
     b.long_rows = lrows.as<uint32_t>();
+    b.stash = stash.as<uint64_t>();
     b.scan_part = part.as<uint64_t>();
     b.out = outd.as<OutDesc>();
     b.bases = reinterpret_cast<int64_t *>(hv.as<char>() + sizeof(Counters));
@@ -138,10 +140,18 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     kn_.K = sh.K;
     kn_.self_query = selfq;
     kn_.exclude_self = selfq && (sh.flags & FRNN_EXCLUDE_SELF);
-    kn_.queries_per_item = sh.o.queries_per_item;
+    kn_.window = sh.o.queries_per_item;
     kn_.cells_per_item = sh.o.cells_per_item;
     kn_.long_cap = sh.o.row_cap_lds;
     kn_.persistent = sh.o.persistent;
+    kn_.stash_cap = sh.o.stash_cap;
+}
+
+void BatchContext::retarget(hipStream_t s) {
+    DevBuf *all[] = {&bd_b, &bd_q, &ev_b, &ev_q, &pch, &qch, &ctr_b, &hv, &grid, &cell_off, &ext,
+                     &xs, &perm, &key, &rank, &skey, &cells, &qs, &qperm, &qkey, &qrank, &sqkey,
+                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &stash, &part, &outd};
+    for (DevBuf *d : all) d->set_stream(s);
 }
 
 BatchContext::~BatchContext() {
@@ -208,11 +218,6 @@ void BatchContext::set_inputs(const frnn_event *ev, int E, hipStream_t s) {
         FRNN_HIP(hipMemcpyAsync(qch.get(), h + o_qc, sizeof(Chunk) * qc.size(), hipMemcpyHostToDevice, s));
 }
 
-static int qblocks_for(const frnn_opts &o, int64_t q_cap) {
-    int64_t cap = (int64_t)256 * o.blocks_per_cu;
-    int64_t need = (q_cap + kWavesPerBlock - 1) / kWavesPerBlock;
-    return (int)std::max<int64_t>(1, std::min(cap, need));
-}
 
 void BatchContext::launch_a(hipStream_t s) {
     const bool selfq = sh_.flags & FRNN_SELF_QUERY;
@@ -232,14 +237,14 @@ void BatchContext::launch_a(hipStream_t s) {
         LAUNCH("scan_cells_q", s, launch_scan_cells(bq_, sh_.cells_cap, true, s));
         LAUNCH("scatter_q", s, launch_scatter(bq_, sh_.qch_cap, true, s));
     }
-    LAUNCH("items", s, launch_items(bq_, kn_, sh_.qch_cap, s));
-    LAUNCH("count", s, launch_count(bq_, kn_, D, qblocks_for(sh_.o, sh_.q_cap), s));
+    LAUNCH("count", s, launch_count(bq_, kn_, D, query_blocks(sh_.o, sh_.qch_cap), s));
     LAUNCH("scan_rows", s, launch_scan_rows(bq_, kn_, sh_.q_cap, s));
     LAUNCH("bases", s, launch_bases(bq_, sh_.E_cap, s));
 }
 
 void BatchContext::launch_b(hipStream_t s) {
-    LAUNCH("fill", s, launch_fill(bq_, kn_, sh_.D, qblocks_for(sh_.o, sh_.q_cap), s));
+    LAUNCH("stash_sort", s, launch_stash_sort(bq_, kn_, sh_.qch_cap, s));
+    LAUNCH("fill", s, launch_fill(bq_, kn_, sh_.D, query_blocks(sh_.o, sh_.qch_cap), s));
     LAUNCH("long_sort", s, launch_long_sort(bq_, kn_, 256, s));
     LAUNCH("finalize", s, launch_finalize(bq_, sh_.qch_cap, s));
 }
@@ -328,7 +333,8 @@ struct Cached {
     hipEvent_t done;
 };
 std::mutex g_cache_mu;
-std::vector<Cached> g_cache;
+// never destroyed: no HIP call may run from a static destructor at exit
+std::vector<Cached> &g_cache = *new std::vector<Cached>();
 constexpr size_t kCacheMax = 8;
 }  // namespace
 
@@ -346,6 +352,7 @@ std::unique_ptr<BatchContext> acquire_context(const BatchContext::Shape &need, h
             // the previous run of this context may still be on another stream
             FRNN_HIP(hipStreamWaitEvent(s, c.done, 0));
             (void)hipEventDestroy(c.done);
+            c.ctx->retarget(s);
             return std::move(c.ctx);
         }
     }
@@ -358,6 +365,7 @@ void return_context(std::unique_ptr<BatchContext> ctx, hipStream_t s) {
         (void)hipGetLastError();
         (void)hipStreamSynchronize(s);
         if (ev) (void)hipEventDestroy(ev);
+        ctx->retarget(nullptr);
         return;  // drop the context
     }
     std::lock_guard<std::mutex> g(g_cache_mu);
@@ -367,6 +375,7 @@ void return_context(std::unique_ptr<BatchContext> ctx, hipStream_t s) {
         g_cache.erase(g_cache.begin());
         (void)hipEventSynchronize(old.done);
         (void)hipEventDestroy(old.done);
+        old.ctx->retarget(nullptr);  // its work is done; its stream may be gone
     }
 }
 
@@ -429,7 +438,7 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
             hand_out(*ctx, c, bo, outs);
             frnn_stats stt{};
             stt.candidates = (int64_t)c.ctr.candidates;
-            stt.work_items = c.ctr.n_items;
+            stt.work_items = c.ctr.n_groups;
             stt.pairs = (int64_t)c.ctr.nnz;
             stt.long_row_keys = (int64_t)c.ctr.long_total;
             record_stats(stt);

@@ -58,6 +58,10 @@ public:
     // 4. fill into the given output (graph B)
     void phase_b(const OutDesc &od, hipStream_t s);
 
+    // Make every buffer's stream-ordered release follow stream s (the
+    // stream of the current user, or null once the device work is done).
+    void retarget(hipStream_t s);
+
     int E() const { return E_; }
     const std::vector<int64_t> &q_off() const { return qoff_; }
     const std::vector<int64_t> &n_q() const { return nq_; }
@@ -76,7 +80,7 @@ private:
     Knobs kn_{};
     Bufs bb_{}, bq_{};  // build run and query run
     DevBuf bd_b, bd_q, ev_b, ev_q, pch, qch, ctr_b, hv, grid, cell_off, ext, xs, perm, key, rank,
-        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, items, deg, offs, lofs, lrows, part, outd;
+        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, stash, part, outd;
     Pinned stage_, back_;
     hipGraphExec_t ga_ = nullptr, gb_ = nullptr;
     hipGraph_t gra_ = nullptr, grb_ = nullptr;

@@ -70,12 +70,21 @@ struct Counters {
     uint64_t nnz;          // output pairs (after the cap)
     uint64_t long_total;   // keys of rows sorted in global memory
     uint64_t candidates;   // distance evaluations of the count pass
-    uint32_t n_items;      // work items
-    uint32_t head_count;   // work-queue heads
-    uint32_t head_fill;
+    uint32_t n_groups;     // cell-block groups evaluated by the count pass
     uint32_t n_long;       // rows sorted in global memory
     uint32_t status;       // kStatus* bits
-    uint32_t pad[7];
+    uint32_t pad[9];
+    // persistent work queues: [pass][XCD], one 64-byte line each
+    uint32_t heads[2][8][16];
+};
+
+// One neighbour key run of a work group: offsets o[a] (a = 1..G-1) of the
+// neighbour cell on the grid axes other than axis 0, and the key offset
+// sum_a o[a] * stride[a].
+struct RunEntry {
+    int32_t koff;
+    int8_t o[kGMax];
+    int8_t pad[6];
 };
 
 constexpr uint32_t kStatusNonfinitePts = 1u;
@@ -96,19 +105,11 @@ struct Knobs {
     int32_t K;             // <= 0: no cap
     int32_t self_query;    // queries are the sorted points
     int32_t exclude_self;
-    int32_t queries_per_item;
+    int32_t window;        // sorted queries per work window (divides kChunkRows)
     int32_t cells_per_item;
     int32_t long_cap;      // rows longer than this sort in global memory
     int32_t persistent;
-};
-
-// A work item: queries sorted slots [qpos, qpos + nq) of event ev, all in
-// the block of cells that starts with cell key `key`'s block.
-struct alignas(16) Item {
-    int32_t qpos;
-    int32_t nq;
-    int32_t ev;
-    uint32_t key;
+    int32_t stash_cap;     // hits per query kept by the count pass (0 = none)
 };
 
 // Device buffers of a run.
@@ -120,6 +121,7 @@ struct Bufs {
     Counters *ctr;
     int64_t *bases;        // [E+1] first output pair of each event
     GridDesc *grid;        // [E]
+    RunEntry *runs;        // [E][kRunsMax]
     int64_t *cell_off;     // [E+1]
     uint32_t *ext;         // [E][2][D] order-preserving min / max bits
     // points, concatenated over events
@@ -132,12 +134,12 @@ struct Bufs {
     float *qs;
     int32_t *qperm;
     uint32_t *qkey, *qrank, *sqkey, *qcells;
-    // work and rows
-    Item *items;
+    // rows
     uint32_t *deg;         // in-radius count per query (global row)
     int64_t *offs;         // [total_q+1] exclusive scan of capped counts
     int64_t *lofs;         // [total_q+1] exclusive scan of long-row lengths
     uint32_t *long_rows;
+    uint64_t *stash;       // [total_q][stash_cap] hit keys by sorted query slot
     uint64_t *scan_part;   // scan block partials (2 x kScanBlocks)
     OutDesc *out;
 };

@@ -296,6 +296,22 @@ __global__ void __launch_bounds__(256) k_plan(Bufs b) {
         g.C = C;
         g.runs = runs;
         b.grid[e] = g;
+        // neighbour runs: offsets in -m..m on grid axes 1..G-1 (base 2m+1
+        // digits of the run index) and their key offsets
+        for (int s = 0; s < runs; ++s) {
+            RunEntry re;
+            re.koff = 0;
+            for (int a = 0; a < kGMax; ++a) re.o[a] = 0;
+            for (int a = 0; a < 6; ++a) re.pad[a] = 0;
+            int t = s;
+            for (int a = 1; a < G; ++a) {
+                const int o = t % W - m;
+                t /= W;
+                re.o[a] = (int8_t)o;
+                re.koff += o * (int32_t)g.stride[a];
+            }
+            b.runs[(int64_t)e * kRunsMax + s] = re;
+        }
         local += C;
     }
     // exclusive scan of the cell counts over events -> cell offsets
@@ -579,78 +595,44 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Bufs b, Knobs kn) {
     }
 }
 
-// ----------------------------------------------------------- work items
-// A work item is a run of at most queries_per_item sorted queries whose
-// cells lie in one block of cells_per_item cells along grid axis 0 (same
-// coordinates on the other grid axes), so all of them share one set of
-// neighbour key runs.
-__global__ void __launch_bounds__(256) k_items(Bufs b, Knobs kn) {
-    const BatchDesc bd = *b.bd;
-    const int QB = kn.queries_per_item, R = kn.cells_per_item;
-    const uint32_t *qcells = kn.self_query ? b.cells : b.qcells;
-    const uint32_t *sqkey = kn.self_query ? b.skey : b.sqkey;
-    const int l = lane_id();
-    for (int c = blockIdx.x; c < bd.n_qchunks; c += gridDim.x) {
-        const Chunk ch = b.qchunks[c];
-        const GridDesc &g = b.grid[ch.ev];
-        const int G = g.G;
-        const int n0 = G > 0 ? g.n[0] : 1;
-        const int64_t coff = b.cell_off[ch.ev];
-        for (int64_t base = ch.r0; base < ch.r1; base += blockDim.x) {
-            const int64_t p = base + threadIdx.x;
-            bool start = false;
-            Item it{0, 0, 0, 0u};
-            if (p < ch.r1) {
-                const uint32_t k = sqkey[p];
-                const uint32_t c0 = G > 0 ? k % (uint32_t)n0 : 0u;
-                const uint32_t b0 = (c0 / R) * R;
-                const uint32_t b1 = min(b0 + R - 1, (uint32_t)n0 - 1);
-                const uint32_t kf = k - c0 + b0, kl = k - c0 + b1;
-                const int64_t rs = qcells[coff + kf], re = qcells[coff + kl + 1];
-                if ((p - rs) % QB == 0) {
-                    start = true;
-                    it = Item{(int32_t)p, (int32_t)min((int64_t)QB, re - p), ch.ev, k};
-                }
-            }
-            const uint64_t m = ballot(start);
-            if (m) {
-                const int leader = __ffsll((unsigned long long)m) - 1;
-                uint32_t at = 0;
-                if (l == leader) at = atomicAdd(&b.ctr->n_items, (uint32_t)__popcll(m));
-                at = (uint32_t)__shfl((int)at, leader);
-                if (start) b.items[at + lanes_below(m)] = it;
-            }
-        }
-    }
-}
-
 // ---------------------------------------------------- count and fill pass
 template <int DT>
 struct QueryRow {
     float q[DT];
 };
 
-// Squared distance in the canonical order: three rounded operations per
-// axis, axes 0..D-1, starting from +0.  x is a padded row in global memory.
+template <int DT>
+struct CandRow {
+    float x[(DT + 3) & ~3];
+};
+
+// Loads one padded point row (float4 pieces up to D).
 template <int DT, bool EXACT_D>
-__device__ __forceinline__ float dist2_row(const QueryRow<DT> &qr, const float *xrow, int D) {
+__device__ __forceinline__ void load_row(CandRow<DT> &c, const float *xrow, int D) {
     constexpr int DP = (DT + 3) & ~3;
-    float x[DP];
 #pragma unroll
     for (int d4 = 0; d4 < DP; d4 += 4) {
         if (EXACT_D || d4 < D) {
             float4 v = *reinterpret_cast<const float4 *>(xrow + d4);
-            x[d4] = v.x;
-            x[d4 + 1] = v.y;
-            x[d4 + 2] = v.z;
-            x[d4 + 3] = v.w;
+            c.x[d4] = v.x;
+            c.x[d4 + 1] = v.y;
+            c.x[d4 + 2] = v.z;
+            c.x[d4 + 3] = v.w;
+        } else {
+            c.x[d4] = c.x[d4 + 1] = c.x[d4 + 2] = c.x[d4 + 3] = 0.0f;
         }
     }
+}
+
+// Squared distance in the canonical order: three rounded operations per
+// axis, axes 0..D-1, starting from +0.
+template <int DT, bool EXACT_D>
+__device__ __forceinline__ float dist2(const QueryRow<DT> &qr, const CandRow<DT> &c, int D) {
     float s = 0.0f;
 #pragma unroll
     for (int d = 0; d < DT; ++d) {
         if (EXACT_D || d < D) {
-            float t = qr.q[d] - x[d];
+            float t = qr.q[d] - c.x[d];
             float u = t * t;
             s = s + u;
         }
@@ -661,10 +643,9 @@ __device__ __forceinline__ float dist2_row(const QueryRow<DT> &qr, const float *
 struct WaveLds {
     uint32_t run_base[kRunsMax];
     uint32_t run_pref[kRunsMax + 1];
-    uint32_t cand[kCandLds];
 };
 
-// Position of candidate v (0 <= v < L) among the item's concatenated runs.
+// Position of candidate v (0 <= v < L) among the group's concatenated runs.
 __device__ __forceinline__ uint32_t locate(const WaveLds &s, int nruns, uint32_t v) {
     int lo = 0, hi = nruns - 1;
     while (lo < hi) {
@@ -697,19 +678,21 @@ __device__ __forceinline__ void sort_and_write(const uint64_t *hits, uint32_t n,
     }
 }
 
-// One wave per work item.  The wave lists the item's neighbour key runs
-// (contiguous ranges of sorted points: for each offset of the grid axes
-// 1..G-1 within +-m, the cells along axis 0 from the block start - m to the
-// block end + m), then evaluates each query of the item against every
-// candidate, 64 candidates per step, one per lane.
-// Count pass: number of hits per query.  Fill pass: the hit keys
-// (dist2 bits << 32 | reference id) gathered in LDS, sorted by the register
-// bitonic network and cut to K; rows longer than long_cap go to global
-// memory for k_long_sort.
-template <int DT, bool EXACT_D, bool FILL>
+// Work assignment.  The sorted queries of each event are cut into windows
+// of kn.window consecutive slots (each chunk of kChunkRows slots holds
+// kChunkRows / window of them).  A wave evaluates one window at a time.
+// Workgroups are dispatched to the 8 XCDs round robin, so the windows are
+// remapped to give every XCD one contiguous range (neighbouring windows
+// read the same points, which then stay in that XCD's L2).
+//   plain:      one window per wave, grid covers all windows
+//   persistent: resident waves drain 8 per-XCD queues of windows, then
+//               help the other XCDs' queues
+template <int DT, bool EXACT_D, bool FILL, int KR>
 __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
     __shared__ WaveLds slds[kWavesPerBlock];
     __shared__ uint64_t shits[FILL ? kWavesPerBlock : 1][FILL ? kRowLds : 1];
+    __shared__ unsigned long long s_cand[kWavesPerBlock];
+    __shared__ uint32_t s_groups[kWavesPerBlock];
     constexpr int DP = (DT + 3) & ~3;
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
@@ -717,163 +700,313 @@ __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
     const BatchDesc &bd = *b.bd;
     const int D = EXACT_D ? DT : bd.D;
     const int Dp = EXACT_D ? DP : bd.Dp;
-    const uint32_t n_items = uniform(b.ctr->n_items);
     const float r2 = kn.r2;
     const uint32_t *cells = b.cells;
+    const uint32_t *qcells = kn.self_query ? b.cells : b.qcells;
+    const uint32_t *sqkey = kn.self_query ? b.skey : b.sqkey;
     const float *qs = kn.self_query ? b.xs : b.qs;
     const int32_t *qperm = kn.self_query ? b.perm : b.qperm;
     int32_t *out_idx = nullptr;
     float *out_d2 = nullptr;
+    uint64_t *long_keys = nullptr;
     if (FILL) {
         out_idx = b.out->indices;
         out_d2 = b.out->dist2;
+        long_keys = b.out->long_keys;
     }
+    const int Wn = kn.window;
+    const uint32_t wpc = kChunkRows / Wn;
+    const uint32_t nwin = (uint32_t)bd.n_qchunks * wpc;
     uint64_t my_cand = 0;
-    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    uint32_t it = blockIdx.x * kWavesPerBlock + w;
-    for (;;) {
-        if (kn.persistent) {
-            uint32_t v = 0;
-            if (lane == 0) v = atomicAdd(FILL ? &b.ctr->head_fill : &b.ctr->head_count, 1u);
-            it = uniform((uint32_t)__shfl((int)v, 0));
-        }
-        if (it >= n_items) break;
-        const Item item = b.items[it];
-        if (!kn.persistent) it += nwaves;
-        const uint32_t qp0 = uniform((uint32_t)item.qpos);
-        const int nq = (int)uniform((uint32_t)item.nq);
-        const int e = (int)uniform((uint32_t)item.ev);
-        const uint32_t key = uniform(item.key);
+    uint32_t my_groups = 0;
+
+    auto process_window = [&](uint32_t wid) {
+        const uint32_t c = wid / wpc, sub = wid % wpc;
+        if (c >= (uint32_t)bd.n_qchunks) return;
+        const Chunk ch = b.qchunks[c];
+        int64_t p = ch.r0 + (int64_t)sub * Wn;
+        const int64_t pend = min(ch.r1, p + Wn);
+        const int e = ch.ev;
         const GridDesc &g = b.grid[e];
-        const int G = g.G, m = g.m, W = 2 * m + 1, runs = g.runs;
+        const int G = g.G, m = g.m, runs = g.runs;
         const int64_t coff = b.cell_off[e];
         const int64_t q_off = b.ev[e].q_off;
-        // grid coordinates of the item's first cell
-        int c[kGMax] = {0, 0, 0, 0, 0, 0};
-        {
-            uint32_t rem = key;
+        const RunEntry *rtab = b.runs + (int64_t)e * kRunsMax;
+        while (p < pend) {
+            // the group: this window's queries in the cell block of slot p
+            const uint32_t key = uniform(sqkey[p]);
+            int c_[kGMax] = {0, 0, 0, 0, 0, 0};
+            {
+                uint32_t rem = key;
 #pragma unroll
-            for (int a = 0; a < kGMax; ++a) {
-                if (a < G) {
-                    c[a] = (int)(rem % (uint32_t)g.n[a]);
-                    rem /= (uint32_t)g.n[a];
-                }
-            }
-        }
-        int lo0 = 0, hi0 = 0;
-        if (G > 0) {
-            const int R = kn.cells_per_item;
-            const int b0 = (c[0] / R) * R;
-            lo0 = max(b0 - m, 0);
-            hi0 = min(b0 + R - 1 + m, g.n[0] - 1);
-        }
-        // neighbour key runs, empty ones dropped
-        uint32_t total = 0;
-        int nruns = 0;
-        for (int s0 = 0; s0 < runs; s0 += 64) {
-            const int s = s0 + lane;
-            uint32_t start = 0, len = 0;
-            if (s < runs) {
-                int t = s;
-                bool ok = true;
-                uint32_t kk = 0;
-#pragma unroll
-                for (int a = 1; a < kGMax; ++a) {
+                for (int a = 0; a < kGMax; ++a) {
                     if (a < G) {
-                        const int ca = c[a] + (t % W) - m;
-                        t /= W;
-                        ok = ok && ca >= 0 && ca < g.n[a];
-                        kk += (uint32_t)ca * g.stride[a];
+                        c_[a] = (int)(rem % (uint32_t)g.n[a]);
+                        rem /= (uint32_t)g.n[a];
                     }
                 }
-                if (ok) {
-                    start = cells[coff + kk + lo0];
-                    len = cells[coff + kk + hi0 + 1] - start;
+            }
+            int lo0 = 0, hi0 = 0;
+            uint32_t kbase = key;  // key of the group's row with c0 = 0
+            int64_t gend = pend;
+            if (G > 0) {
+                const int R = kn.cells_per_item;
+                const int b0 = (c_[0] / R) * R;
+                const int b1 = min(b0 + R - 1, g.n[0] - 1);
+                kbase = key - (uint32_t)c_[0];
+                lo0 = max(b0 - m, 0);
+                hi0 = min(b1 + m, g.n[0] - 1);
+                gend = min(pend, (int64_t)qcells[coff + kbase + b1 + 1]);
+            } else {
+                gend = pend;
+            }
+            const int64_t gbeg = p;
+            p = gend;
+            ++my_groups;
+            if (FILL && kn.stash_cap > 0) {
+                bool any = false;
+                for (int64_t q0 = gbeg; q0 < gend; q0 += 64) {
+                    bool need = false;
+                    if (q0 + lane < gend) need = b.deg[q_off + qperm[q0 + lane]] > (uint32_t)kn.stash_cap;
+                    any = any || ballot(need) != 0;
+                }
+                if (!any) continue;
+            }
+            // neighbour key runs, empty ones dropped
+            uint32_t total = 0;
+            int nruns = 0;
+            for (int s0 = 0; s0 < runs; s0 += 64) {
+                const int s = s0 + lane;
+                uint32_t start = 0, len = 0;
+                if (s < runs) {
+                    const RunEntry re = rtab[s];
+                    bool ok = true;
+#pragma unroll
+                    for (int a = 1; a < kGMax; ++a) {
+                        if (a < G) {
+                            const int ca = c_[a] + re.o[a];
+                            ok = ok && ca >= 0 && ca < g.n[a];
+                        }
+                    }
+                    if (ok) {
+                        const int64_t k0 = coff + (int64_t)kbase + re.koff;
+                        start = cells[k0 + lo0];
+                        len = cells[k0 + hi0 + 1] - start;
+                    }
+                }
+                const uint64_t nz = ballot(len > 0);
+                const uint32_t inc = wave_incl_scan(len);
+                if (len > 0) {
+                    const int at = nruns + (int)lanes_below(nz);
+                    L.run_base[at] = start;
+                    L.run_pref[at] = total + inc - len;
+                }
+                total += uniform((uint32_t)__shfl((int)inc, 63));
+                nruns += __popcll(nz);
+            }
+            if (lane == 0) L.run_pref[nruns] = total;
+            wave_lds_sync();
+            // the first KR*64 candidates stay in registers for every query
+            CandRow<DT> xr[KR];
+            uint32_t pr[KR];
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const uint32_t v = k * 64 + lane;
+                pr[k] = 0;
+                if (k * 64 < (int)total) {
+                    pr[k] = v < total ? locate(L, nruns, v) : 0u;
+                    load_row<DT, EXACT_D>(xr[k], b.xs + (int64_t)pr[k] * Dp, D);
                 }
             }
-            const uint64_t nz = ballot(len > 0);
-            const uint32_t inc = wave_incl_scan(len);
-            if (len > 0) {
-                const int at = nruns + (int)lanes_below(nz);
-                L.run_base[at] = start;
-                L.run_pref[at] = total + inc - len;
+            for (int64_t qp = gbeg; qp < gend; ++qp) {
+                QueryRow<DT> qr;
+                const float *qrow = qs + qp * Dp;
+#pragma unroll
+                for (int d = 0; d < DT; ++d) qr.q[d] = (EXACT_D || d < D) ? qrow[d] : 0.0f;
+                const int64_t qid = q_off + qperm[qp];
+                if (!FILL) {
+                    // count; the first stash_cap hit keys are kept for the fill
+                    uint32_t cnt = 0;
+                    const uint32_t SC = (uint32_t)kn.stash_cap;
+                    uint64_t *st = b.stash + qp * SC;
+                    auto tally = [&](bool hit, float s, uint32_t pos) {
+                        const uint64_t hm = ballot(hit);
+                        if (hit) {
+                            const uint32_t slot = cnt + lanes_below(hm);
+                            if (slot < SC)
+                                st[slot] = ((uint64_t)__float_as_uint(s) << 32) | (uint32_t)b.perm[pos];
+                        }
+                        cnt += (uint32_t)__popcll(hm);
+                    };
+#pragma unroll
+                    for (int k = 0; k < KR; ++k) {
+                        if (k * 64 < (int)total) {
+                            const float s = dist2<DT, EXACT_D>(qr, xr[k], D);
+                            const bool hit = (k * 64 + lane < (int)total) && s <= r2 &&
+                                             !(kn.exclude_self && pr[k] == (uint32_t)qp);
+                            tally(hit, s, pr[k]);
+                        }
+                    }
+                    for (uint32_t v0 = KR * 64; v0 < total; v0 += 64) {
+                        const uint32_t v = v0 + lane;
+                        const bool valid = v < total;
+                        const uint32_t pos = valid ? locate(L, nruns, v) : 0u;
+                        CandRow<DT> x;
+                        load_row<DT, EXACT_D>(x, b.xs + (int64_t)pos * Dp, D);
+                        const float s = dist2<DT, EXACT_D>(qr, x, D);
+                        const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == (uint32_t)qp);
+                        tally(hit, s, pos);
+                    }
+                    if (lane == 0) b.deg[qid] = cnt;
+                    my_cand += total;
+                } else {
+                    const uint32_t dq = b.deg[qid];
+                    if (dq <= (uint32_t)kn.stash_cap) continue;  // sorted from the stash
+                    const int64_t off = b.offs[qid];
+                    const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
+                    const bool lng = dq > (uint32_t)kn.long_cap;
+                    uint64_t *dst = lng ? long_keys + b.lofs[qid] : &shits[w][0];
+                    uint32_t nh = 0;
+                    auto emit = [&](bool hit, float s, uint32_t pos) {
+                        const uint64_t hm = ballot(hit);
+                        if (hit) {
+                            const uint32_t slot = nh + lanes_below(hm);
+                            const uint32_t j = (uint32_t)b.perm[pos];  // original id, hits only
+                            if (slot < dq) dst[slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                        }
+                        nh += (uint32_t)__popcll(hm);
+                    };
+#pragma unroll
+                    for (int k = 0; k < KR; ++k) {
+                        if (k * 64 < (int)total) {
+                            const float s = dist2<DT, EXACT_D>(qr, xr[k], D);
+                            const bool hit = (k * 64 + lane < (int)total) && s <= r2 &&
+                                             !(kn.exclude_self && pr[k] == (uint32_t)qp);
+                            emit(hit, s, pr[k]);
+                        }
+                    }
+                    for (uint32_t v0 = KR * 64; v0 < total; v0 += 64) {
+                        const uint32_t v = v0 + lane;
+                        const bool valid = v < total;
+                        const uint32_t pos = valid ? locate(L, nruns, v) : 0u;
+                        CandRow<DT> x;
+                        load_row<DT, EXACT_D>(x, b.xs + (int64_t)pos * Dp, D);
+                        const float s = dist2<DT, EXACT_D>(qr, x, D);
+                        const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == (uint32_t)qp);
+                        emit(hit, s, pos);
+                    }
+                    if (nh != dq && lane == 0) atomicOr(&b.ctr->status, kStatusInternal);
+                    if (lng) {
+                        if (lane == 0) {
+                            const uint32_t li = atomicAdd(&b.ctr->n_long, 1u);
+                            b.long_rows[li] = (uint32_t)qid;
+                        }
+                        continue;
+                    }
+                    wave_lds_sync();
+                    int32_t *oi = out_idx + off;
+                    float *od = out_d2 ? out_d2 + off : nullptr;
+                    if (dq <= 64)
+                        sort_and_write<1>(&shits[w][0], dq, keep, oi, od, lane);
+                    else if (dq <= 128)
+                        sort_and_write<2>(&shits[w][0], dq, keep, oi, od, lane);
+                    else if (dq <= 256)
+                        sort_and_write<4>(&shits[w][0], dq, keep, oi, od, lane);
+                    else
+                        sort_and_write<8>(&shits[w][0], dq, keep, oi, od, lane);
+                    wave_lds_sync();
+                }
             }
-            total += uniform((uint32_t)__shfl((int)inc, 63));
-            nruns += __popcll(nz);
-        }
-        if (lane == 0) L.run_pref[nruns] = total;
-        wave_lds_sync();
-        const bool listed = total <= (uint32_t)kCandLds;
-        if (listed) {
-            for (uint32_t v = lane; v < total; v += 64) L.cand[v] = locate(L, nruns, v);
             wave_lds_sync();
         }
-        for (int t = 0; t < nq; ++t) {
-            const uint32_t qp = qp0 + t;
-            QueryRow<DT> qr;
-            const float *qrow = qs + (int64_t)qp * Dp;
-#pragma unroll
-            for (int d = 0; d < DT; ++d) qr.q[d] = (EXACT_D || d < D) ? qrow[d] : 0.0f;
-            const int64_t qid = q_off + qperm[qp];
-            if (!FILL) {
-                uint32_t cnt = 0;
-                for (uint32_t v0 = 0; v0 < total; v0 += 64) {
-                    const uint32_t v = v0 + lane;
-                    const bool valid = v < total;
-                    const uint32_t pos = valid ? (listed ? L.cand[v] : locate(L, nruns, v)) : 0u;
-                    const float s = dist2_row<DT, EXACT_D>(qr, b.xs + (int64_t)pos * Dp, D);
-                    const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == qp);
-                    cnt += (uint32_t)__popcll(ballot(hit));
-                }
-                if (lane == 0) b.deg[qid] = cnt;
-                my_cand += total;
-            } else {
-                const uint32_t dq = b.deg[qid];
-                if (dq == 0) continue;
-                const int64_t off = b.offs[qid];
-                const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
-                const bool lng = dq > (uint32_t)kn.long_cap;
-                uint64_t *dst = lng ? b.out->long_keys + b.lofs[qid] : &shits[w][0];
-                uint32_t nh = 0;
-                for (uint32_t v0 = 0; v0 < total; v0 += 64) {
-                    const uint32_t v = v0 + lane;
-                    const bool valid = v < total;
-                    const uint32_t pos = valid ? (listed ? L.cand[v] : locate(L, nruns, v)) : 0u;
-                    const float s = dist2_row<DT, EXACT_D>(qr, b.xs + (int64_t)pos * Dp, D);
-                    const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == qp);
-                    const uint64_t hm = ballot(hit);
-                    if (hit) {
-                        const uint32_t slot = nh + lanes_below(hm);
-                        const uint32_t j = (uint32_t)b.perm[pos];  // original id, hits only
-                        if (slot < dq) dst[slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
-                    }
-                    nh += (uint32_t)__popcll(hm);
-                }
-                if (nh != dq && lane == 0) atomicOr(&b.ctr->status, kStatusInternal);
-                if (lng) {
-                    if (lane == 0) {
-                        const uint32_t li = atomicAdd(&b.ctr->n_long, 1u);
-                        b.long_rows[li] = (uint32_t)qid;
-                    }
-                    continue;
-                }
-                wave_lds_sync();
-                int32_t *oi = out_idx + off;
-                float *od = out_d2 ? out_d2 + off : nullptr;
-                if (dq <= 64)
-                    sort_and_write<1>(&shits[w][0], dq, keep, oi, od, lane);
-                else if (dq <= 128)
-                    sort_and_write<2>(&shits[w][0], dq, keep, oi, od, lane);
-                else if (dq <= 256)
-                    sort_and_write<4>(&shits[w][0], dq, keep, oi, od, lane);
-                else
-                    sort_and_write<8>(&shits[w][0], dq, keep, oi, od, lane);
-                wave_lds_sync();
+    };
+
+    if (kn.persistent) {
+        const int pass = FILL ? 1 : 0;
+        const int x0 = blockIdx.x & 7;
+        for (int qx = 0; qx < 8; ++qx) {
+            const int x = (x0 + qx) & 7;
+            const uint32_t lo = (uint32_t)((uint64_t)nwin * x / 8);
+            const uint32_t hi = (uint32_t)((uint64_t)nwin * (x + 1) / 8);
+            uint32_t *head = &b.ctr->heads[pass][x][0];
+            for (;;) {
+                // a plain read first: a drained queue needs no atomic
+                if (lo + uniform(__atomic_load_n(head, __ATOMIC_RELAXED)) >= hi) break;
+                uint32_t v = 0;
+                if (lane == 0) v = atomicAdd(head, 1u);
+                v = uniform((uint32_t)__shfl((int)v, 0));
+                if (lo + v >= hi) break;
+                process_window(lo + v);
             }
         }
-        wave_lds_sync();
+    } else {
+        const uint32_t nb = gridDim.x, per = nb / 8;  // grid is a multiple of 8 blocks
+        const uint32_t vb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+        const uint32_t wid = vb * kWavesPerBlock + w;
+        if (wid < nwin) process_window(wid);
     }
-    if (!FILL && lane == 0 && my_cand) atomicAdd((unsigned long long *)&b.ctr->candidates, (unsigned long long)my_cand);
+    // one atomic per workgroup for the work counters
+    if (!FILL) {
+        if (lane == 0) {
+            s_cand[w] = my_cand;
+            s_groups[w] = my_groups;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long c = 0;
+            uint32_t gsum = 0;
+            for (int i = 0; i < kWavesPerBlock; ++i) {
+                c += s_cand[i];
+                gsum += s_groups[i];
+            }
+            if (c) atomicAdd((unsigned long long *)&b.ctr->candidates, c);
+            if (gsum) atomicAdd(&b.ctr->n_groups, gsum);
+        }
+    }
+}
+
+// ------------------------------------------------------------ stashed rows
+// Rows whose length is at most SC were kept whole by the count pass: each
+// group of SC lanes sorts one row with the bitonic network and writes its
+// first min(deg, K) entries.
+template <int SC>
+__global__ void __launch_bounds__(256) k_stash_sort(Bufs b, Knobs kn) {
+    const BatchDesc &bd = *b.bd;
+    const int32_t *qperm = kn.self_query ? b.perm : b.qperm;
+    const int lane = lane_id();
+    const int gl = threadIdx.x % SC;          // lane within the row's group
+    constexpr int per = 256 / SC;             // rows per block step
+    for (int c = blockIdx.x; c < bd.n_qchunks; c += gridDim.x) {
+        const Chunk ch = b.qchunks[c];
+        const int64_t q_off = b.ev[ch.ev].q_off;
+        for (int64_t base = ch.r0; base < ch.r1; base += per) {
+            const int64_t qp = base + threadIdx.x / SC;
+            uint32_t dq = 0;
+            int64_t qid = 0;
+            if (qp < ch.r1) {
+                qid = q_off + qperm[qp];
+                dq = b.deg[qid];
+            }
+            const bool mine = dq > 0 && dq <= (uint32_t)SC;
+            uint64_t v = (mine && gl < (int)dq) ? b.stash[qp * SC + gl] : ~0ull;
+#pragma unroll
+            for (int k = 2; k <= SC; k <<= 1) {
+                uint64_t o = shfl_xor64(v, k - 1);
+                v = (lane & (k >> 1)) == 0 ? umin64(v, o) : umax64(v, o);
+#pragma unroll
+                for (int j = k >> 2; j >= 1; j >>= 1) {
+                    o = shfl_xor64(v, j);
+                    v = (lane & j) == 0 ? umin64(v, o) : umax64(v, o);
+                }
+            }
+            const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
+            if (mine && gl < (int)keep) {
+                const int64_t off = b.offs[qid] + gl;
+                b.out->indices[off] = (int32_t)(uint32_t)v;
+                if (b.out->dist2) b.out->dist2[off] = __uint_as_float((uint32_t)(v >> 32));
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------ long rows
@@ -1032,27 +1165,21 @@ hipError_t launch_scan_rows(const Bufs &b, const Knobs &kn, int64_t total_q, hip
     return launch_scan_mode<kScanRows>(b, kn, total_q + 1, s);
 }
 
-hipError_t launch_items(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s) {
-    if (nqchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_items, dim3(std::min(nqchunks, 8192)), dim3(256), 0, s, b, kn);
-    FRNN_CHECK_LAUNCH();
-    return hipSuccess;
-}
-
 template <bool FILL>
 static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
+    blocks = (blocks + 7) / 8 * 8;  // whole XCD rounds (see the window remap)
     dim3 grid(blocks), block(64 * kWavesPerBlock);
     switch (D) {
-    case 3: hipLaunchKernelGGL((k_query<3, true, FILL>), grid, block, 0, s, b, kn); break;
-    case 8: hipLaunchKernelGGL((k_query<8, true, FILL>), grid, block, 0, s, b, kn); break;
-    case 12: hipLaunchKernelGGL((k_query<12, true, FILL>), grid, block, 0, s, b, kn); break;
+    case 3: hipLaunchKernelGGL((k_query<3, true, FILL, 4>), grid, block, 0, s, b, kn); break;
+    case 8: hipLaunchKernelGGL((k_query<8, true, FILL, 4>), grid, block, 0, s, b, kn); break;
+    case 12: hipLaunchKernelGGL((k_query<12, true, FILL, 4>), grid, block, 0, s, b, kn); break;
     default:
         if (D <= 4)
-            hipLaunchKernelGGL((k_query<4, false, FILL>), grid, block, 0, s, b, kn);
+            hipLaunchKernelGGL((k_query<4, false, FILL, 4>), grid, block, 0, s, b, kn);
         else if (D <= 16)
-            hipLaunchKernelGGL((k_query<16, false, FILL>), grid, block, 0, s, b, kn);
+            hipLaunchKernelGGL((k_query<16, false, FILL, 2>), grid, block, 0, s, b, kn);
         else
-            hipLaunchKernelGGL((k_query<32, false, FILL>), grid, block, 0, s, b, kn);
+            hipLaunchKernelGGL((k_query<32, false, FILL, 1>), grid, block, 0, s, b, kn);
     }
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
@@ -1064,6 +1191,19 @@ hipError_t launch_count(const Bufs &b, const Knobs &kn, int D, int blocks, hipSt
 
 hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
     return launch_query_t<true>(b, kn, D, blocks, s);
+}
+
+hipError_t launch_stash_sort(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s) {
+    dim3 grid(std::max(1, std::min(nqchunks, 8192))), block(256);
+    switch (kn.stash_cap) {
+    case 0: return hipSuccess;
+    case 8: hipLaunchKernelGGL(k_stash_sort<8>, grid, block, 0, s, b, kn); break;
+    case 16: hipLaunchKernelGGL(k_stash_sort<16>, grid, block, 0, s, b, kn); break;
+    case 32: hipLaunchKernelGGL(k_stash_sort<32>, grid, block, 0, s, b, kn); break;
+    default: return hipErrorInvalidValue;
+    }
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
 }
 
 hipError_t launch_bases(const Bufs &b, int E, hipStream_t s) {

@@ -16,10 +16,12 @@ hipError_t launch_zero_cells(const Bufs &b, int64_t cells_cap, bool queries, hip
 hipError_t launch_keys(const Bufs &b, int nchunks, bool queries, hipStream_t s);
 hipError_t launch_scan_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s);
 hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t s);
-hipError_t launch_items(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s);
+// blocks: plain mode, enough for every window (rounded up to a multiple of
+// 8); persistent mode, the resident grid.
 hipError_t launch_count(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
 hipError_t launch_scan_rows(const Bufs &b, const Knobs &kn, int64_t total_q, hipStream_t s);
 hipError_t launch_bases(const Bufs &b, int E, hipStream_t s);
+hipError_t launch_stash_sort(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s);
 hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
 hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStream_t s);
 hipError_t launch_finalize(const Bufs &b, int nqchunks, hipStream_t s);

@@ -172,8 +172,9 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 std::atomic<bool> g_prof_on{false};
-std::vector<ProfRec> g_prof_pending;
-std::map<std::string, std::pair<int64_t, double>> g_prof_total;
+std::vector<ProfRec> &g_prof_pending = *new std::vector<ProfRec>();
+std::map<std::string, std::pair<int64_t, double>> &g_prof_total =
+    *new std::map<std::string, std::pair<int64_t, double>>();
 thread_local ProfRec t_open{"", nullptr, nullptr};
 }  // namespace
 
@@ -253,15 +254,20 @@ frnn_status Opts::validate(std::string *why) const {
     if (!(o.cells_per_point > 0.f) || !std::isfinite(o.cells_per_point)) return bad("cells_per_point must be > 0");
     if (o.cell_multiple < 1 || o.cell_multiple > 3) return bad("cell_multiple out of 1..3");
     if (o.cells_per_item < 1 || o.cells_per_item > 8) return bad("cells_per_item out of 1..8");
-    if (o.queries_per_item < 1 || o.queries_per_item > 64) return bad("queries_per_item out of 1..64");
+    if (o.queries_per_item < 1 || o.queries_per_item > 256 || (o.queries_per_item & (o.queries_per_item - 1)))
+        return bad("queries_per_item must be a power of two in 1..256");
     if (o.blocks_per_cu < 1 || o.blocks_per_cu > 16) return bad("blocks_per_cu out of 1..16");
     if (o.row_cap_lds < 1 || o.row_cap_lds > kRowLds) return bad("row_cap_lds out of 1..512");
+    if (o.stash_cap != 0 && o.stash_cap != 8 && o.stash_cap != 16 && o.stash_cap != 32)
+        return bad("stash_cap must be 0, 8, 16 or 32");
     return FRNN_OK;
 }
 
 // ------------------------------------------------------------- pipeline
 static thread_local bool t_capturing = false;
-static thread_local Pinned t_stage, t_back;
+// never freed: thread-local destructors may run after the HIP runtime is gone
+static thread_local Pinned &t_stage = *new Pinned();
+static thread_local Pinned &t_back = *new Pinned();
 
 void set_capturing(bool on) { t_capturing = on; }
 bool capturing() { return t_capturing; }
@@ -282,10 +288,12 @@ static int64_t cell_cap_of(int64_t n, float cpp) {
     return (int64_t)c;
 }
 
-static int query_blocks(const Opts &o, int64_t total_q) {
-    int64_t cap = (int64_t)256 * o.o.blocks_per_cu;
-    int64_t need = (total_q + kWavesPerBlock - 1) / kWavesPerBlock;
-    return (int)std::max<int64_t>(1, std::min(cap, need));
+// Workgroups of the count and fill kernels: the resident grid when
+// persistent, else one wave per window of sorted queries.
+int query_blocks(const frnn_opts &o, int64_t nqchunks) {
+    if (o.persistent) return 256 * o.blocks_per_cu;
+    const int64_t windows = nqchunks * (kChunkRows / o.queries_per_item);
+    return (int)std::max<int64_t>(8, (windows + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
 frnn_status build_index(Index &ix, const float *const *points, const int64_t *n, int E, int D,
@@ -339,6 +347,7 @@ frnn_status build_index(Index &ix, const float *const *points, const int64_t *n,
     ix.ev.reset(sizeof(EventDev) * E, s);
     ix.pchunks.reset(sizeof(Chunk) * std::max<size_t>(1, ch.size()), s);
     ix.grid.reset(sizeof(GridDesc) * E, s);
+    ix.runs.reset(sizeof(RunEntry) * kRunsMax * E, s);
     ix.cell_off.reset(sizeof(int64_t) * (E + 1), s);
     ix.ext.reset(sizeof(uint32_t) * 2 * E * D, s);
     ix.xs.reset(sizeof(float) * std::max<int64_t>(1, tot) * ix.Dp, s);
@@ -361,6 +370,7 @@ frnn_status build_index(Index &ix, const float *const *points, const int64_t *n,
     b.pchunks = ix.pchunks.as<Chunk>();
     b.ctr = ix.ctr.as<Counters>();
     b.grid = ix.grid.as<GridDesc>();
+    b.runs = ix.runs.as<RunEntry>();
     b.cell_off = ix.cell_off.as<int64_t>();
     b.ext = ix.ext.as<uint32_t>();
     b.xs = ix.xs.as<float>();
@@ -442,9 +452,10 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     DevBuf dbd(sizeof(BatchDesc), s), dev(sizeof(EventDev) * E, s),
         dqch(sizeof(Chunk) * std::max<size_t>(1, qch.size()), s);
     DevBuf hv(sizeof(Counters) + sizeof(int64_t) * (E + 1), s);
-    DevBuf items(sizeof(Item) * tq1, s), deg(sizeof(uint32_t) * tq1, s),
+    DevBuf deg(sizeof(uint32_t) * tq1, s),
         offs(sizeof(int64_t) * (tq1 + 1), s), lofs(sizeof(int64_t) * (tq1 + 1), s),
         lrows(sizeof(uint32_t) * tq1, s), part(sizeof(uint64_t) * 2 * kScanBlocks, s),
+        stash(sizeof(uint64_t) * tq1 * std::max(1, op.o.stash_cap), s),
         outd(sizeof(OutDesc), s);
     DevBuf qs, qperm, qkey, qrank, sqkey, qcells;
     if (!selfq) {
@@ -468,6 +479,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     b.ctr = hv.as<Counters>();
     b.bases = reinterpret_cast<int64_t *>(hv.as<char>() + sizeof(Counters));
     b.grid = ix.grid.as<GridDesc>();
+    b.runs = ix.runs.as<RunEntry>();
     b.cell_off = ix.cell_off.as<int64_t>();
     b.ext = ix.ext.as<uint32_t>();
     b.xs = ix.xs.as<float>();
@@ -480,11 +492,11 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     b.qrank = qrank.as<uint32_t>();
     b.sqkey = selfq ? ix.skey.as<uint32_t>() : sqkey.as<uint32_t>();
     b.qcells = selfq ? ix.cells.as<uint32_t>() : qcells.as<uint32_t>();
-    b.items = items.as<Item>();
     b.deg = deg.as<uint32_t>();
     b.offs = offs.as<int64_t>();
     b.lofs = lofs.as<int64_t>();
     b.long_rows = lrows.as<uint32_t>();
+    b.stash = stash.as<uint64_t>();
     b.scan_part = part.as<uint64_t>();
     b.out = outd.as<OutDesc>();
 
@@ -493,11 +505,12 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     kn.K = qa.K;
     kn.self_query = selfq;
     kn.exclude_self = excl;
-    kn.queries_per_item = op.o.queries_per_item;
+    kn.window = op.o.queries_per_item;
     kn.cells_per_item = op.o.cells_per_item;
     kn.long_cap = op.o.row_cap_lds;
     kn.persistent = op.o.persistent;
-    const int qblocks = query_blocks(op, totq);
+    kn.stash_cap = op.o.stash_cap;
+    const int qblocks = query_blocks(op.o, nqc);
 
     LAUNCH("init", s, launch_init(b, E, D, false, s));
     if (!selfq) {
@@ -507,7 +520,6 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
         LAUNCH("scan_cells_q", s, launch_scan_cells(b, ix.cells_cap, true, s));
         LAUNCH("scatter_q", s, launch_scatter(b, nqc, true, s));
     }
-    LAUNCH("items", s, launch_items(b, kn, nqc, s));
     LAUNCH("count", s, launch_count(b, kn, D, qblocks, s));
     LAUNCH("scan_rows", s, launch_scan_rows(b, kn, totq, s));
     LAUNCH("bases", s, launch_bases(b, E, s));
@@ -544,6 +556,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     OutDesc od{reinterpret_cast<int64_t *>(ob), reinterpret_cast<int32_t *>(ob + b_off),
                want_d2 ? reinterpret_cast<float *>(ob + b_off + b_idx) : nullptr, lkeys.as<uint64_t>()};
     LAUNCH("set_out", s, launch_set_out(b.out, od, s));
+    LAUNCH("stash_sort", s, launch_stash_sort(b, kn, nqc, s));
     LAUNCH("fill", s, launch_fill(b, kn, D, qblocks, s));
     if (c.long_total) LAUNCH("long_sort", s, launch_long_sort(b, kn, 256, s));
     LAUNCH("finalize", s, launch_finalize(b, nqc, s));
@@ -560,7 +573,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     }
     frnn_stats st{};
     st.candidates = (int64_t)c.candidates;
-    st.work_items = c.n_items;
+    st.work_items = c.n_groups;
     st.pairs = nnz;
     st.long_row_keys = (int64_t)c.long_total;
     if (stats) *stats = st;

@@ -142,7 +142,7 @@ struct Index {
     int n_pchunks = 0;
     std::vector<int64_t> n_pts, pt_off;
     std::vector<const float *> pts;
-    DevBuf bd, ev, pchunks, grid, cell_off, ext, xs, perm, skey, cells, ctr;
+    DevBuf bd, ev, pchunks, grid, runs, cell_off, ext, xs, perm, skey, cells, ctr;
     std::vector<GridDesc> grid_host;  // valid after a synchronised build
     Pinned stage;                     // descriptor staging of the build copies
     hipStream_t stream = nullptr;
@@ -183,6 +183,7 @@ void prof_set(bool on);
 int prof_read(frnn_kernel_time *out, int cap, bool reset);
 
 float r2_of(float r);
+int query_blocks(const frnn_opts &o, int64_t nqchunks);
 
 // Graph capture in progress on this thread (per-launch timing is skipped).
 void set_capturing(bool on);

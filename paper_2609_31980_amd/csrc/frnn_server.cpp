@@ -8,7 +8,8 @@
 // stream while earlier batches are still being filled on others.  After the
 // count pass the batch's exact output size is known; it is reserved against
 // the budget (waiting for releases if needed) before the fill.  Output bytes
-// stay charged until the client releases the result.
+// stay charged until the client releases the result.  The ledger's rules
+// (frnn_sched.h) keep this free of deadlock.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -18,6 +19,7 @@
 #include <deque>
 #include <functional>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -25,6 +27,7 @@
 
 #include "frnn_batch.h"
 #include "frnn_runtime.h"
+#include "frnn_sched.h"
 
 using namespace frnn;
 
@@ -34,24 +37,6 @@ double now_s() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
-
-struct Budget {
-    std::mutex mu;
-    std::condition_variable cv;
-    int64_t limit = 0, used = 0, peak = 0;
-    void add(int64_t b) {
-        std::lock_guard<std::mutex> g(mu);
-        used += b;
-        peak = std::max(peak, used);
-    }
-    void sub(int64_t b) {
-        {
-            std::lock_guard<std::mutex> g(mu);
-            used -= b;
-        }
-        cv.notify_all();
-    }
-};
 
 struct Request {
     uint64_t ticket = 0;
@@ -70,7 +55,7 @@ struct Request {
 struct frnn_server_s {
     frnn_server_opts o{};
     Opts opts;
-    std::shared_ptr<Budget> budget = std::make_shared<Budget>();
+    std::shared_ptr<BudgetLedger> budget;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Request>> queue;
@@ -102,25 +87,24 @@ void frnn_server_s::worker(int id) {
             cv_work.wait(lk, [&] { return stop || !queue.empty(); });
             if (stop && queue.empty()) break;
             // admit in arrival order while the pre-count footprint fits
-            while (!queue.empty() && (int)batch.size() < o.max_batch_events) {
-                auto &r = queue.front();
-                std::unique_lock<std::mutex> bl(budget->mu);
-                if (budget->used + r->precount > budget->limit) break;
-                budget->used += r->precount;
-                budget->peak = std::max(budget->peak, budget->used);
-                bl.unlock();
-                r->tm.admit_s = now_s();
-                batch.push_back(r);
-                queue.pop_front();
-            }
-            if (batch.empty()) {
+            std::vector<int64_t> pre;
+            for (size_t i = 0; i < queue.size() && (int)i < o.max_batch_events; ++i)
+                pre.push_back(queue[i]->precount);
+            const int k = budget->admit(pre.data(), (int)pre.size(), o.max_batch_events);
+            if (k == 0) {
                 // over budget: wait for a release, then try again
                 lk.unlock();
-                std::unique_lock<std::mutex> bl(budget->mu);
-                budget->cv.wait_for(bl, std::chrono::milliseconds(2));
+                budget->wait_release(0.002);
                 continue;
             }
+            const double ta = now_s();
+            for (int i = 0; i < k; ++i) {
+                queue.front()->tm.admit_s = ta;
+                batch.push_back(queue.front());
+                queue.pop_front();
+            }
             bid = next_batch++;
+            budget->begin(bid);
             if (!queue.empty()) cv_work.notify_one();
         }
         const int E = (int)batch.size();
@@ -156,20 +140,24 @@ void frnn_server_s::worker(int id) {
                 const int64_t outb = (int64_t)sizeof(int64_t) * (ctx->total_q() + E) +
                                      (int64_t)c.ctr.nnz * (want_d2 ? 8 : 4) +
                                      (int64_t)c.ctr.long_total * 8 + 512;
-                {
-                    std::unique_lock<std::mutex> bl(budget->mu);
-                    if (outb > budget->limit) throw Fail{FRNN_ERR_BUDGET, "batch output exceeds the budget"};
-                    const bool ok = budget->cv.wait_for(bl, std::chrono::seconds(30), [&] {
-                        return budget->used + outb <= budget->limit;
-                    });
-                    if (!ok) throw Fail{FRNN_ERR_BUDGET, "timed out waiting for budget"};
-                    budget->used += outb;
-                    budget->peak = std::max(budget->peak, budget->used);
+                if (outb > budget->limit()) throw Fail{FRNN_ERR_BUDGET, "batch output exceeds the budget"};
+                if (!budget->reserve_output(bid, outb, 30.0))
+                    throw Fail{FRNN_ERR_BUDGET, "timed out waiting for budget"};
+                BatchOutput bo;
+                try {
+                    bo = alloc_output(*ctx, c, want_d2, s);
+                } catch (...) {
+                    budget->release(outb);
+                    throw;
                 }
-                BatchOutput bo = alloc_output(*ctx, c, want_d2, s);
-                std::shared_ptr<Budget> bud = budget;
-                bo.own->on_release = [bud, outb]() { bud->sub(outb); };
-                ctx->phase_b(bo.od, s);
+                std::shared_ptr<BudgetLedger> bud = budget;
+                bo.own->on_release = [bud, outb]() { bud->release(outb); };
+                try {
+                    ctx->phase_b(bo.od, s);
+                } catch (...) {
+                    delete bo.own;  // returns the reservation
+                    throw;
+                }
                 hand_out(*ctx, c, bo, outs.data());
             } catch (...) {
                 return_context(std::move(ctx), s);
@@ -177,6 +165,9 @@ void frnn_server_s::worker(int id) {
             }
             return_context(std::move(ctx), s);
             FRNN_HIP(hipStreamSynchronize(s));  // results complete on the device
+            // the client may release the results after this stream is gone
+            if (E > 0 && outs[0].owner_) static_cast<OutputOwner *>(outs[0].owner_)->buf.set_stream(nullptr);
+            for (auto &in : inputs) in.set_stream(nullptr);
         } catch (const Fail &f) {
             st = f.st;
             err = f.msg;
@@ -187,7 +178,7 @@ void frnn_server_s::worker(int id) {
         const double t1 = now_s();
         int64_t pre = 0;
         for (auto &r : batch) pre += r->precount;
-        budget->sub(pre);
+        budget->end(bid, pre);
         {
             std::lock_guard<std::mutex> g(mu);
             for (int e = 0; e < E; ++e) {
@@ -245,7 +236,7 @@ frnn_status frnn_server_create(const frnn_server_opts *o, frnn_server *out) {
             delete s;
             return fail(st, why);
         }
-        s->budget->limit = o->hbm_budget_bytes;
+        s->budget = std::make_shared<BudgetLedger>(o->hbm_budget_bytes);
         for (int i = 0; i < o->max_inflight; ++i) s->workers.emplace_back([s, i] { s->worker(i); });
         *out = s;
         return FRNN_OK;
@@ -262,7 +253,7 @@ frnn_status frnn_server_submit(frnn_server s, const float *points, int64_t N, ui
         auto r = std::make_shared<Request>();
         r->N = N;
         r->precount = s->precount_bytes(N);
-        if (r->precount > s->budget->limit) return fail(FRNN_ERR_BUDGET, "event larger than the whole budget");
+        if (r->precount > s->budget->limit()) return fail(FRNN_ERR_BUDGET, "event larger than the whole budget");
         r->host.assign(points, points + N * (int64_t)s->o.D);
         r->tm.submit_s = now_s();
         {

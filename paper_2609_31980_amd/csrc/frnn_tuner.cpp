@@ -89,16 +89,17 @@ std::string cache_key(int D, int64_t N, float r, int K) {
 }
 
 const char *kFields[] = {"grid_axes_max", "cells_per_point", "cell_multiple", "cells_per_item",
-                         "queries_per_item", "persistent", "blocks_per_cu", "row_cap_lds"};
+                         "queries_per_item", "persistent", "blocks_per_cu", "row_cap_lds",
+                         "stash_cap"};
 
 std::string opts_json(const frnn_opts &o) {
     char buf[512];
     std::snprintf(buf, sizeof buf,
                   "{\"grid_axes_max\": %d, \"cells_per_point\": %.9g, \"cell_multiple\": %d, "
                   "\"cells_per_item\": %d, \"queries_per_item\": %d, \"persistent\": %d, "
-                  "\"blocks_per_cu\": %d, \"row_cap_lds\": %d}",
+                  "\"blocks_per_cu\": %d, \"row_cap_lds\": %d, \"stash_cap\": %d}",
                   o.grid_axes_max, (double)o.cells_per_point, o.cell_multiple, o.cells_per_item,
-                  o.queries_per_item, o.persistent, o.blocks_per_cu, o.row_cap_lds);
+                  o.queries_per_item, o.persistent, o.blocks_per_cu, o.row_cap_lds, o.stash_cap);
     return buf;
 }
 
@@ -138,6 +139,7 @@ std::map<std::string, frnn_opts> read_cache(const std::string &path) {
             else if (!std::strcmp(fld, "persistent")) o.persistent = (int)v;
             else if (!std::strcmp(fld, "blocks_per_cu")) o.blocks_per_cu = (int)v;
             else if (!std::strcmp(fld, "row_cap_lds")) o.row_cap_lds = (int)v;
+            else if (!std::strcmp(fld, "stash_cap")) o.stash_cap = (int)v;
         }
         if (ok) m[key] = o;
         p = b1 + 1;
@@ -191,7 +193,8 @@ extern "C" frnn_status frnn_tune(const float *points, int64_t N, int32_t D, floa
         const int axes[] = {3, 4, 5, 6};
         const float cpps[] = {0.5f, 1.f, 2.f, 4.f, 16.f};
         const int cpis[] = {1, 2, 4};
-        const int qpis[] = {8, 16, 32, 64};
+        const int qpis[] = {8, 16, 32, 64, 128};
+        const int stashes[] = {0, 8, 16, 32};
         const int pers[] = {0, 1};
         const int bpcs[] = {4, 8, 16};
         auto consider = [&](frnn_opts cand) {
@@ -229,6 +232,11 @@ extern "C" frnn_status frnn_tune(const float *points, int64_t N, int32_t D, floa
         for (int v : qpis) {
             frnn_opts c = cur;
             c.queries_per_item = v;
+            consider(c);
+        }
+        for (int v : stashes) {
+            frnn_opts c = cur;
+            c.stash_cap = v;
             consider(c);
         }
         for (int v : pers) {

@@ -35,7 +35,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("grid_axes_max", ctypes.c_int32), ("cells_per_point", ctypes.c_float),
                 ("cell_multiple", ctypes.c_int32), ("cells_per_item", ctypes.c_int32),
                 ("queries_per_item", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("row_cap_lds", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("row_cap_lds", ctypes.c_int32),
+                ("stash_cap", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1,0 +1,183 @@
+"""GPU tests of the batched pipeline, the server, the tuner and the
+full-size density workload, all against the CPU oracle or against the
+single-event path (which is itself checked against the oracle)."""
+import numpy as np
+import pytest
+
+import pinlib
+from gpu_util import check_csr_invariants, check_rows, dev, gpu_csr, say
+from paper_2609_31980_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def frnn():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2609_31980_amd import frnn as f
+    return f
+
+
+def _np(csr):
+    off, idx, d2 = csr.numpy()
+    return off, idx, d2
+
+
+def test_batch_matches_oracle_and_single(orc, frnn):
+    sizes = [3000, 0, 1, 12000, 700, 5000]
+    evs = [inputs.tracks(n, 8, seed=40 + i) if n else np.zeros((0, 8), np.float32)
+           for i, n in enumerate(sizes)]
+    say("batch of 6 uneven events")
+    outs = frnn.query_batch([dev(e) for e in evs], 0.1, 256)
+    for e, (x, o) in enumerate(zip(evs, outs)):
+        want = orc.frnn(x, 0.1, 256)
+        pinlib.assert_csr_equal(_np(o), pinlib.as_tuple(want), f"batch event {e}")
+        if len(x):
+            pinlib.assert_csr_equal(_np(o), gpu_csr(x, 0.1, 256), f"batch vs single event {e}")
+
+
+def test_batch_graph_replay_varies_inputs(orc, frnn):
+    """The graph of a capacity class replays for different batches of it."""
+    import torch
+    for rep, seed in enumerate((50, 51, 52)):
+        sizes = [4000 + 500 * rep, 2500, 6000 - 300 * rep]
+        evs = [inputs.tracks(n, 8, seed=seed * 10 + i) for i, n in enumerate(sizes)]
+        outs = frnn.query_batch([dev(e) for e in evs], 0.1, 8)
+        torch.cuda.synchronize()
+        for e, (x, o) in enumerate(zip(evs, outs)):
+            pinlib.assert_csr_equal(_np(o), pinlib.as_tuple(orc.frnn(x, 0.1, 8)), f"replay {rep} event {e}")
+
+
+def test_batch_separate_queries_and_exclusion(orc, frnn):
+    xs, qs = [], []
+    for i in range(4):
+        x, q = inputs.clustered(8000 + 1000 * i, 900, 12, 0.03, seed=60 + i)
+        xs.append(x)
+        qs.append(q)
+    outs = frnn.query_batch([dev(x) for x in xs], inputs.C4_RADIUS, 64, queries=[dev(q) for q in qs])
+    for e, o in enumerate(outs):
+        pinlib.assert_csr_equal(_np(o), pinlib.as_tuple(orc.frnn(xs[e], inputs.C4_RADIUS, 64, Q=qs[e])),
+                                f"query batch event {e}")
+    evs = [inputs.tracks(3000, 8, seed=70 + i) for i in range(3)]
+    outs = frnn.query_batch([dev(e) for e in evs], 0.1, 0, exclude_self=True)
+    for e, o in enumerate(outs):
+        pinlib.assert_csr_equal(_np(o), pinlib.as_tuple(orc.frnn(evs[e], 0.1, 0, exclude_self=True)),
+                                f"exclude-self batch event {e}")
+
+
+def test_batch_eager_equals_graph(frnn):
+    """Per-launch timing forces eager launches; outputs must not change."""
+    evs = [inputs.tracks(n, 8, seed=80 + n) for n in (5000, 9000)]
+    a = [_np(o) for o in frnn.query_batch([dev(e) for e in evs], 0.1, 256)]
+    frnn.profile_enable(True)
+    try:
+        b = [_np(o) for o in frnn.query_batch([dev(e) for e in evs], 0.1, 256)]
+    finally:
+        frnn.profile_enable(False)
+        frnn.profile_read()
+    for x, y in zip(a, b):
+        pinlib.assert_csr_equal(x, y, "graph vs eager")
+
+
+def test_batch_rejects_nonfinite(frnn):
+    evs = [inputs.tracks(2000, 8, seed=1), inputs.tracks(2000, 8, seed=2)]
+    evs[1][7, 3] = np.nan
+    with pytest.raises(frnn.FrnnError) as e:
+        frnn.query_batch([dev(x) for x in evs], 0.1, 256)
+    assert e.value.name == "NONFINITE"
+    outs = frnn.query_batch([dev(evs[0])], 0.1, 256)   # the library still works
+    assert outs[0].nnz > 0
+
+
+def test_server_alone_and_in_the_mix(orc, frnn):
+    """Each served result equals the same event served alone and the
+    oracle, bit for bit."""
+    probe = inputs.tracks(7000, 8, seed=90)
+    want = orc.frnn(probe, 0.1, 256)
+    srv = frnn.Server(8, 0.1, 256, max_batch_events=16, max_inflight=2)
+    t = srv.submit(probe)
+    alone, tm = srv.wait(t)
+    pinlib.assert_csr_equal(_np(alone), pinlib.as_tuple(want), "served alone")
+    assert tm["batch_events"] == 1
+    others = [inputs.tracks(n, 8, seed=91 + i) for i, n in enumerate([3000, 12000, 500, 8000] * 5)]
+    tickets = []
+    for i, o in enumerate(others):
+        tickets.append(("other", i, srv.submit(o)))
+        if i == 9:
+            tickets.append(("probe", -1, srv.submit(probe)))
+    batches = set()
+    for kind, i, t in tickets:
+        c, tm = srv.wait(t)
+        batches.add(tm["batch_id"])
+        if kind == "probe":
+            pinlib.assert_csr_equal(_np(c), pinlib.as_tuple(want), "served in the mix")
+            mixed = tm["batch_events"]
+        elif i % 7 == 0:
+            pinlib.assert_csr_equal(_np(c), pinlib.as_tuple(orc.frnn(others[i], 0.1, 256)), f"other {i}")
+        c.release()
+    say(f"probe was served in a batch of {mixed}; {len(batches)} batches")
+    srv.close()
+
+
+def test_server_budget_admission(frnn):
+    ev = inputs.tracks(20000, 8, seed=5)
+    # room for about two events at a time: later ones wait for releases
+    srv = frnn.Server(8, 0.1, 256, hbm_budget_bytes=8_000_000, max_batch_events=8, max_inflight=2)
+    ts = [srv.submit(ev) for _ in range(6)]
+    ref = None
+    for t in ts:
+        c, tm = srv.wait(t)
+        got = _np(c)
+        c.release()
+        if ref is None:
+            ref = got
+        pinlib.assert_csr_equal(got, ref, "budgeted run")
+        assert tm["batch_events"] <= 3
+    with pytest.raises(frnn.FrnnError) as e:
+        srv.submit(inputs.tracks(300000, 8, seed=6))
+    assert e.value.name == "BUDGET"
+    srv.close()
+
+
+def test_tuner_candidates_all_exact(frnn):
+    x = dev(inputs.tracks(30000, 8, seed=7))
+    best, rep = frnn.tune(x, 0.1, 256)
+    assert rep["candidates_tried"] >= 10 and rep["candidates_rejected"] == 0
+    assert rep["best_ms"] <= rep["default_ms"] * 1.05
+
+
+def test_out_of_memory_hook(frnn):
+    x = dev(inputs.tracks(5000, 8, seed=8))
+    ix = frnn.build(x, 0.1)
+    frnn.fail_alloc_after(1)
+    with pytest.raises(frnn.FrnnError) as e:
+        ix.query(None, 0.1, 16)
+    frnn.fail_alloc_after(0)
+    assert e.value.name == "OOM"
+    c = ix.query(None, 0.1, 16)          # recovers
+    assert c.nnz > 0
+
+
+@pytest.mark.timeout(600)
+def test_density_workload_full_size(orc, frnn):
+    """1M references, 200k queries, D=12, K=64: a seeded 2% of the rows
+    against the oracle, and every query's uncapped count."""
+    w = inputs.c4()
+    say("density workload: GPU")
+    import torch
+    x, q = dev(w.points), dev(w.queries)
+    ix = frnn.build(x, w.r)
+    capped = ix.query(q, w.r, w.K).numpy()
+    full = ix.query(q, w.r, 0, want_dist2=False).numpy()
+    torch.cuda.synchronize()
+    check_csr_invariants(capped, len(w.points), w.K)
+    rows = inputs.subset_rows(len(w.queries), 0.02, 4)
+    say("density workload: oracle rows (2%)")
+    check_rows(orc, capped, w.points, w.r, w.K, rows, Q=w.queries, what="density K=64")
+    gdeg = np.diff(full[0])
+    assert np.array_equal(np.diff(capped[0]), np.minimum(gdeg, w.K))
+    say("density workload: oracle counts (all queries)")
+    odeg = orc.degrees(w.points, w.r, Q=w.queries)
+    assert np.array_equal(gdeg, odeg), "uncapped counts differ"
+    say(f"density: mean degree {gdeg.mean():.1f}, rows over K: {(gdeg > w.K).mean():.2f}")

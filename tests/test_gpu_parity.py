@@ -107,9 +107,10 @@ def test_identical_points_long_rows(orc, frnn):
 def test_forced_long_row_path(orc, frnn):
     """Rows longer than a tiny on-chip cap take the global-memory sort."""
     X = inputs.tracks(8000, 8, seed=3)
-    o = frnn.default_opts(row_cap_lds=2)
-    check_full(orc, X, 0.1, 0, opts=o, what="long path uncapped")
-    check_full(orc, X, 0.1, 5, opts=o, what="long path K=5")
+    for sc in (0, 8):
+        o = frnn.default_opts(row_cap_lds=2, stash_cap=sc)
+        check_full(orc, X, 0.1, 0, opts=o, what=f"long path uncapped stash={sc}")
+        check_full(orc, X, 0.1, 5, opts=o, what=f"long path K=5 stash={sc}")
 
 
 def test_lattice_boundaries(orc, frnn):
@@ -139,7 +140,9 @@ def test_grid_options_same_output(orc, frnn):
     for kw in (dict(grid_axes_max=0), dict(grid_axes_max=1), dict(grid_axes_max=5, cells_per_point=16.0),
                dict(cell_multiple=2, grid_axes_max=4), dict(cell_multiple=3, grid_axes_max=3),
                dict(cells_per_item=4), dict(queries_per_item=1), dict(queries_per_item=64),
-               dict(persistent=0), dict(blocks_per_cu=1)):
+               dict(persistent=0), dict(blocks_per_cu=1), dict(stash_cap=0), dict(stash_cap=8),
+               dict(stash_cap=32), dict(stash_cap=0, persistent=0), dict(queries_per_item=256),
+               dict(queries_per_item=2, cells_per_item=3)):
         got = gpu_csr(X, 0.1, 256, opts=frnn.default_opts(**kw))
         pinlib.assert_csr_equal(got, pinlib.as_tuple(want), f"opts {kw}")
 
