@@ -51,15 +51,7 @@ def pct(a, q):
 
 
 # ------------------------------------------------------------ single event
-def bench_single(frnn, x, r, K, steps, warmup):
-    def step():
-        ix = frnn.build(x, r)
-        c = ix.query(None, r, K)
-        nnz = c.nnz
-        c.release()
-        ix.close()
-        return nnz
-
+def time_steps(step, steps, warmup):
     for _ in range(warmup):
         nnz = step()
     sync()
@@ -67,17 +59,42 @@ def bench_single(frnn, x, r, K, steps, warmup):
     for _ in range(steps):
         nnz = step()
     sync()
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0, nnz
+
+
+def bench_single(frnn, x, r, K, steps, warmup):
+    """One step = the whole path for one event (bin, count, fill), input
+    resident in HBM.  Headline: the single-event launch sequence replayed as
+    a HIP graph (one synchronisation).  Beside it: the same kernels through
+    the build + query API (two synchronisations, eager launches)."""
+    def step_graph():
+        c = frnn.query_batch([x], r, K)[0]
+        n = c.nnz
+        c.release()
+        return n
+
+    def step_api():
+        ix = frnn.build(x, r)
+        c = ix.query(None, r, K)
+        n = c.nnz
+        c.release()
+        ix.close()
+        return n
+
+    dt, nnz = time_steps(step_graph, steps, warmup)
     stats = frnn.last_stats()
-    # second pass with per-launch HIP events for the kernel durations
+    dt_api, nnz_api = time_steps(step_api, steps, warmup)
+    assert nnz_api == nnz
+    # a third pass with per-launch HIP events (eager launches) for the
+    # kernel durations of the same work
     frnn.profile_enable(True)
     frnn.profile_read(reset=True)
     for _ in range(steps):
-        step()
+        step_graph()
     sync()
     prof = frnn.profile_read(reset=True)
     frnn.profile_enable(False)
-    return dt, nnz, stats, prof
+    return dt, dt_api, nnz, stats, prof
 
 
 # ------------------------------------------------------------ CPU baseline
@@ -119,6 +136,9 @@ def bench_batched(frnn, rounds=3):
             ix.close()
         return outs
 
+    def per_event_graph():
+        return [frnn.query_batch([x], r, K)[0] for x in xs]
+
     def batched():
         return frnn.query_batch(xs, r, K)
 
@@ -134,25 +154,31 @@ def bench_batched(frnn, rounds=3):
         o.release()
     del a, b
     sync()
-    tp, tb = [], []
+    times = {per_event: [], per_event_graph: [], batched: []}
+    fns = [per_event, per_event_graph, batched]
+    for fn in fns:          # warm-up (graph capture, pools)
+        [o.release() for o in fn()]
     for i in range(rounds):
-        order = (per_event, batched) if i % 2 == 0 else (batched, per_event)
+        order = fns if i % 2 == 0 else fns[::-1]
         for fn in order:
             sync()
             t0 = time.perf_counter()
             outs = fn()
             sync()
-            dt = time.perf_counter() - t0
+            times[fn].append(time.perf_counter() - t0)
             for o in outs:
                 o.release()
-            (tp if fn is per_event else tb).append(dt)
     E = len(xs)
+    tp, tg, tb = (float(np.median(times[f])) for f in fns)
     res = {"events": E, "points": npts, "pairs": nnz,
-           "per_event_ms": float(np.median(tp)) * 1e3, "batched_ms": float(np.median(tb)) * 1e3,
-           "per_event_events_per_s": E / float(np.median(tp)),
-           "batched_events_per_s": E / float(np.median(tb)),
-           "batched_pairs_per_s": nnz / float(np.median(tb)),
-           "speedup": float(np.median(tp)) / float(np.median(tb)), "identical_output": True}
+           "per_event_ms": tp * 1e3, "per_event_graph_ms": tg * 1e3, "batched_ms": tb * 1e3,
+           "per_event_events_per_s": E / tp, "per_event_graph_events_per_s": E / tg,
+           "batched_events_per_s": E / tb, "batched_pairs_per_s": nnz / tb,
+           "speedup_vs_per_event": tp / tb, "speedup_vs_per_event_graph": tg / tb,
+           "identical_output": True,
+           "per_event": "64 x (build + query API calls)",
+           "per_event_graph": "64 x single-event graph-replayed calls",
+           "batched": "one graph-replayed launch sequence over all 64 events"}
     del xs
     torch.cuda.empty_cache()
     return res
@@ -276,7 +302,7 @@ def main():
     x = torch.from_numpy(w.points).cuda()
     D = w.points.shape[1]
     log("single event: timing")
-    dt, nnz, stats, prof = bench_single(frnn, x, w.r, w.K, args.steps, args.warmup)
+    dt, dt_api, nnz, stats, prof = bench_single(frnn, x, w.r, w.K, args.steps, args.warmup)
     ms = dt / args.steps * 1e3
     kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1), "total_ms": v[1]} for k, v in prof.items()}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
@@ -298,6 +324,9 @@ def main():
                                   "K=256, queries = references", "N": 300000, "D": 8, "r": 0.1, "K": 256,
                       "parallelism": "1 GPU"},
            "events_per_s": args.steps / dt, "pairs_per_step": nnz,
+           "api_build_query": {"ms_per_step": dt_api / args.steps * 1e3,
+                               "pairs_per_s": nnz * args.steps / dt_api,
+                               "events_per_s": args.steps / dt_api},
            "roofline": roof, "kernels": kern}
     if not args.no_cpu:
         log("cpu baseline")

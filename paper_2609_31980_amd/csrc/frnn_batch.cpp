@@ -70,12 +70,14 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     Dp_ = (D + 3) & ~3;
     const bool selfq = sh.flags & FRNN_SELF_QUERY;
     const int Ec = sh.E_cap;
-    bd_b.reset(sizeof(BatchDesc), s);
-    ev_b.reset(sizeof(EventDev) * Ec, s);
-    pch.reset(sizeof(Chunk) * sh.pch_cap, s);
-    qch.reset(sizeof(Chunk) * sh.qch_cap, s);
-    ctr_b.reset(sizeof(Counters), s);
-    hv.reset(sizeof(Counters) + sizeof(int64_t) * (Ec + 1), s);
+    // descriptors (one block, one copy per batch): batch | events | point
+    // chunks | query chunks, each region sized for the capacity
+    o_ev_ = 256;
+    o_pc_ = o_ev_ + sizeof(EventDev) * Ec;
+    o_qc_ = o_pc_ + sizeof(Chunk) * sh.pch_cap;
+    desc.reset(o_qc_ + sizeof(Chunk) * sh.qch_cap, s);
+    // read-back block: query counters | build counters | event bases
+    hv.reset(2 * sizeof(Counters) + sizeof(int64_t) * (Ec + 1), s);
     grid.reset(sizeof(GridDesc) * Ec, s);
     runs.reset(sizeof(RunEntry) * kRunsMax * Ec, s);
     cell_off.reset(sizeof(int64_t) * (Ec + 1), s);
@@ -103,10 +105,10 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     outd.reset(sizeof(OutDesc), s);
 
     Bufs b{};
-    b.bd = bd_b.as<BatchDesc>();
-    b.ev = ev_b.as<EventDev>();
-    b.pchunks = pch.as<Chunk>();
-    b.qchunks = qch.as<Chunk>();
+    b.bd = desc.as<BatchDesc>();
+    b.ev = reinterpret_cast<const EventDev *>(desc.as<char>() + o_ev_);
+    b.pchunks = reinterpret_cast<const Chunk *>(desc.as<char>() + o_pc_);
+    b.qchunks = reinterpret_cast<const Chunk *>(desc.as<char>() + o_qc_);
     b.grid = grid.as<GridDesc>();
     b.runs = runs.as<RunEntry>();
     b.cell_off = cell_off.as<int64_t>();
@@ -130,9 +132,9 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     b.stash = stash.as<uint64_t>();
     b.scan_part = part.as<uint64_t>();
     b.out = outd.as<OutDesc>();
-    b.bases = reinterpret_cast<int64_t *>(hv.as<char>() + sizeof(Counters));
+    b.bases = reinterpret_cast<int64_t *>(hv.as<char>() + 2 * sizeof(Counters));
     bb_ = b;
-    bb_.ctr = ctr_b.as<Counters>();
+    bb_.ctr = reinterpret_cast<Counters *>(hv.as<char>() + sizeof(Counters));
     bq_ = b;
     bq_.ctr = hv.as<Counters>();
 
@@ -148,7 +150,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
 }
 
 void BatchContext::retarget(hipStream_t s) {
-    DevBuf *all[] = {&bd_b, &bd_q, &ev_b, &ev_q, &pch, &qch, &ctr_b, &hv, &grid, &cell_off, &ext,
+    DevBuf *all[] = {&desc, &hv, &grid, &cell_off, &ext,
                      &xs, &perm, &key, &rank, &skey, &cells, &qs, &qperm, &qkey, &qrank, &sqkey,
                      &qcells, &runs, &deg, &offs, &lofs, &lrows, &stash, &part, &outd};
     for (DevBuf *d : all) d->set_stream(s);
@@ -203,28 +205,20 @@ void BatchContext::set_inputs(const frnn_event *ev, int E, hipStream_t s) {
     bd.r_build = sh_.r;
     bd.total_pts = tp;
     bd.total_q = tq;
-    const size_t o_ev = 256, o_pc = o_ev + sizeof(EventDev) * E;
-    const size_t o_qc = o_pc + sizeof(Chunk) * pc.size();
-    char *h = (char *)stage_.ensure(o_qc + sizeof(Chunk) * qc.size() + 16);
+    char *h = (char *)stage_.ensure(o_qc_ + sizeof(Chunk) * std::max<size_t>(1, qc.size()));
     std::memcpy(h, &bd, sizeof(bd));
-    std::memcpy(h + o_ev, evh.data(), sizeof(EventDev) * E);
-    if (!pc.empty()) std::memcpy(h + o_pc, pc.data(), sizeof(Chunk) * pc.size());
-    if (!qc.empty()) std::memcpy(h + o_qc, qc.data(), sizeof(Chunk) * qc.size());
-    FRNN_HIP(hipMemcpyAsync(bd_b.get(), h, sizeof(bd), hipMemcpyHostToDevice, s));
-    FRNN_HIP(hipMemcpyAsync(ev_b.get(), h + o_ev, sizeof(EventDev) * E, hipMemcpyHostToDevice, s));
-    if (!pc.empty())
-        FRNN_HIP(hipMemcpyAsync(pch.get(), h + o_pc, sizeof(Chunk) * pc.size(), hipMemcpyHostToDevice, s));
-    if (!qc.empty())
-        FRNN_HIP(hipMemcpyAsync(qch.get(), h + o_qc, sizeof(Chunk) * qc.size(), hipMemcpyHostToDevice, s));
+    std::memcpy(h + o_ev_, evh.data(), sizeof(EventDev) * E);
+    if (!pc.empty()) std::memcpy(h + o_pc_, pc.data(), sizeof(Chunk) * pc.size());
+    if (!qc.empty()) std::memcpy(h + o_qc_, qc.data(), sizeof(Chunk) * qc.size());
+    FRNN_HIP(hipMemcpyAsync(desc.get(), h, o_qc_ + sizeof(Chunk) * qc.size(), hipMemcpyHostToDevice, s));
 }
-
 
 void BatchContext::launch_a(hipStream_t s) {
     const bool selfq = sh_.flags & FRNN_SELF_QUERY;
     const int D = sh_.D;
     LAUNCH("init", s, launch_init(bb_, sh_.E_cap, D, true, s));
     LAUNCH("extent", s, launch_extent(bb_, sh_.pch_cap, false, s));
-    LAUNCH("plan", s, launch_plan(bb_, s));
+    LAUNCH("plan", s, launch_plan(bb_, sh_.E_cap, s));
     LAUNCH("zero_cells", s, launch_zero_cells(bb_, sh_.cells_cap, false, s));
     LAUNCH("keys", s, launch_keys(bb_, sh_.pch_cap, false, s));
     LAUNCH("scan_cells", s, launch_scan_cells(bb_, sh_.cells_cap, false, s));
@@ -295,18 +289,17 @@ void BatchContext::phase_a(hipStream_t s) {
 }
 
 BatchCounts BatchContext::read_counts(hipStream_t s) {
-    const size_t hvb = sizeof(Counters) + sizeof(int64_t) * (E_ + 1);
-    char *p = (char *)back_.ensure(hvb + sizeof(Counters));
+    const size_t hvb = 2 * sizeof(Counters) + sizeof(int64_t) * (E_ + 1);
+    char *p = (char *)back_.ensure(hvb);
     FRNN_HIP(hipMemcpyAsync(p, hv.get(), hvb, hipMemcpyDeviceToHost, s));
-    FRNN_HIP(hipMemcpyAsync(p + hvb, ctr_b.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
     FRNN_HIP(hipStreamSynchronize(s));
     BatchCounts c;
     std::memcpy(&c.ctr, p, sizeof(Counters));
     Counters cb;
-    std::memcpy(&cb, p + hvb, sizeof(Counters));
+    std::memcpy(&cb, p + sizeof(Counters), sizeof(Counters));
     c.build_status = cb.status;
     c.bases.resize(E_ + 1);
-    std::memcpy(c.bases.data(), p + sizeof(Counters), sizeof(int64_t) * (E_ + 1));
+    std::memcpy(c.bases.data(), p + 2 * sizeof(Counters), sizeof(int64_t) * (E_ + 1));
     return c;
 }
 

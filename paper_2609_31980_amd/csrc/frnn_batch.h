@@ -79,7 +79,8 @@ private:
     std::vector<int64_t> qoff_, nq_;
     Knobs kn_{};
     Bufs bb_{}, bq_{};  // build run and query run
-    DevBuf bd_b, bd_q, ev_b, ev_q, pch, qch, ctr_b, hv, grid, cell_off, ext, xs, perm, key, rank,
+    size_t o_ev_ = 0, o_pc_ = 0, o_qc_ = 0;
+    DevBuf desc, hv, grid, cell_off, ext, xs, perm, key, rank,
         skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, stash, part, outd;
     Pinned stage_, back_;
     hipGraphExec_t ga_ = nullptr, gb_ = nullptr;

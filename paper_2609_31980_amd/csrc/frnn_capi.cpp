@@ -75,7 +75,7 @@ void frnn_opts_default(frnn_opts *o) {
     o->cell_multiple = 1;
     o->cells_per_item = 1;
     o->queries_per_item = 32;
-    o->persistent = 1;
+    o->persistent = 0;
     o->blocks_per_cu = 8;
     o->row_cap_lds = kRowLds;
     o->stash_cap = 16;

@@ -16,7 +16,7 @@ constexpr int kDMax = 32;        // most coordinates per point
 constexpr int kRunsMax = 256;    // neighbour runs per work item (LDS table size)
 constexpr int kCandLds = 512;    // candidate positions listed in LDS per work item
 constexpr int kRowLds = 512;     // longest row collected and sorted on chip
-constexpr int kChunkRows = 1024; // rows per chunk of the per-point kernels
+constexpr int kChunkRows = 256;  // rows per chunk of the per-point kernels
 constexpr int kWavesPerBlock = 4;
 
 // Cell grid of one event, chosen on the device from the event's extent.

@@ -197,9 +197,9 @@ __global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries) {
 }
 
 // ------------------------------------------------------------------ plan
-// One block.  For every event: grid axes = the coordinates of largest
-// extent; cell width h = r_h / m with r_h = r (1 + 2^-16) + 2^-60 (float64);
-// the most axes (up to the limit) whose cell count stays within the cap.
+// One wave per event.  Grid axes = the coordinates of largest extent; cell
+// width h = r_h / m with r_h = r (1 + 2^-16) + 2^-60 (float64); the most
+// axes (up to the limit) whose cell count stays within the cap.
 //
 // Why no neighbour is lost (the roundoff-safe grid): float32 rounding is
 // monotone and every u_d is >= 0, so s <= r2 implies fl32(t_a^2) <= r2 on
@@ -207,114 +207,124 @@ __global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries) {
 // Cell coordinates v = fl64(fl64(x - lo) * inv_h) carry a relative error
 // below 2^-51, far less than the 2^-16 margin in h, so |v(x) - v(y)| < m and
 // the floors differ by at most m; clamping to [0, n-1] cannot widen the gap.
+__device__ __forceinline__ double shfl_f64(double v, int src) {
+    return __shfl(v, src);
+}
+
 __global__ void __launch_bounds__(256) k_plan(Bufs b) {
-    __shared__ int64_t ssum[256];
     const BatchDesc bd = *b.bd;
     const int E = bd.E, D = bd.D;
+    const int lane = lane_id();
+    const int e = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (e >= E) return;
+    const EventDev ev = b.ev[e];
+    // lane d < D: extent and lower bound of coordinate d; a non-finite
+    // input (reported to the host as an error) must still give an
+    // in-bounds grid, so its extent counts as empty
+    double x = -1.0, lo = 0.0;
+    if (lane < D) {
+        const float flo = ord2f(b.ext[((int64_t)e * 2 + 0) * D + lane]);
+        const float fhi = ord2f(b.ext[((int64_t)e * 2 + 1) * D + lane]);
+        x = ev.n_pts > 0 ? (double)fhi - (double)flo : 0.0;
+        if (!(x >= 0.0 && x <= 1.0e39)) x = 0.0;
+        lo = ev.n_pts > 0 ? (double)flo : 0.0;
+        if (!(lo >= -3.5e38 && lo <= 3.5e38)) lo = 0.0;
+    }
+    // rank by decreasing extent, ties by coordinate index
+    int rank = 0;
+    for (int d2 = 0; d2 < D; ++d2) {
+        const double x2 = shfl_f64(x, d2);
+        rank += (x2 > x || (x2 == x && d2 < lane)) ? 1 : 0;
+    }
+    GridDesc g;
+    for (int a = 0; a < kGMax; ++a) {
+        g.axis[a] = 0;
+        g.n[a] = 1;
+        g.stride[a] = 0;
+        g.lo[a] = 0.0;
+    }
+    const int m = bd.cell_multiple;
+    g.m = m;
+    const double rh = (double)bd.r_build * (1.0 + 0x1p-16) + 0x1p-60;
+    double inv_h = 1.0 / (rh / (double)m);
+    int64_t cap = (int64_t)((double)bd.cells_per_point * (double)(ev.n_pts > 0 ? ev.n_pts : 1));
+    if (cap < 1) cap = 1;
+    if (cap > ((int64_t)1 << 30)) cap = (int64_t)1 << 30;
+    if (cap > ev.cell_cap) cap = ev.cell_cap;
+    const int gmax = min(bd.grid_axes_max, min(D, kGMax));
+    double cext[kGMax];
+    for (int a = 0; a < gmax; ++a) {
+        const uint64_t hit = ballot(lane < D && rank == a);
+        const int ax = __ffsll((unsigned long long)hit) - 1;
+        g.axis[a] = ax;
+        cext[a] = shfl_f64(x, ax);
+        g.lo[a] = shfl_f64(lo, ax);
+    }
+    int G = 0;
+    const int W = 2 * m + 1;
+    for (int gg = gmax; gg >= 1; --gg) {
+        int64_t runs = 1;
+        for (int a = 1; a < gg; ++a) runs *= W;
+        if (runs > kRunsMax) continue;
+        double C = 1.0;
+        for (int a = 0; a < gg; ++a) C *= floor(cext[a] * inv_h) + 1.0;
+        if (C <= (double)cap) {
+            G = gg;
+            break;
+        }
+    }
+    if (G == 0 && gmax >= 1) {
+        // even one axis at width r_h/m has too many cells: widen the cells
+        // (wider cells never lose a neighbour)
+        G = 1;
+        if (cext[0] > 0.0) {
+            const double w = (double)(cap - 1) / cext[0];
+            inv_h = w < inv_h ? w : inv_h;
+        }
+    }
+    g.G = G;
+    g.inv_h = inv_h;
+    g.h = inv_h > 0.0 ? 1.0 / inv_h : 0.0;
+    uint32_t C = 1;
+    int runs = 1;
+    for (int a = 0; a < G; ++a) {
+        double na = floor(cext[a] * inv_h) + 1.0;
+        if (na > (double)cap) na = (double)cap;
+        g.n[a] = (int32_t)na;
+        g.stride[a] = C;
+        C *= (uint32_t)g.n[a];
+        if (a >= 1) runs *= W;
+    }
+    g.C = C;
+    g.runs = runs;
+    if (lane == 0) b.grid[e] = g;
+    // neighbour runs: offsets in -m..m on grid axes 1..G-1 (base 2m+1
+    // digits of the run index) and their key offsets
+    for (int s = lane; s < runs; s += 64) {
+        RunEntry re;
+        re.koff = 0;
+        for (int a = 0; a < kGMax; ++a) re.o[a] = 0;
+        for (int a = 0; a < 6; ++a) re.pad[a] = 0;
+        int t = s;
+        for (int a = 1; a < G; ++a) {
+            const int o = t % W - m;
+            t /= W;
+            re.o[a] = (int8_t)o;
+            re.koff += o * (int32_t)g.stride[a];
+        }
+        b.runs[(int64_t)e * kRunsMax + s] = re;
+    }
+}
+
+// Exclusive scan of the events' cell counts -> cell offsets (one block).
+__global__ void __launch_bounds__(256) k_plan_offsets(Bufs b) {
+    __shared__ int64_t ssum[256];
+    const int E = b.bd->E;
     const int per = (E + 255) / 256;
     const int e0 = threadIdx.x * per;
     const int e1 = min(E, e0 + per);
     int64_t local = 0;
-    for (int e = e0; e < e1; ++e) {
-        const EventDev ev = b.ev[e];
-        GridDesc g;
-        for (int a = 0; a < kGMax; ++a) {
-            g.axis[a] = 0;
-            g.n[a] = 1;
-            g.stride[a] = 0;
-            g.lo[a] = 0.0;
-        }
-        const int m = bd.cell_multiple;
-        g.m = m;
-        const double rh = (double)bd.r_build * (1.0 + 0x1p-16) + 0x1p-60;
-        double inv_h = 1.0 / (rh / (double)m);
-        int64_t cap = (int64_t)((double)bd.cells_per_point * (double)(ev.n_pts > 0 ? ev.n_pts : 1));
-        if (cap < 1) cap = 1;
-        if (cap > ((int64_t)1 << 30)) cap = (int64_t)1 << 30;
-        if (cap > ev.cell_cap) cap = ev.cell_cap;
-        const int gmax = min(bd.grid_axes_max, min(D, kGMax));
-        // axes by decreasing extent (ties: lower coordinate first)
-        double cext[kGMax];
-        uint32_t used = 0;
-        for (int a = 0; a < gmax; ++a) {
-            int best = -1;
-            double bext = -1.0;
-            for (int d = 0; d < D; ++d) {
-                if (used & (1u << d)) continue;
-                float lo = ord2f(b.ext[((int64_t)e * 2 + 0) * D + d]);
-                float hi = ord2f(b.ext[((int64_t)e * 2 + 1) * D + d]);
-                double x = ev.n_pts > 0 ? (double)hi - (double)lo : 0.0;
-                // non-finite input (reported to the host as an error) must
-                // still give an in-bounds grid: treat its extent as empty
-                if (!(x >= 0.0 && x <= 1.0e39)) x = 0.0;
-                if (x > bext) {
-                    bext = x;
-                    best = d;
-                }
-            }
-            used |= 1u << best;
-            g.axis[a] = best;
-            cext[a] = bext;
-            double lo = ev.n_pts > 0 ? (double)ord2f(b.ext[((int64_t)e * 2 + 0) * D + best]) : 0.0;
-            g.lo[a] = (lo >= -3.5e38 && lo <= 3.5e38) ? lo : 0.0;
-        }
-        int G = 0;
-        const int W = 2 * m + 1;
-        for (int gg = gmax; gg >= 1; --gg) {
-            int64_t runs = 1;
-            for (int a = 1; a < gg; ++a) runs *= W;
-            if (runs > kRunsMax) continue;
-            double C = 1.0;
-            for (int a = 0; a < gg; ++a) C *= floor(cext[a] * inv_h) + 1.0;
-            if (C <= (double)cap) {
-                G = gg;
-                break;
-            }
-        }
-        if (G == 0 && gmax >= 1) {
-            // even one axis at width r_h/m has too many cells: widen the
-            // cells (wider cells never lose a neighbour)
-            G = 1;
-            if (cext[0] > 0.0) {
-                double w = (double)(cap - 1) / cext[0];
-                inv_h = w < inv_h ? w : inv_h;
-            }
-        }
-        g.G = G;
-        g.inv_h = inv_h;
-        g.h = inv_h > 0.0 ? 1.0 / inv_h : 0.0;
-        uint32_t C = 1;
-        int runs = 1;
-        for (int a = 0; a < G; ++a) {
-            double na = floor(cext[a] * inv_h) + 1.0;
-            if (na > (double)cap) na = (double)cap;
-            g.n[a] = (int32_t)na;
-            g.stride[a] = C;
-            C *= (uint32_t)g.n[a];
-            if (a >= 1) runs *= W;
-        }
-        g.C = C;
-        g.runs = runs;
-        b.grid[e] = g;
-        // neighbour runs: offsets in -m..m on grid axes 1..G-1 (base 2m+1
-        // digits of the run index) and their key offsets
-        for (int s = 0; s < runs; ++s) {
-            RunEntry re;
-            re.koff = 0;
-            for (int a = 0; a < kGMax; ++a) re.o[a] = 0;
-            for (int a = 0; a < 6; ++a) re.pad[a] = 0;
-            int t = s;
-            for (int a = 1; a < G; ++a) {
-                const int o = t % W - m;
-                t /= W;
-                re.o[a] = (int8_t)o;
-                re.koff += o * (int32_t)g.stride[a];
-            }
-            b.runs[(int64_t)e * kRunsMax + s] = re;
-        }
-        local += C;
-    }
-    // exclusive scan of the cell counts over events -> cell offsets
+    for (int e = e0; e < e1; ++e) local += b.grid[e].C;
     ssum[threadIdx.x] = local;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
@@ -732,6 +742,16 @@ __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
         const int64_t coff = b.cell_off[e];
         const int64_t q_off = b.ev[e].q_off;
         const RunEntry *rtab = b.runs + (int64_t)e * kRunsMax;
+        if (FILL && kn.stash_cap > 0) {
+            // nothing to do when every row of the window was stashed
+            bool any = false;
+            for (int64_t q0 = p; q0 < pend; q0 += 64) {
+                bool need = false;
+                if (q0 + lane < pend) need = b.deg[q_off + qperm[q0 + lane]] > (uint32_t)kn.stash_cap;
+                any = any || ballot(need) != 0;
+            }
+            if (!any) return;
+        }
         while (p < pend) {
             // the group: this window's queries in the cell block of slot p
             const uint32_t key = uniform(sqkey[p]);
@@ -975,36 +995,36 @@ __global__ void __launch_bounds__(256) k_stash_sort(Bufs b, Knobs kn) {
     const int32_t *qperm = kn.self_query ? b.perm : b.qperm;
     const int lane = lane_id();
     const int gl = threadIdx.x % SC;          // lane within the row's group
-    constexpr int per = 256 / SC;             // rows per block step
-    for (int c = blockIdx.x; c < bd.n_qchunks; c += gridDim.x) {
-        const Chunk ch = b.qchunks[c];
+    constexpr int per = 256 / SC;             // rows per block
+    constexpr int steps = kChunkRows / per;   // blocks per chunk
+    const uint32_t nvb = (uint32_t)bd.n_qchunks * steps;
+    for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const Chunk ch = b.qchunks[vb / steps];
         const int64_t q_off = b.ev[ch.ev].q_off;
-        for (int64_t base = ch.r0; base < ch.r1; base += per) {
-            const int64_t qp = base + threadIdx.x / SC;
-            uint32_t dq = 0;
-            int64_t qid = 0;
-            if (qp < ch.r1) {
-                qid = q_off + qperm[qp];
-                dq = b.deg[qid];
-            }
-            const bool mine = dq > 0 && dq <= (uint32_t)SC;
-            uint64_t v = (mine && gl < (int)dq) ? b.stash[qp * SC + gl] : ~0ull;
+        const int64_t qp = ch.r0 + (int64_t)(vb % steps) * per + threadIdx.x / SC;
+        uint32_t dq = 0;
+        int64_t qid = 0;
+        if (qp < ch.r1) {
+            qid = q_off + qperm[qp];
+            dq = b.deg[qid];
+        }
+        const bool mine = dq > 0 && dq <= (uint32_t)SC;
+        uint64_t v = (mine && gl < (int)dq) ? b.stash[qp * SC + gl] : ~0ull;
 #pragma unroll
-            for (int k = 2; k <= SC; k <<= 1) {
-                uint64_t o = shfl_xor64(v, k - 1);
-                v = (lane & (k >> 1)) == 0 ? umin64(v, o) : umax64(v, o);
+        for (int k = 2; k <= SC; k <<= 1) {
+            uint64_t o = shfl_xor64(v, k - 1);
+            v = (lane & (k >> 1)) == 0 ? umin64(v, o) : umax64(v, o);
 #pragma unroll
-                for (int j = k >> 2; j >= 1; j >>= 1) {
-                    o = shfl_xor64(v, j);
-                    v = (lane & j) == 0 ? umin64(v, o) : umax64(v, o);
-                }
+            for (int j = k >> 2; j >= 1; j >>= 1) {
+                o = shfl_xor64(v, j);
+                v = (lane & j) == 0 ? umin64(v, o) : umax64(v, o);
             }
-            const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
-            if (mine && gl < (int)keep) {
-                const int64_t off = b.offs[qid] + gl;
-                b.out->indices[off] = (int32_t)(uint32_t)v;
-                if (b.out->dist2) b.out->dist2[off] = __uint_as_float((uint32_t)(v >> 32));
-            }
+        }
+        const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
+        if (mine && gl < (int)keep) {
+            const int64_t off = b.offs[qid] + gl;
+            b.out->indices[off] = (int32_t)(uint32_t)v;
+            if (b.out->dist2) b.out->dist2[off] = __uint_as_float((uint32_t)(v >> 32));
         }
     }
 }
@@ -1111,8 +1131,11 @@ hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, hipStream_t s
     return hipSuccess;
 }
 
-hipError_t launch_plan(const Bufs &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(256), 0, s, b);
+hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_plan, dim3((E_cap + kWavesPerBlock - 1) / kWavesPerBlock), dim3(64 * kWavesPerBlock),
+                       0, s, b);
+    FRNN_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_plan_offsets, dim3(1), dim3(256), 0, s, b);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1194,7 +1217,9 @@ hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStr
 }
 
 hipError_t launch_stash_sort(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s) {
-    dim3 grid(std::max(1, std::min(nqchunks, 8192))), block(256);
+    const int per = kn.stash_cap > 0 ? 256 / kn.stash_cap : 1;
+    const int64_t nvb = (int64_t)nqchunks * (kChunkRows / per);
+    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(nvb, 65536))), block(256);
     switch (kn.stash_cap) {
     case 0: return hipSuccess;
     case 8: hipLaunchKernelGGL(k_stash_sort<8>, grid, block, 0, s, b, kn); break;

@@ -11,7 +11,7 @@ namespace frnn {
 
 hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s);
 hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, hipStream_t s);
-hipError_t launch_plan(const Bufs &b, hipStream_t s);
+hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s);
 hipError_t launch_zero_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s);
 hipError_t launch_keys(const Bufs &b, int nchunks, bool queries, hipStream_t s);
 hipError_t launch_scan_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s);

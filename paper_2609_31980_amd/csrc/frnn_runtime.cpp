@@ -343,9 +343,8 @@ frnn_status build_index(Index &ix, const float *const *points, const int64_t *n,
     std::memcpy(h + o_ev, evh.data(), sizeof(EventDev) * E);
     if (!ch.empty()) std::memcpy(h + o_ch, ch.data(), sizeof(Chunk) * ch.size());
 
-    ix.bd.reset(sizeof(BatchDesc), s);
-    ix.ev.reset(sizeof(EventDev) * E, s);
-    ix.pchunks.reset(sizeof(Chunk) * std::max<size_t>(1, ch.size()), s);
+    // descriptors: one device block, one copy
+    ix.desc.reset(stage, s);
     ix.grid.reset(sizeof(GridDesc) * E, s);
     ix.runs.reset(sizeof(RunEntry) * kRunsMax * E, s);
     ix.cell_off.reset(sizeof(int64_t) * (E + 1), s);
@@ -359,15 +358,14 @@ frnn_status build_index(Index &ix, const float *const *points, const int64_t *n,
     DevBuf rank(sizeof(uint32_t) * std::max<int64_t>(1, tot), s);
     DevBuf part(sizeof(uint64_t) * 2 * kScanBlocks, s);
 
-    FRNN_HIP(hipMemcpyAsync(ix.bd.get(), h, sizeof(bd), hipMemcpyHostToDevice, s));
-    FRNN_HIP(hipMemcpyAsync(ix.ev.get(), h + o_ev, sizeof(EventDev) * E, hipMemcpyHostToDevice, s));
-    if (!ch.empty())
-        FRNN_HIP(hipMemcpyAsync(ix.pchunks.get(), h + o_ch, sizeof(Chunk) * ch.size(), hipMemcpyHostToDevice, s));
+    FRNN_HIP(hipMemcpyAsync(ix.desc.get(), h, stage, hipMemcpyHostToDevice, s));
 
     Bufs b{};
-    b.bd = ix.bd.as<BatchDesc>();
-    b.ev = ix.ev.as<EventDev>();
-    b.pchunks = ix.pchunks.as<Chunk>();
+    b.bd = ix.desc.as<BatchDesc>();
+    b.ev = reinterpret_cast<const EventDev *>(ix.desc.as<char>() + o_ev);
+    b.pchunks = reinterpret_cast<const Chunk *>(ix.desc.as<char>() + o_ch);
+    ix.o_ev = o_ev;
+    ix.o_ch = o_ch;
     b.ctr = ix.ctr.as<Counters>();
     b.grid = ix.grid.as<GridDesc>();
     b.runs = ix.runs.as<RunEntry>();
@@ -383,7 +381,7 @@ frnn_status build_index(Index &ix, const float *const *points, const int64_t *n,
 
     LAUNCH("init", s, launch_init(b, E, D, true, s));
     LAUNCH("extent", s, launch_extent(b, ix.n_pchunks, false, s));
-    LAUNCH("plan", s, launch_plan(b, s));
+    LAUNCH("plan", s, launch_plan(b, E, s));
     LAUNCH("zero_cells", s, launch_zero_cells(b, ccap, false, s));
     LAUNCH("keys", s, launch_keys(b, ix.n_pchunks, false, s));
     LAUNCH("scan_cells", s, launch_scan_cells(b, ccap, false, s));
@@ -400,6 +398,7 @@ frnn_status build_index(Index &ix, const float *const *points, const int64_t *n,
         ix.grid_host.resize(E);
         std::memcpy(ix.grid_host.data(), p + sizeof(Counters), sizeof(GridDesc) * E);
         if (c.status & kStatusNonfinitePts) return fail(FRNN_ERR_NONFINITE, "non-finite coordinate in the points");
+        ix.status_checked = true;
     }
     return FRNN_OK;
 }
@@ -449,8 +448,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     if (!qch.empty()) std::memcpy(h + o_ch, qch.data(), sizeof(Chunk) * qch.size());
 
     const int64_t tq1 = std::max<int64_t>(1, totq);
-    DevBuf dbd(sizeof(BatchDesc), s), dev(sizeof(EventDev) * E, s),
-        dqch(sizeof(Chunk) * std::max<size_t>(1, qch.size()), s);
+    DevBuf desc(stage, s);
     DevBuf hv(sizeof(Counters) + sizeof(int64_t) * (E + 1), s);
     DevBuf deg(sizeof(uint32_t) * tq1, s),
         offs(sizeof(int64_t) * (tq1 + 1), s), lofs(sizeof(int64_t) * (tq1 + 1), s),
@@ -466,16 +464,13 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
         sqkey.reset(sizeof(uint32_t) * tq1, s);
         qcells.reset(sizeof(uint32_t) * (ix.cells_cap + 1), s);
     }
-    FRNN_HIP(hipMemcpyAsync(dbd.get(), h, sizeof(bd), hipMemcpyHostToDevice, s));
-    FRNN_HIP(hipMemcpyAsync(dev.get(), h + o_ev, sizeof(EventDev) * E, hipMemcpyHostToDevice, s));
-    if (!qch.empty())
-        FRNN_HIP(hipMemcpyAsync(dqch.get(), h + o_ch, sizeof(Chunk) * qch.size(), hipMemcpyHostToDevice, s));
+    FRNN_HIP(hipMemcpyAsync(desc.get(), h, stage, hipMemcpyHostToDevice, s));
 
     Bufs b{};
-    b.bd = dbd.as<BatchDesc>();
-    b.ev = dev.as<EventDev>();
-    b.pchunks = ix.pchunks.as<Chunk>();
-    b.qchunks = dqch.as<Chunk>();
+    b.bd = desc.as<BatchDesc>();
+    b.ev = reinterpret_cast<const EventDev *>(desc.as<char>() + o_ev);
+    b.pchunks = reinterpret_cast<const Chunk *>(ix.desc.as<char>() + ix.o_ch);
+    b.qchunks = reinterpret_cast<const Chunk *>(desc.as<char>() + o_ch);
     b.ctr = hv.as<Counters>();
     b.bases = reinterpret_cast<int64_t *>(hv.as<char>() + sizeof(Counters));
     b.grid = ix.grid.as<GridDesc>();
@@ -528,11 +523,13 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     const size_t hvb = sizeof(Counters) + sizeof(int64_t) * (E + 1);
     char *p = (char *)t_back.ensure(hvb + sizeof(Counters));
     FRNN_HIP(hipMemcpyAsync(p, hv.get(), hvb, hipMemcpyDeviceToHost, s));
-    FRNN_HIP(hipMemcpyAsync(p + hvb, ix.ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
+    // an index built without a synchronisation reports its status here
+    if (!ix.status_checked)
+        FRNN_HIP(hipMemcpyAsync(p + hvb, ix.ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
     FRNN_HIP(hipStreamSynchronize(s));
-    Counters c, cb;
+    Counters c, cb{};
     std::memcpy(&c, p, sizeof(c));
-    std::memcpy(&cb, p + hvb, sizeof(cb));
+    if (!ix.status_checked) std::memcpy(&cb, p + hvb, sizeof(cb));
     std::vector<int64_t> bases(E + 1);
     std::memcpy(bases.data(), p + sizeof(Counters), sizeof(int64_t) * (E + 1));
     if (cb.status & kStatusNonfinitePts) return fail(FRNN_ERR_NONFINITE, "non-finite coordinate in the points");

@@ -142,7 +142,9 @@ struct Index {
     int n_pchunks = 0;
     std::vector<int64_t> n_pts, pt_off;
     std::vector<const float *> pts;
-    DevBuf bd, ev, pchunks, grid, runs, cell_off, ext, xs, perm, skey, cells, ctr;
+    DevBuf desc, grid, runs, cell_off, ext, xs, perm, skey, cells, ctr;
+    size_t o_ev = 0, o_ch = 0;        // offsets of the event and chunk tables in desc
+    bool status_checked = false;      // non-finite input already ruled out
     std::vector<GridDesc> grid_host;  // valid after a synchronised build
     Pinned stage;                     // descriptor staging of the build copies
     hipStream_t stream = nullptr;
