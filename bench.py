@@ -280,7 +280,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-events", type=int, default=600)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="also run one plain device copy of this many MiB (for scaling HBM counters)")
+                    help="also write and then read this many MiB with plain kernels (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
@@ -291,13 +291,14 @@ def main():
     from paper_2609_31980_amd import frnn, inputs
 
     if args.calib_copy_mib:
+        # a plain write kernel and a plain read kernel of known size, to
+        # scale the HBM byte counters (FETCH_SIZE, WRITE_SIZE)
         a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
         a.fill_(1.0)
-        c = torch.empty_like(a)
         sync()
-        c.copy_(a)
+        s = a.sum()
         sync()
-        del a, c
+        del a, s
     w = inputs.c2()
     x = torch.from_numpy(w.points).cuda()
     D = w.points.shape[1]

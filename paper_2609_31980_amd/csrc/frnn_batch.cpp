@@ -97,6 +97,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
         qcells.reset(sizeof(uint32_t) * (sh.cells_cap + 1), s);
     }
     deg.reset(sizeof(uint32_t) * sh.q_cap, s);
+    sdeg.reset(sizeof(uint32_t) * sh.q_cap, s);
     offs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
     lofs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
     lrows.reset(sizeof(uint32_t) * sh.q_cap, s);
@@ -126,6 +127,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     b.sqkey = selfq ? skey.as<uint32_t>() : sqkey.as<uint32_t>();
     b.qcells = selfq ? cells.as<uint32_t>() : qcells.as<uint32_t>();
     b.deg = deg.as<uint32_t>();
+    b.sdeg = sdeg.as<uint32_t>();
     b.offs = offs.as<int64_t>();
     b.lofs = lofs.as<int64_t>();
     b.long_rows = lrows.as<uint32_t>();
@@ -152,7 +154,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
 void BatchContext::retarget(hipStream_t s) {
     DevBuf *all[] = {&desc, &hv, &grid, &cell_off, &ext,
                      &xs, &perm, &key, &rank, &skey, &cells, &qs, &qperm, &qkey, &qrank, &sqkey,
-                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &stash, &part, &outd};
+                     &qcells, &runs, &deg, &sdeg, &offs, &lofs, &lrows, &stash, &part, &outd};
     for (DevBuf *d : all) d->set_stream(s);
 }
 
@@ -217,16 +219,14 @@ void BatchContext::launch_a(hipStream_t s) {
     const bool selfq = sh_.flags & FRNN_SELF_QUERY;
     const int D = sh_.D;
     LAUNCH("init", s, launch_init(bb_, sh_.E_cap, D, true, s));
-    LAUNCH("extent", s, launch_extent(bb_, sh_.pch_cap, false, s));
+    LAUNCH("extent", s, launch_extent(bb_, sh_.pch_cap, false, sh_.cells_cap + 1, s));
     LAUNCH("plan", s, launch_plan(bb_, sh_.E_cap, s));
-    LAUNCH("zero_cells", s, launch_zero_cells(bb_, sh_.cells_cap, false, s));
     LAUNCH("keys", s, launch_keys(bb_, sh_.pch_cap, false, s));
     LAUNCH("scan_cells", s, launch_scan_cells(bb_, sh_.cells_cap, false, s));
     LAUNCH("scatter", s, launch_scatter(bb_, sh_.pch_cap, false, s));
     LAUNCH("init", s, launch_init(bq_, sh_.E_cap, D, false, s));
     if (!selfq) {
-        LAUNCH("extent_q", s, launch_extent(bq_, sh_.qch_cap, true, s));
-        LAUNCH("zero_cells_q", s, launch_zero_cells(bq_, sh_.cells_cap, true, s));
+        LAUNCH("extent_q", s, launch_extent(bq_, sh_.qch_cap, true, sh_.cells_cap + 1, s));
         LAUNCH("keys_q", s, launch_keys(bq_, sh_.qch_cap, true, s));
         LAUNCH("scan_cells_q", s, launch_scan_cells(bq_, sh_.cells_cap, true, s));
         LAUNCH("scatter_q", s, launch_scatter(bq_, sh_.qch_cap, true, s));
@@ -237,10 +237,8 @@ void BatchContext::launch_a(hipStream_t s) {
 }
 
 void BatchContext::launch_b(hipStream_t s) {
-    LAUNCH("stash_sort", s, launch_stash_sort(bq_, kn_, sh_.qch_cap, s));
     LAUNCH("fill", s, launch_fill(bq_, kn_, sh_.D, query_blocks(sh_.o, sh_.qch_cap), s));
     LAUNCH("long_sort", s, launch_long_sort(bq_, kn_, 256, s));
-    LAUNCH("finalize", s, launch_finalize(bq_, sh_.qch_cap, s));
 }
 
 static bool capture(hipStream_t s, hipGraph_t *g, hipGraphExec_t *ge, void (*fn)(void *, hipStream_t),
@@ -304,7 +302,7 @@ BatchCounts BatchContext::read_counts(hipStream_t s) {
 }
 
 void BatchContext::phase_b(const OutDesc &od, hipStream_t s) {
-    LAUNCH("set_out", s, launch_set_out(bq_.out, od, s));
+    LAUNCH("set_out", s, launch_set_out(bq_, od, s));
     if (graphs_enabled && !prof_enabled()) {
         if (!gb_ &&
             !capture(s, &grb_, &gb_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_b(st); }, this)) {

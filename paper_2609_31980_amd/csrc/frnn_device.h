@@ -136,6 +136,7 @@ struct Bufs {
     uint32_t *qkey, *qrank, *sqkey, *qcells;
     // rows
     uint32_t *deg;         // in-radius count per query (global row)
+    uint32_t *sdeg;        // the same count by sorted query slot
     int64_t *offs;         // [total_q+1] exclusive scan of capped counts
     int64_t *lofs;         // [total_q+1] exclusive scan of long-row lengths
     uint32_t *long_rows;

@@ -2,10 +2,11 @@
 // gfx950 (CDNA4, 64-lane wavefronts).
 //
 // Pipeline (every size is read from device memory, see frnn_device.h):
-//   binning    k_init, k_extent, k_plan, k_zero_cells, k_keys, scan, k_scatter
+//   binning    k_init, k_extent (+ clears cells), k_plan, k_keys, scan, k_scatter
 //   work items k_items                       one item = queries of a cell block
 //   counting   k_query<count>, scan of the capped counts, k_bases
-//   filling    k_query<fill>, k_long_sort, k_finalize
+//   filling    k_set_out, k_query<fill> (stashed rows, per-event offsets, long
+//              rows re-evaluated), k_long_sort
 //
 // Exactness: the squared distance is computed in float32 as
 //   s = +0; for d in 0..D-1: t = q_d - x_d; u = t*t; s = s + u
@@ -148,7 +149,30 @@ __global__ void k_init(Bufs b, int32_t init_ext) {
 // ---------------------------------------------------------------- extent
 // Per-event per-axis min / max of the points and a finiteness check
 // (queries: finiteness only).  Thread t of a block always reads axis t % D.
-__global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries) {
+// A block keeps its running min / max across the chunks it takes and
+// publishes them (LDS, then one global atomic per axis) only when the event
+// changes, so few atomics meet on the same address.  The same launch clears
+// the cell histogram for the capacity of the run.
+__device__ __forceinline__ void flush_extent(Bufs &b, int ev, int D, int t, int stride, uint32_t mn,
+                                             uint32_t mx, uint32_t *smin, uint32_t *smax) {
+    if (t < kDMax) {
+        smin[t] = 0xffffffffu;
+        smax[t] = 0u;
+    }
+    __syncthreads();
+    if (t < stride) {
+        atomicMin(&smin[t % D], mn);
+        atomicMax(&smax[t % D], mx);
+    }
+    __syncthreads();
+    if (t < D) {
+        atomicMin(&b.ext[((int64_t)ev * 2 + 0) * D + t], smin[t]);
+        atomicMax(&b.ext[((int64_t)ev * 2 + 1) * D + t], smax[t]);
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries, int64_t zero_n) {
     __shared__ uint32_t smin[kDMax], smax[kDMax];
     __shared__ int sbad;
     const BatchDesc bd = *b.bd;
@@ -157,43 +181,41 @@ __global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries) {
     const Chunk *chunks = queries ? b.qchunks : b.pchunks;
     const int stride = (256 / D) * D;
     const int t = threadIdx.x;
+    // clear the cell histogram (zero_n cells, the capacity)
+    uint32_t *cells = queries ? b.qcells : b.cells;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + t; i < zero_n; i += (int64_t)gridDim.x * blockDim.x)
+        cells[i] = 0u;
+    if (t == 0) sbad = 0;
+    __syncthreads();
+    uint32_t mn = 0xffffffffu, mx = 0u;
+    bool bad = false;
+    int cur = -1;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const Chunk ch = chunks[c];
+        if (!queries && ch.ev != cur) {
+            if (cur >= 0) flush_extent(b, cur, D, t, stride, mn, mx, smin, smax);
+            cur = ch.ev;
+            mn = 0xffffffffu;
+            mx = 0u;
+        }
         const EventDev ev = b.ev[ch.ev];
         const float *src = queries ? ev.qry : ev.pts;
         const int64_t off = queries ? ev.q_off : ev.pt_off;
-        if (t < kDMax) {
-            smin[t] = 0xffffffffu;
-            smax[t] = 0u;
-        }
-        if (t == 0) sbad = 0;
-        __syncthreads();
-        uint32_t mn = 0xffffffffu, mx = 0u;
-        bool bad = false;
         if (t < stride) {
             const int64_t f0 = (ch.r0 - off) * D, f1 = (ch.r1 - off) * D;
             for (int64_t f = f0 + t; f < f1; f += stride) {
-                float x = src[f];
+                const float x = src[f];
                 bad |= !finite32(x);
-                uint32_t o = f2ord(x);
+                const uint32_t o = f2ord(x);
                 mn = o < mn ? o : mn;
                 mx = o > mx ? o : mx;
             }
-            if (!queries) {
-                atomicMin(&smin[t % D], mn);
-                atomicMax(&smax[t % D], mx);
-            }
         }
-        if (bad) sbad = 1;
-        __syncthreads();
-        if (!queries && t < D) {
-            atomicMin(&b.ext[((int64_t)ch.ev * 2 + 0) * D + t], smin[t]);
-            atomicMax(&b.ext[((int64_t)ch.ev * 2 + 1) * D + t], smax[t]);
-        }
-        if (t == 0 && sbad)
-            atomicOr(&b.ctr->status, queries ? kStatusNonfiniteQry : kStatusNonfinitePts);
-        __syncthreads();
     }
+    if (!queries && cur >= 0) flush_extent(b, cur, D, t, stride, mn, mx, smin, smax);
+    if (bad) sbad = 1;
+    __syncthreads();
+    if (t == 0 && sbad) atomicOr(&b.ctr->status, queries ? kStatusNonfiniteQry : kStatusNonfinitePts);
 }
 
 // ------------------------------------------------------------------ plan
@@ -344,17 +366,6 @@ __global__ void __launch_bounds__(256) k_plan_offsets(Bufs b) {
     }
 }
 
-// Clears the cell histogram (cells 0..total, the last one is the sentinel
-// the exclusive scan turns into the total).
-__global__ void k_zero_cells(Bufs b, int32_t queries) {
-    const BatchDesc bd = *b.bd;
-    const int64_t n = b.cell_off[bd.E] + 1;
-    uint32_t *cells = queries ? b.qcells : b.cells;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        cells[i] = 0u;
-}
-
 // ------------------------------------------------------------------ keys
 __device__ __forceinline__ uint32_t cell_key(const GridDesc &g, const float *row) {
     uint32_t key = 0;
@@ -433,8 +444,9 @@ __global__ void __launch_bounds__(256) k_scatter(Bufs b, int32_t queries) {
 }
 
 // ------------------------------------------------------------------ scan
-// Exclusive scan of pairs of 64-bit values in three launches with a fixed
-// grid (block partials, scan of the partials, apply).  Modes:
+// Exclusive scan of pairs of 64-bit values in two launches with a fixed
+// grid (block partials; then each block adds its predecessors' partials and
+// scans its range).  Modes:
 //   0: point cells   (in place, 32-bit)
 //   1: query cells   (in place, 32-bit)
 //   2: row offsets   deg -> (min(deg, K), deg if the row is long else 0)
@@ -476,6 +488,10 @@ __device__ __forceinline__ void scan_store(const Bufs &b, uint64_t i, ulonglong2
     } else {
         b.offs[i] = (int64_t)v.x;
         b.lofs[i] = (int64_t)v.y;
+        if (i == (uint64_t)b.bd->total_q) {  // the appended zero: its prefix is the total
+            b.ctr->nnz = v.x;
+            b.ctr->long_total = v.y;
+        }
     }
 }
 
@@ -553,35 +569,22 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Bufs b, Knobs kn) 
     }
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(1024) k_scan_parts(Bufs b, int32_t nparts) {
-    ulonglong2 v;
-    v.x = 0;
-    v.y = 0;
-    if ((int)threadIdx.x < nparts) {
-        v.x = b.scan_part[2 * threadIdx.x];
-        v.y = b.scan_part[2 * threadIdx.x + 1];
-    }
-    ulonglong2 tot;
-    ulonglong2 ex = block_excl_scan(v, &tot);
-    if ((int)threadIdx.x < nparts) {
-        b.scan_part[2 * threadIdx.x] = ex.x;
-        b.scan_part[2 * threadIdx.x + 1] = ex.y;
-    }
-    if (MODE == kScanRows && threadIdx.x == 0) {
-        b.ctr->nnz = tot.x;
-        b.ctr->long_total = tot.y;
-    }
-}
-
+// Each block adds up the partials of the blocks before it (at most
+// kScanBlocks of them), then scans its own range.
 template <int MODE>
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Bufs b, Knobs kn) {
     const uint64_t n = scan_n<MODE>(b);
     uint64_t lo, hi;
     scan_range<MODE>(b, n, &lo, &hi);
+    ulonglong2 pre;
+    pre.x = 0;
+    pre.y = 0;
+    for (unsigned j = threadIdx.x; j < blockIdx.x; j += blockDim.x) {
+        pre.x += b.scan_part[2 * j];
+        pre.y += b.scan_part[2 * j + 1];
+    }
     ulonglong2 run;
-    run.x = b.scan_part[2 * blockIdx.x];
-    run.y = b.scan_part[2 * blockIdx.x + 1];
+    block_excl_scan(pre, &run);
     for (uint64_t t0 = lo; t0 < hi; t0 += (uint64_t)kScanThreads * kScanItems) {
         const uint64_t i0 = t0 + (uint64_t)threadIdx.x * kScanItems;
         ulonglong2 v[kScanItems];
@@ -689,21 +692,30 @@ __device__ __forceinline__ void sort_and_write(const uint64_t *hits, uint32_t n,
 }
 
 // Work assignment.  The sorted queries of each event are cut into windows
-// of kn.window consecutive slots (each chunk of kChunkRows slots holds
-// kChunkRows / window of them).  A wave evaluates one window at a time.
+// of kn.window (<= 64) consecutive slots (each chunk of kChunkRows slots
+// holds kChunkRows / window of them).  A wave evaluates one window at a time.
 // Workgroups are dispatched to the 8 XCDs round robin, so the windows are
 // remapped to give every XCD one contiguous range (neighbouring windows
 // read the same points, which then stay in that XCD's L2).
 //   plain:      one window per wave, grid covers all windows
 //   persistent: resident waves drain 8 per-XCD queues of windows, then
 //               help the other XCDs' queues
+//
+// Inside a window, one lane per query loads its cell key, original index and
+// (fill pass) row length, and the query rows go to LDS, all in one round of
+// parallel loads; the window's cell-block groups are the runs of equal block
+// keys (a ballot).  For each group the wave lists the neighbour key runs
+// (the next group's runs are fetched while this group is evaluated), keeps
+// the first KR*64 candidates' rows and ids in registers, and evaluates every
+// query of the group against them, 64 candidates per step, one per lane.
 template <int DT, bool EXACT_D, bool FILL, int KR>
-__global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
+__device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
+    constexpr int DP = (DT + 3) & ~3;
     __shared__ WaveLds slds[kWavesPerBlock];
+    __shared__ float4 sq[kWavesPerBlock][64 * DP / 4];  // the window's query rows
     __shared__ uint64_t shits[FILL ? kWavesPerBlock : 1][FILL ? kRowLds : 1];
     __shared__ unsigned long long s_cand[kWavesPerBlock];
     __shared__ uint32_t s_groups[kWavesPerBlock];
-    constexpr int DP = (DT + 3) & ~3;
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
     WaveLds &L = slds[w];
@@ -711,8 +723,8 @@ __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
     const int D = EXACT_D ? DT : bd.D;
     const int Dp = EXACT_D ? DP : bd.Dp;
     const float r2 = kn.r2;
+    const uint32_t SC = (uint32_t)kn.stash_cap;
     const uint32_t *cells = b.cells;
-    const uint32_t *qcells = kn.self_query ? b.cells : b.qcells;
     const uint32_t *sqkey = kn.self_query ? b.skey : b.sqkey;
     const float *qs = kn.self_query ? b.xs : b.qs;
     const int32_t *qperm = kn.self_query ? b.perm : b.qperm;
@@ -734,137 +746,217 @@ __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
         const uint32_t c = wid / wpc, sub = wid % wpc;
         if (c >= (uint32_t)bd.n_qchunks) return;
         const Chunk ch = b.qchunks[c];
-        int64_t p = ch.r0 + (int64_t)sub * Wn;
-        const int64_t pend = min(ch.r1, p + Wn);
+        const int64_t p0 = ch.r0 + (int64_t)sub * Wn;
+        const int64_t pend = min(ch.r1, p0 + Wn);
+        if (p0 >= pend) return;
+        const int nwq = (int)(pend - p0);
         const int e = ch.ev;
         const GridDesc &g = b.grid[e];
         const int G = g.G, m = g.m, runs = g.runs;
+        const int n0 = G > 0 ? g.n[0] : 1;
+        const int R = kn.cells_per_item;
         const int64_t coff = b.cell_off[e];
         const int64_t q_off = b.ev[e].q_off;
         const RunEntry *rtab = b.runs + (int64_t)e * kRunsMax;
-        if (FILL && kn.stash_cap > 0) {
-            // nothing to do when every row of the window was stashed
-            bool any = false;
-            for (int64_t q0 = p; q0 < pend; q0 += 64) {
-                bool need = false;
-                if (q0 + lane < pend) need = b.deg[q_off + qperm[q0 + lane]] > (uint32_t)kn.stash_cap;
-                any = any || ballot(need) != 0;
+        // one lane per query of the window
+        const bool inw = lane < nwq;
+        const uint32_t wkey = inw ? sqkey[p0 + lane] : 0u;
+        const int32_t wperm = inw ? qperm[p0 + lane] : 0;
+        const uint32_t wdeg = (FILL && inw) ? b.sdeg[p0 + lane] : 0u;
+        uint64_t need = ballot(inw);
+        if (FILL) {
+            // per-event offsets of this window's rows, and the rows kept whole
+            // by the count pass: sorted here, SC lanes per row
+            const int64_t wqid = q_off + wperm;
+            int64_t woff = 0;
+            if (inw) {
+                woff = b.offs[wqid];
+                b.out->offsets[wqid + e + 1] = b.offs[wqid + 1] - b.bases[e];
             }
-            if (!any) return;
-        }
-        while (p < pend) {
-            // the group: this window's queries in the cell block of slot p
-            const uint32_t key = uniform(sqkey[p]);
-            int c_[kGMax] = {0, 0, 0, 0, 0, 0};
-            {
-                uint32_t rem = key;
-#pragma unroll
-                for (int a = 0; a < kGMax; ++a) {
-                    if (a < G) {
-                        c_[a] = (int)(rem % (uint32_t)g.n[a]);
-                        rem /= (uint32_t)g.n[a];
-                    }
-                }
-            }
-            int lo0 = 0, hi0 = 0;
-            uint32_t kbase = key;  // key of the group's row with c0 = 0
-            int64_t gend = pend;
-            if (G > 0) {
-                const int R = kn.cells_per_item;
-                const int b0 = (c_[0] / R) * R;
-                const int b1 = min(b0 + R - 1, g.n[0] - 1);
-                kbase = key - (uint32_t)c_[0];
-                lo0 = max(b0 - m, 0);
-                hi0 = min(b1 + m, g.n[0] - 1);
-                gend = min(pend, (int64_t)qcells[coff + kbase + b1 + 1]);
-            } else {
-                gend = pend;
-            }
-            const int64_t gbeg = p;
-            p = gend;
-            ++my_groups;
-            if (FILL && kn.stash_cap > 0) {
-                bool any = false;
-                for (int64_t q0 = gbeg; q0 < gend; q0 += 64) {
-                    bool need = false;
-                    if (q0 + lane < gend) need = b.deg[q_off + qperm[q0 + lane]] > (uint32_t)kn.stash_cap;
-                    any = any || ballot(need) != 0;
-                }
-                if (!any) continue;
-            }
-            // neighbour key runs, empty ones dropped
-            uint32_t total = 0;
-            int nruns = 0;
-            for (int s0 = 0; s0 < runs; s0 += 64) {
-                const int s = s0 + lane;
-                uint32_t start = 0, len = 0;
-                if (s < runs) {
-                    const RunEntry re = rtab[s];
-                    bool ok = true;
-#pragma unroll
-                    for (int a = 1; a < kGMax; ++a) {
-                        if (a < G) {
-                            const int ca = c_[a] + re.o[a];
-                            ok = ok && ca >= 0 && ca < g.n[a];
+            if (SC > 0) {
+                const int rpp = 64 / (int)SC;  // rows per pass
+                const int gl = lane % (int)SC;
+                for (int t0 = 0; t0 < nwq; t0 += rpp) {
+                    const int t = t0 + lane / (int)SC;
+                    const uint32_t dq = (uint32_t)__shfl((int)wdeg, t);
+                    const int64_t off = __shfl((long long)woff, t);
+                    const bool mine = t < nwq && dq > 0 && dq <= SC;
+                    uint64_t v = (mine && gl < (int)dq) ? b.stash[(p0 + t) * SC + gl] : ~0ull;
+                    for (int kk = 2; kk <= (int)SC; kk <<= 1) {
+                        uint64_t o = shfl_xor64(v, kk - 1);
+                        v = (lane & (kk >> 1)) == 0 ? umin64(v, o) : umax64(v, o);
+                        for (int j = kk >> 2; j >= 1; j >>= 1) {
+                            o = shfl_xor64(v, j);
+                            v = (lane & j) == 0 ? umin64(v, o) : umax64(v, o);
                         }
                     }
-                    if (ok) {
-                        const int64_t k0 = coff + (int64_t)kbase + re.koff;
-                        start = cells[k0 + lo0];
-                        len = cells[k0 + hi0 + 1] - start;
+                    const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
+                    if (mine && gl < (int)keep) {
+                        out_idx[off + gl] = (int32_t)(uint32_t)v;
+                        if (out_d2) out_d2[off + gl] = __uint_as_float((uint32_t)(v >> 32));
                     }
                 }
-                const uint64_t nz = ballot(len > 0);
-                const uint32_t inc = wave_incl_scan(len);
-                if (len > 0) {
-                    const int at = nruns + (int)lanes_below(nz);
-                    L.run_base[at] = start;
-                    L.run_pref[at] = total + inc - len;
+            }
+            need = ballot(inw && wdeg > SC);  // rows to evaluate again
+            if (!need) return;
+        }
+        {
+            const float4 *src = reinterpret_cast<const float4 *>(qs + p0 * Dp);
+            float4 *dst = &sq[w][0];
+            for (int i = lane; i < nwq * (Dp / 4); i += 64) dst[i] = src[i];
+        }
+        // grid coordinates of each lane's query cell, decoded once per window
+        int cw[kGMax] = {0, 0, 0, 0, 0, 0};
+        {
+            uint32_t rem = wkey;
+#pragma unroll
+            for (int a = 0; a < kGMax; ++a) {
+                if (a < G) {
+                    cw[a] = (int)(rem % (uint32_t)g.n[a]);
+                    rem /= (uint32_t)g.n[a];
                 }
-                total += uniform((uint32_t)__shfl((int)inc, 63));
-                nruns += __popcll(nz);
+            }
+        }
+        const uint32_t c0 = (uint32_t)cw[0];
+        const uint32_t bkey = wkey - c0 + (c0 / R) * R;  // key of the cell block's first cell
+        const uint32_t prev = (uint32_t)__shfl_up((int)bkey, 1);
+        const uint64_t starts = ballot(inw && (lane == 0 || bkey != prev));
+        // groups with work: those holding a needed query
+        uint64_t todo = 0;
+        for (uint64_t sm = starts; sm;) {
+            const int gb = __ffsll((unsigned long long)sm) - 1;
+            sm &= sm - 1;
+            const int ge = sm ? __ffsll((unsigned long long)sm) - 1 : nwq;
+            const uint64_t range = (ge >= 64 ? ~0ull : ((1ull << ge) - 1)) & ~((1ull << gb) - 1);
+            if (need & range) todo |= 1ull << gb;
+        }
+        wave_lds_sync();
+
+        // neighbour runs of the group whose first query is window lane gb:
+        // lane s < runs probes run s (start, length)
+        // one run-table entry per lane, loaded once per window (tables with
+        // more than 64 runs are read per group instead)
+        RunEntry wre{};
+        if (lane < runs) wre = rtab[lane];
+        auto probe = [&](int gb, int s, uint32_t &start, uint32_t &len) {
+            start = 0;
+            len = 0;
+            if (s >= runs) return;
+            const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)wkey, gb);
+            int cc[kGMax];
+#pragma unroll
+            for (int a = 0; a < kGMax; ++a) cc[a] = __builtin_amdgcn_readlane(cw[a], gb);
+            int lo0 = 0, hi0 = 0;
+            uint32_t kbase = key;
+            if (G > 0) {
+                const int b0 = (cc[0] / R) * R;
+                const int b1 = min(b0 + R - 1, n0 - 1);
+                kbase = key - (uint32_t)cc[0];
+                lo0 = max(b0 - m, 0);
+                hi0 = min(b1 + m, n0 - 1);
+            }
+            const RunEntry re = runs <= 64 ? wre : rtab[s];
+            bool ok = true;
+#pragma unroll
+            for (int a = 1; a < kGMax; ++a) {
+                if (a < G) {
+                    const int ca = cc[a] + re.o[a];
+                    ok = ok && ca >= 0 && ca < g.n[a];
+                }
+            }
+            if (ok) {
+                const int64_t k0 = coff + (int64_t)kbase + re.koff;
+                start = cells[k0 + lo0];
+                len = cells[k0 + hi0 + 1] - start;
+            }
+        };
+        // compacts probed runs into the LDS table; returns the candidates so far
+        auto commit = [&](uint32_t start, uint32_t len, uint32_t &total, int &nruns) {
+            const uint64_t nz = ballot(len > 0);
+            const uint32_t inc = wave_incl_scan(len);
+            if (len > 0) {
+                const int at = nruns + (int)lanes_below(nz);
+                L.run_base[at] = start;
+                L.run_pref[at] = total + inc - len;
+            }
+            total += uniform((uint32_t)__shfl((int)inc, 63));
+            nruns += __popcll(nz);
+        };
+
+        const bool one_batch = runs <= 64;
+        uint32_t nst = 0, nln = 0;
+        if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nln);
+        while (todo) {
+            const int gb = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const uint64_t later = starts & ~((2ull << gb) - 1);
+            const int ge = later ? __ffsll((unsigned long long)later) - 1 : nwq;
+            ++my_groups;
+            uint32_t total = 0;
+            int nruns = 0;
+            if (one_batch) {
+                commit(nst, nln, total, nruns);
+            } else {
+                for (int s0 = 0; s0 < runs; s0 += 64) {
+                    uint32_t st0, ln0;
+                    probe(gb, s0 + lane, st0, ln0);
+                    commit(st0, ln0, total, nruns);
+                }
             }
             if (lane == 0) L.run_pref[nruns] = total;
             wave_lds_sync();
             // the first KR*64 candidates stay in registers for every query
             CandRow<DT> xr[KR];
-            uint32_t pr[KR];
+            uint32_t pr[KR], pj[KR];
+            uint64_t vmask[KR];  // lanes holding a candidate, per register chunk
 #pragma unroll
             for (int k = 0; k < KR; ++k) {
                 const uint32_t v = k * 64 + lane;
+                vmask[k] = ballot(v < total);
                 pr[k] = 0;
+                pj[k] = 0;
                 if (k * 64 < (int)total) {
                     pr[k] = v < total ? locate(L, nruns, v) : 0u;
                     load_row<DT, EXACT_D>(xr[k], b.xs + (int64_t)pr[k] * Dp, D);
+                    pj[k] = (uint32_t)b.perm[pr[k]];
                 }
             }
-            for (int64_t qp = gbeg; qp < gend; ++qp) {
+            // fetch the next group's runs while this one is evaluated
+            if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nln);
+            for (int t = gb; t < ge; ++t) {
+                const int64_t qp = p0 + t;
                 QueryRow<DT> qr;
-                const float *qrow = qs + qp * Dp;
 #pragma unroll
-                for (int d = 0; d < DT; ++d) qr.q[d] = (EXACT_D || d < D) ? qrow[d] : 0.0f;
-                const int64_t qid = q_off + qperm[qp];
+                for (int d4 = 0; d4 < DP; d4 += 4) {
+                    if (EXACT_D || d4 < Dp) {
+                        const float4 v = sq[w][t * (Dp / 4) + d4 / 4];
+                        qr.q[d4] = v.x;
+                        if (d4 + 1 < DT) qr.q[d4 + 1] = v.y;
+                        if (d4 + 2 < DT) qr.q[d4 + 2] = v.z;
+                        if (d4 + 3 < DT) qr.q[d4 + 3] = v.w;
+                    }
+                }
+                const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
                 if (!FILL) {
                     // count; the first stash_cap hit keys are kept for the fill
                     uint32_t cnt = 0;
-                    const uint32_t SC = (uint32_t)kn.stash_cap;
                     uint64_t *st = b.stash + qp * SC;
-                    auto tally = [&](bool hit, float s, uint32_t pos) {
-                        const uint64_t hm = ballot(hit);
-                        if (hit) {
-                            const uint32_t slot = cnt + lanes_below(hm);
-                            if (slot < SC)
-                                st[slot] = ((uint64_t)__float_as_uint(s) << 32) | (uint32_t)b.perm[pos];
+                    auto tally = [&](uint64_t hm, float s, uint32_t j) {
+                        if (hm) {
+                            if ((hm >> lane) & 1) {
+                                const uint32_t slot = cnt + lanes_below(hm);
+                                if (slot < SC) st[slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                            }
+                            cnt += (uint32_t)__popcll(hm);
                         }
-                        cnt += (uint32_t)__popcll(hm);
                     };
 #pragma unroll
                     for (int k = 0; k < KR; ++k) {
                         if (k * 64 < (int)total) {
                             const float s = dist2<DT, EXACT_D>(qr, xr[k], D);
-                            const bool hit = (k * 64 + lane < (int)total) && s <= r2 &&
-                                             !(kn.exclude_self && pr[k] == (uint32_t)qp);
-                            tally(hit, s, pr[k]);
+                            uint64_t hm = ballot(s <= r2) & vmask[k];
+                            if (kn.exclude_self) hm &= ~ballot(pr[k] == (uint32_t)qp);
+                            tally(hm, s, pj[k]);
                         }
                     }
                     for (uint32_t v0 = KR * 64; v0 < total; v0 += 64) {
@@ -875,34 +967,37 @@ __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
                         load_row<DT, EXACT_D>(x, b.xs + (int64_t)pos * Dp, D);
                         const float s = dist2<DT, EXACT_D>(qr, x, D);
                         const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == (uint32_t)qp);
-                        tally(hit, s, pos);
+                        tally(ballot(hit), s, hit ? (uint32_t)b.perm[pos] : 0u);
                     }
-                    if (lane == 0) b.deg[qid] = cnt;
+                    if (lane == 0) {
+                        b.deg[qid] = cnt;
+                        b.sdeg[qp] = cnt;
+                    }
                     my_cand += total;
                 } else {
-                    const uint32_t dq = b.deg[qid];
-                    if (dq <= (uint32_t)kn.stash_cap) continue;  // sorted from the stash
+                    const uint32_t dq = (uint32_t)__builtin_amdgcn_readlane((int)wdeg, t);
+                    if (dq <= SC) continue;  // sorted from the stash
                     const int64_t off = b.offs[qid];
                     const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
                     const bool lng = dq > (uint32_t)kn.long_cap;
                     uint64_t *dst = lng ? long_keys + b.lofs[qid] : &shits[w][0];
                     uint32_t nh = 0;
-                    auto emit = [&](bool hit, float s, uint32_t pos) {
-                        const uint64_t hm = ballot(hit);
-                        if (hit) {
-                            const uint32_t slot = nh + lanes_below(hm);
-                            const uint32_t j = (uint32_t)b.perm[pos];  // original id, hits only
-                            if (slot < dq) dst[slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                    auto emit = [&](uint64_t hm, float s, uint32_t j) {
+                        if (hm) {
+                            if ((hm >> lane) & 1) {
+                                const uint32_t slot = nh + lanes_below(hm);
+                                if (slot < dq) dst[slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                            }
+                            nh += (uint32_t)__popcll(hm);
                         }
-                        nh += (uint32_t)__popcll(hm);
                     };
 #pragma unroll
                     for (int k = 0; k < KR; ++k) {
                         if (k * 64 < (int)total) {
                             const float s = dist2<DT, EXACT_D>(qr, xr[k], D);
-                            const bool hit = (k * 64 + lane < (int)total) && s <= r2 &&
-                                             !(kn.exclude_self && pr[k] == (uint32_t)qp);
-                            emit(hit, s, pr[k]);
+                            uint64_t hm = ballot(s <= r2) & vmask[k];
+                            if (kn.exclude_self) hm &= ~ballot(pr[k] == (uint32_t)qp);
+                            emit(hm, s, pj[k]);
                         }
                     }
                     for (uint32_t v0 = KR * 64; v0 < total; v0 += 64) {
@@ -913,7 +1008,7 @@ __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
                         load_row<DT, EXACT_D>(x, b.xs + (int64_t)pos * Dp, D);
                         const float s = dist2<DT, EXACT_D>(qr, x, D);
                         const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == (uint32_t)qp);
-                        emit(hit, s, pos);
+                        emit(ballot(hit), s, hit ? (uint32_t)b.perm[pos] : 0u);
                     }
                     if (nh != dq && lane == 0) atomicOr(&b.ctr->status, kStatusInternal);
                     if (lng) {
@@ -973,60 +1068,29 @@ __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            unsigned long long c = 0;
+            unsigned long long cs = 0;
             uint32_t gsum = 0;
             for (int i = 0; i < kWavesPerBlock; ++i) {
-                c += s_cand[i];
+                cs += s_cand[i];
                 gsum += s_groups[i];
             }
-            if (c) atomicAdd((unsigned long long *)&b.ctr->candidates, c);
+            if (cs) atomicAdd((unsigned long long *)&b.ctr->candidates, cs);
             if (gsum) atomicAdd(&b.ctr->n_groups, gsum);
         }
     }
 }
 
-// ------------------------------------------------------------ stashed rows
-// Rows whose length is at most SC were kept whole by the count pass: each
-// group of SC lanes sorts one row with the bitonic network and writes its
-// first min(deg, K) entries.
-template <int SC>
-__global__ void __launch_bounds__(256) k_stash_sort(Bufs b, Knobs kn) {
-    const BatchDesc &bd = *b.bd;
-    const int32_t *qperm = kn.self_query ? b.perm : b.qperm;
-    const int lane = lane_id();
-    const int gl = threadIdx.x % SC;          // lane within the row's group
-    constexpr int per = 256 / SC;             // rows per block
-    constexpr int steps = kChunkRows / per;   // blocks per chunk
-    const uint32_t nvb = (uint32_t)bd.n_qchunks * steps;
-    for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        const Chunk ch = b.qchunks[vb / steps];
-        const int64_t q_off = b.ev[ch.ev].q_off;
-        const int64_t qp = ch.r0 + (int64_t)(vb % steps) * per + threadIdx.x / SC;
-        uint32_t dq = 0;
-        int64_t qid = 0;
-        if (qp < ch.r1) {
-            qid = q_off + qperm[qp];
-            dq = b.deg[qid];
-        }
-        const bool mine = dq > 0 && dq <= (uint32_t)SC;
-        uint64_t v = (mine && gl < (int)dq) ? b.stash[qp * SC + gl] : ~0ull;
-#pragma unroll
-        for (int k = 2; k <= SC; k <<= 1) {
-            uint64_t o = shfl_xor64(v, k - 1);
-            v = (lane & (k >> 1)) == 0 ? umin64(v, o) : umax64(v, o);
-#pragma unroll
-            for (int j = k >> 2; j >= 1; j >>= 1) {
-                o = shfl_xor64(v, j);
-                v = (lane & j) == 0 ? umin64(v, o) : umax64(v, o);
-            }
-        }
-        const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
-        if (mine && gl < (int)keep) {
-            const int64_t off = b.offs[qid] + gl;
-            b.out->indices[off] = (int32_t)(uint32_t)v;
-            if (b.out->dist2) b.out->dist2[off] = __uint_as_float((uint32_t)(v >> 32));
-        }
-    }
+// Two entry points with the same body: the second asks the compiler for 5
+// resident waves per SIMD (at most 96 registers), which the measurements
+// favour for the 8-dimensional kernel even with a few spilled registers.
+template <int DT, bool EXACT_D, bool FILL, int KR>
+__global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
+    query_body<DT, EXACT_D, FILL, KR>(b, kn);
+}
+
+template <int DT, bool EXACT_D, bool FILL, int KR>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_query_o5(Bufs b, Knobs kn) {
+    query_body<DT, EXACT_D, FILL, KR>(b, kn);
 }
 
 // ------------------------------------------------------------ long rows
@@ -1089,24 +1153,13 @@ __global__ void k_bases(Bufs b) {
     }
 }
 
-// Per-event offsets: event e's rows start at offsets[q_off + e] = 0.
-__global__ void __launch_bounds__(256) k_finalize(Bufs b) {
-    const BatchDesc bd = *b.bd;
-    int64_t *eo = b.out->offsets;
-    if (blockIdx.x == 0)
-        for (int e = threadIdx.x; e < bd.E; e += blockDim.x) eo[b.ev[e].q_off + e] = 0;
-    for (int c = blockIdx.x; c < bd.n_qchunks; c += gridDim.x) {
-        const Chunk ch = b.qchunks[c];
-        const int64_t base = b.bases[ch.ev];
-        for (int64_t g = ch.r0 + threadIdx.x; g < ch.r1; g += blockDim.x)
-            eo[g + ch.ev + 1] = b.offs[g + 1] - base;
-    }
-}
-
 // Writes the output descriptor from kernel arguments (so the values are
 // captured at launch time, unlike a copy from host memory).
-__global__ void k_set_out(OutDesc *dst, OutDesc v) {
-    if (threadIdx.x == 0) *dst = v;
+// Also writes each event's leading zero offset (offsets[q_off + e]), the
+// one per-event entry no query row writes.
+__global__ void k_set_out(Bufs b, OutDesc v) {
+    if (threadIdx.x == 0) *b.out = v;
+    for (int e = threadIdx.x; e < b.bd->E; e += blockDim.x) v.offsets[b.ev[e].q_off + e] = 0;
 }
 
 // --------------------------------------------------------------- launches
@@ -1124,9 +1177,9 @@ hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s
     return hipSuccess;
 }
 
-hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, hipStream_t s) {
-    if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_extent, dim3(std::min(nchunks, 8192)), dim3(256), 0, s, b, (int32_t)queries);
+hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, int64_t zero_n, hipStream_t s) {
+    const int blocks = std::max(1, std::min(std::max(nchunks, (int)((zero_n + 4095) / 4096)), 512));
+    hipLaunchKernelGGL(k_extent, dim3(blocks), dim3(256), 0, s, b, (int32_t)queries, zero_n);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1136,13 +1189,6 @@ hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s) {
                        0, s, b);
     FRNN_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_plan_offsets, dim3(1), dim3(256), 0, s, b);
-    FRNN_CHECK_LAUNCH();
-    return hipSuccess;
-}
-
-hipError_t launch_zero_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s) {
-    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((cells_cap + 1 + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_zero_cells, dim3(blocks), dim3(256), 0, s, b, (int32_t)queries);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1171,8 +1217,6 @@ static hipError_t launch_scan_mode(const Bufs &b, const Knobs &kn, int64_t n_cap
     const int nb = scan_blocks(n_cap);
     hipLaunchKernelGGL(k_scan_reduce<MODE>, dim3(nb), dim3(kScanThreads), 0, s, b, kn);
     FRNN_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_scan_parts<MODE>, dim3(1), dim3(1024), 0, s, b, (int32_t)nb);
-    FRNN_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_scan_apply<MODE>, dim3(nb), dim3(kScanThreads), 0, s, b, kn);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
@@ -1192,15 +1236,23 @@ template <bool FILL>
 static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
     blocks = (blocks + 7) / 8 * 8;  // whole XCD rounds (see the window remap)
     dim3 grid(blocks), block(64 * kWavesPerBlock);
+    // register-resident candidate chunks: the count pass evaluates every
+    // candidate; the fill pass only re-evaluates rows longer than the stash
+    constexpr int KR3 = 4, KR8 = 2, KR12 = 4, KRG = 2;
     switch (D) {
-    case 3: hipLaunchKernelGGL((k_query<3, true, FILL, 4>), grid, block, 0, s, b, kn); break;
-    case 8: hipLaunchKernelGGL((k_query<8, true, FILL, 4>), grid, block, 0, s, b, kn); break;
-    case 12: hipLaunchKernelGGL((k_query<12, true, FILL, 4>), grid, block, 0, s, b, kn); break;
+    case 3: hipLaunchKernelGGL((k_query<3, true, FILL, KR3>), grid, block, 0, s, b, kn); break;
+    case 8:
+        if constexpr (FILL)
+            hipLaunchKernelGGL((k_query<8, true, true, KR8>), grid, block, 0, s, b, kn);
+        else
+            hipLaunchKernelGGL((k_query_o5<8, true, false, KR8>), grid, block, 0, s, b, kn);
+        break;
+    case 12: hipLaunchKernelGGL((k_query<12, true, FILL, KR12>), grid, block, 0, s, b, kn); break;
     default:
         if (D <= 4)
-            hipLaunchKernelGGL((k_query<4, false, FILL, 4>), grid, block, 0, s, b, kn);
+            hipLaunchKernelGGL((k_query<4, false, FILL, KR3>), grid, block, 0, s, b, kn);
         else if (D <= 16)
-            hipLaunchKernelGGL((k_query<16, false, FILL, 2>), grid, block, 0, s, b, kn);
+            hipLaunchKernelGGL((k_query<16, false, FILL, KRG>), grid, block, 0, s, b, kn);
         else
             hipLaunchKernelGGL((k_query<32, false, FILL, 1>), grid, block, 0, s, b, kn);
     }
@@ -1216,21 +1268,6 @@ hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStr
     return launch_query_t<true>(b, kn, D, blocks, s);
 }
 
-hipError_t launch_stash_sort(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s) {
-    const int per = kn.stash_cap > 0 ? 256 / kn.stash_cap : 1;
-    const int64_t nvb = (int64_t)nqchunks * (kChunkRows / per);
-    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(nvb, 65536))), block(256);
-    switch (kn.stash_cap) {
-    case 0: return hipSuccess;
-    case 8: hipLaunchKernelGGL(k_stash_sort<8>, grid, block, 0, s, b, kn); break;
-    case 16: hipLaunchKernelGGL(k_stash_sort<16>, grid, block, 0, s, b, kn); break;
-    case 32: hipLaunchKernelGGL(k_stash_sort<32>, grid, block, 0, s, b, kn); break;
-    default: return hipErrorInvalidValue;
-    }
-    FRNN_CHECK_LAUNCH();
-    return hipSuccess;
-}
-
 hipError_t launch_bases(const Bufs &b, int E, hipStream_t s) {
     int blocks = std::max(1, std::min((E + 1 + 255) / 256, 64));
     hipLaunchKernelGGL(k_bases, dim3(blocks), dim3(256), 0, s, b);
@@ -1244,16 +1281,11 @@ hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStrea
     return hipSuccess;
 }
 
-hipError_t launch_set_out(OutDesc *dst, const OutDesc &v, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_out, dim3(1), dim3(64), 0, s, dst, v);
+hipError_t launch_set_out(const Bufs &b, const OutDesc &v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_out, dim3(1), dim3(256), 0, s, b, v);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
 
-hipError_t launch_finalize(const Bufs &b, int nqchunks, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(std::max(1, std::min(nqchunks, 8192))), dim3(256), 0, s, b);
-    FRNN_CHECK_LAUNCH();
-    return hipSuccess;
-}
 
 }  // namespace frnn

@@ -10,9 +10,9 @@
 namespace frnn {
 
 hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s);
-hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, hipStream_t s);
+// also clears zero_n cells of the (point or query) cell histogram
+hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, int64_t zero_n, hipStream_t s);
 hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s);
-hipError_t launch_zero_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s);
 hipError_t launch_keys(const Bufs &b, int nchunks, bool queries, hipStream_t s);
 hipError_t launch_scan_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s);
 hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t s);
@@ -21,10 +21,8 @@ hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t 
 hipError_t launch_count(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
 hipError_t launch_scan_rows(const Bufs &b, const Knobs &kn, int64_t total_q, hipStream_t s);
 hipError_t launch_bases(const Bufs &b, int E, hipStream_t s);
-hipError_t launch_stash_sort(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s);
 hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
 hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStream_t s);
-hipError_t launch_finalize(const Bufs &b, int nqchunks, hipStream_t s);
-hipError_t launch_set_out(OutDesc *dst, const OutDesc &v, hipStream_t s);
+hipError_t launch_set_out(const Bufs &b, const OutDesc &v, hipStream_t s);
 
 }  // namespace frnn

@@ -254,8 +254,8 @@ frnn_status Opts::validate(std::string *why) const {
     if (!(o.cells_per_point > 0.f) || !std::isfinite(o.cells_per_point)) return bad("cells_per_point must be > 0");
     if (o.cell_multiple < 1 || o.cell_multiple > 3) return bad("cell_multiple out of 1..3");
     if (o.cells_per_item < 1 || o.cells_per_item > 8) return bad("cells_per_item out of 1..8");
-    if (o.queries_per_item < 1 || o.queries_per_item > 256 || (o.queries_per_item & (o.queries_per_item - 1)))
-        return bad("queries_per_item must be a power of two in 1..256");
+    if (o.queries_per_item < 1 || o.queries_per_item > 64 || (o.queries_per_item & (o.queries_per_item - 1)))
+        return bad("queries_per_item must be a power of two in 1..64");
     if (o.blocks_per_cu < 1 || o.blocks_per_cu > 16) return bad("blocks_per_cu out of 1..16");
     if (o.row_cap_lds < 1 || o.row_cap_lds > kRowLds) return bad("row_cap_lds out of 1..512");
     if (o.stash_cap != 0 && o.stash_cap != 8 && o.stash_cap != 16 && o.stash_cap != 32)
@@ -380,9 +380,8 @@ frnn_status build_index(Index &ix, const float *const *points, const int64_t *n,
     b.scan_part = part.as<uint64_t>();
 
     LAUNCH("init", s, launch_init(b, E, D, true, s));
-    LAUNCH("extent", s, launch_extent(b, ix.n_pchunks, false, s));
+    LAUNCH("extent", s, launch_extent(b, ix.n_pchunks, false, ccap + 1, s));
     LAUNCH("plan", s, launch_plan(b, E, s));
-    LAUNCH("zero_cells", s, launch_zero_cells(b, ccap, false, s));
     LAUNCH("keys", s, launch_keys(b, ix.n_pchunks, false, s));
     LAUNCH("scan_cells", s, launch_scan_cells(b, ccap, false, s));
     LAUNCH("scatter", s, launch_scatter(b, ix.n_pchunks, false, s));
@@ -450,7 +449,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     const int64_t tq1 = std::max<int64_t>(1, totq);
     DevBuf desc(stage, s);
     DevBuf hv(sizeof(Counters) + sizeof(int64_t) * (E + 1), s);
-    DevBuf deg(sizeof(uint32_t) * tq1, s),
+    DevBuf deg(sizeof(uint32_t) * tq1, s), sdeg(sizeof(uint32_t) * tq1, s),
         offs(sizeof(int64_t) * (tq1 + 1), s), lofs(sizeof(int64_t) * (tq1 + 1), s),
         lrows(sizeof(uint32_t) * tq1, s), part(sizeof(uint64_t) * 2 * kScanBlocks, s),
         stash(sizeof(uint64_t) * tq1 * std::max(1, op.o.stash_cap), s),
@@ -488,6 +487,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     b.sqkey = selfq ? ix.skey.as<uint32_t>() : sqkey.as<uint32_t>();
     b.qcells = selfq ? ix.cells.as<uint32_t>() : qcells.as<uint32_t>();
     b.deg = deg.as<uint32_t>();
+    b.sdeg = sdeg.as<uint32_t>();
     b.offs = offs.as<int64_t>();
     b.lofs = lofs.as<int64_t>();
     b.long_rows = lrows.as<uint32_t>();
@@ -509,8 +509,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
 
     LAUNCH("init", s, launch_init(b, E, D, false, s));
     if (!selfq) {
-        LAUNCH("extent_q", s, launch_extent(b, nqc, true, s));
-        LAUNCH("zero_cells_q", s, launch_zero_cells(b, ix.cells_cap, true, s));
+        LAUNCH("extent_q", s, launch_extent(b, nqc, true, ix.cells_cap + 1, s));
         LAUNCH("keys_q", s, launch_keys(b, nqc, true, s));
         LAUNCH("scan_cells_q", s, launch_scan_cells(b, ix.cells_cap, true, s));
         LAUNCH("scatter_q", s, launch_scatter(b, nqc, true, s));
@@ -552,11 +551,9 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     DevBuf lkeys(sizeof(uint64_t) * std::max<uint64_t>(1, c.long_total), s);
     OutDesc od{reinterpret_cast<int64_t *>(ob), reinterpret_cast<int32_t *>(ob + b_off),
                want_d2 ? reinterpret_cast<float *>(ob + b_off + b_idx) : nullptr, lkeys.as<uint64_t>()};
-    LAUNCH("set_out", s, launch_set_out(b.out, od, s));
-    LAUNCH("stash_sort", s, launch_stash_sort(b, kn, nqc, s));
+    LAUNCH("set_out", s, launch_set_out(b, od, s));
     LAUNCH("fill", s, launch_fill(b, kn, D, qblocks, s));
     if (c.long_total) LAUNCH("long_sort", s, launch_long_sort(b, kn, 256, s));
-    LAUNCH("finalize", s, launch_finalize(b, nqc, s));
 
     own->refs = E;
     for (int e = 0; e < E; ++e) {

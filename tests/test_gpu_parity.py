@@ -141,7 +141,7 @@ def test_grid_options_same_output(orc, frnn):
                dict(cell_multiple=2, grid_axes_max=4), dict(cell_multiple=3, grid_axes_max=3),
                dict(cells_per_item=4), dict(queries_per_item=1), dict(queries_per_item=64),
                dict(persistent=0), dict(blocks_per_cu=1), dict(stash_cap=0), dict(stash_cap=8),
-               dict(stash_cap=32), dict(stash_cap=0, persistent=0), dict(queries_per_item=256),
+               dict(stash_cap=32), dict(stash_cap=0, persistent=0), dict(queries_per_item=8, persistent=1),
                dict(queries_per_item=2, cells_per_item=3)):
         got = gpu_csr(X, 0.1, 256, opts=frnn.default_opts(**kw))
         pinlib.assert_csr_equal(got, pinlib.as_tuple(want), f"opts {kw}")
