@@ -97,11 +97,11 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
         qcells.reset(sizeof(uint32_t) * (sh.cells_cap + 1), s);
     }
     deg.reset(sizeof(uint32_t) * sh.q_cap, s);
-    sdeg.reset(sizeof(uint32_t) * sh.q_cap, s);
     offs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
     lofs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
     lrows.reset(sizeof(uint32_t) * sh.q_cap, s);
     stash.reset(sizeof(uint64_t) * sh.q_cap * std::max(1, sh.o.stash_cap), s);
+    flist.reset(sizeof(uint32_t) * std::max<int64_t>(1, sh.qch_cap * (kChunkRows / sh.o.queries_per_item)), s);
     part.reset(sizeof(uint64_t) * 2 * kScanBlocks, s);
     outd.reset(sizeof(OutDesc), s);
 
@@ -127,11 +127,11 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     b.sqkey = selfq ? skey.as<uint32_t>() : sqkey.as<uint32_t>();
     b.qcells = selfq ? cells.as<uint32_t>() : qcells.as<uint32_t>();
     b.deg = deg.as<uint32_t>();
-    b.sdeg = sdeg.as<uint32_t>();
     b.offs = offs.as<int64_t>();
     b.lofs = lofs.as<int64_t>();
     b.long_rows = lrows.as<uint32_t>();
     b.stash = stash.as<uint64_t>();
+    b.fill_list = flist.as<uint32_t>();
     b.scan_part = part.as<uint64_t>();
     b.out = outd.as<OutDesc>();
     b.bases = reinterpret_cast<int64_t *>(hv.as<char>() + 2 * sizeof(Counters));
@@ -154,7 +154,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
 void BatchContext::retarget(hipStream_t s) {
     DevBuf *all[] = {&desc, &hv, &grid, &cell_off, &ext,
                      &xs, &perm, &key, &rank, &skey, &cells, &qs, &qperm, &qkey, &qrank, &sqkey,
-                     &qcells, &runs, &deg, &sdeg, &offs, &lofs, &lrows, &stash, &part, &outd};
+                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &stash, &flist, &part, &outd};
     for (DevBuf *d : all) d->set_stream(s);
 }
 
@@ -237,7 +237,8 @@ void BatchContext::launch_a(hipStream_t s) {
 }
 
 void BatchContext::launch_b(hipStream_t s) {
-    LAUNCH("fill", s, launch_fill(bq_, kn_, sh_.D, query_blocks(sh_.o, sh_.qch_cap), s));
+    LAUNCH("short_rows", s, launch_short_rows(bq_, kn_, sh_.qch_cap, s));
+    LAUNCH("fill", s, launch_fill(bq_, kn_, sh_.D, fill_blocks(sh_.qch_cap * (kChunkRows / sh_.o.queries_per_item)), s));
     LAUNCH("long_sort", s, launch_long_sort(bq_, kn_, 256, s));
 }
 

@@ -81,7 +81,7 @@ private:
     Bufs bb_{}, bq_{};  // build run and query run
     size_t o_ev_ = 0, o_pc_ = 0, o_qc_ = 0;
     DevBuf desc, hv, grid, cell_off, ext, xs, perm, key, rank,
-        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, sdeg, offs, lofs, lrows, stash, part, outd;
+        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, stash, flist, part, outd;
     Pinned stage_, back_;
     hipGraphExec_t ga_ = nullptr, gb_ = nullptr;
     hipGraph_t gra_ = nullptr, grb_ = nullptr;

@@ -73,9 +73,10 @@ struct Counters {
     uint32_t n_groups;     // cell-block groups evaluated by the count pass
     uint32_t n_long;       // rows sorted in global memory
     uint32_t status;       // kStatus* bits
-    uint32_t pad[9];
-    // persistent work queues: [pass][XCD], one 64-byte line each
-    uint32_t heads[2][8][16];
+    uint32_t n_fill;       // windows listed for the fill pass
+    uint32_t pad[8];
+    // persistent count-pass work queues, one per XCD, one 64-byte line each
+    uint32_t heads[8][16];
 };
 
 // One neighbour key run of a work group: offsets o[a] (a = 1..G-1) of the
@@ -136,11 +137,11 @@ struct Bufs {
     uint32_t *qkey, *qrank, *sqkey, *qcells;
     // rows
     uint32_t *deg;         // in-radius count per query (global row)
-    uint32_t *sdeg;        // the same count by sorted query slot
     int64_t *offs;         // [total_q+1] exclusive scan of capped counts
     int64_t *lofs;         // [total_q+1] exclusive scan of long-row lengths
     uint32_t *long_rows;
-    uint64_t *stash;       // [total_q][stash_cap] hit keys by sorted query slot
+    uint64_t *stash;       // [total_q][stash_cap] first hit keys per query (global row)
+    uint32_t *fill_list;   // windows holding rows longer than the stash
     uint64_t *scan_part;   // scan block partials (2 x kScanBlocks)
     OutDesc *out;
 };

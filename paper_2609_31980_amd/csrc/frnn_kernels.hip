@@ -3,10 +3,10 @@
 //
 // Pipeline (every size is read from device memory, see frnn_device.h):
 //   binning    k_init, k_extent (+ clears cells), k_plan, k_keys, scan, k_scatter
-//   work items k_items                       one item = queries of a cell block
-//   counting   k_query<count>, scan of the capped counts, k_bases
-//   filling    k_set_out, k_query<fill> (stashed rows, per-event offsets, long
-//              rows re-evaluated), k_long_sort
+//   counting   k_query<count> over windows of sorted queries, scan of the
+//              capped counts, k_bases
+//   filling    k_set_out, k_short_rows (per-event offsets, rows the stash
+//              holds), k_query<fill> (windows with longer rows), k_long_sort
 //
 // Exactness: the squared distance is computed in float32 as
 //   s = +0; for d in 0..D-1: t = q_d - x_d; u = t*t; s = s + u
@@ -741,6 +741,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     const uint32_t nwin = (uint32_t)bd.n_qchunks * wpc;
     uint64_t my_cand = 0;
     uint32_t my_groups = 0;
+    bool more = false;  // count pass: the window holds a row longer than the stash
 
     auto process_window = [&](uint32_t wid) {
         const uint32_t c = wid / wpc, sub = wid % wpc;
@@ -762,42 +763,10 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         const bool inw = lane < nwq;
         const uint32_t wkey = inw ? sqkey[p0 + lane] : 0u;
         const int32_t wperm = inw ? qperm[p0 + lane] : 0;
-        const uint32_t wdeg = (FILL && inw) ? b.sdeg[p0 + lane] : 0u;
+        const uint32_t wdeg = (FILL && inw) ? b.deg[q_off + wperm] : 0u;
         uint64_t need = ballot(inw);
         if (FILL) {
-            // per-event offsets of this window's rows, and the rows kept whole
-            // by the count pass: sorted here, SC lanes per row
-            const int64_t wqid = q_off + wperm;
-            int64_t woff = 0;
-            if (inw) {
-                woff = b.offs[wqid];
-                b.out->offsets[wqid + e + 1] = b.offs[wqid + 1] - b.bases[e];
-            }
-            if (SC > 0) {
-                const int rpp = 64 / (int)SC;  // rows per pass
-                const int gl = lane % (int)SC;
-                for (int t0 = 0; t0 < nwq; t0 += rpp) {
-                    const int t = t0 + lane / (int)SC;
-                    const uint32_t dq = (uint32_t)__shfl((int)wdeg, t);
-                    const int64_t off = __shfl((long long)woff, t);
-                    const bool mine = t < nwq && dq > 0 && dq <= SC;
-                    uint64_t v = (mine && gl < (int)dq) ? b.stash[(p0 + t) * SC + gl] : ~0ull;
-                    for (int kk = 2; kk <= (int)SC; kk <<= 1) {
-                        uint64_t o = shfl_xor64(v, kk - 1);
-                        v = (lane & (kk >> 1)) == 0 ? umin64(v, o) : umax64(v, o);
-                        for (int j = kk >> 2; j >= 1; j >>= 1) {
-                            o = shfl_xor64(v, j);
-                            v = (lane & j) == 0 ? umin64(v, o) : umax64(v, o);
-                        }
-                    }
-                    const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
-                    if (mine && gl < (int)keep) {
-                        out_idx[off + gl] = (int32_t)(uint32_t)v;
-                        if (out_d2) out_d2[off + gl] = __uint_as_float((uint32_t)(v >> 32));
-                    }
-                }
-            }
-            need = ballot(inw && wdeg > SC);  // rows to evaluate again
+            need = ballot(inw && wdeg > SC);  // rows the stash did not hold
             if (!need) return;
         }
         {
@@ -940,7 +909,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 if (!FILL) {
                     // count; the first stash_cap hit keys are kept for the fill
                     uint32_t cnt = 0;
-                    uint64_t *st = b.stash + qp * SC;
+                    uint64_t *st = b.stash + qid * SC;
                     auto tally = [&](uint64_t hm, float s, uint32_t j) {
                         if (hm) {
                             if ((hm >> lane) & 1) {
@@ -969,10 +938,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                         const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == (uint32_t)qp);
                         tally(ballot(hit), s, hit ? (uint32_t)b.perm[pos] : 0u);
                     }
-                    if (lane == 0) {
-                        b.deg[qid] = cnt;
-                        b.sdeg[qp] = cnt;
-                    }
+                    if (lane == 0) b.deg[qid] = cnt;
+                    more = more || cnt > SC;
                     my_cand += total;
                 } else {
                     const uint32_t dq = (uint32_t)__builtin_amdgcn_readlane((int)wdeg, t);
@@ -1034,16 +1001,24 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
             }
             wave_lds_sync();
         }
+        if (!FILL && more) {
+            if (lane == 0) b.fill_list[atomicAdd(&b.ctr->n_fill, 1u)] = wid;
+            more = false;
+        }
     };
 
-    if (kn.persistent) {
-        const int pass = FILL ? 1 : 0;
+    if (FILL) {
+        // the listed windows, grid-strided
+        const uint32_t n = b.ctr->n_fill;
+        const uint32_t nw = gridDim.x * kWavesPerBlock;
+        for (uint32_t i = blockIdx.x * kWavesPerBlock + w; i < n; i += nw) process_window(b.fill_list[i]);
+    } else if (kn.persistent) {
         const int x0 = blockIdx.x & 7;
         for (int qx = 0; qx < 8; ++qx) {
             const int x = (x0 + qx) & 7;
             const uint32_t lo = (uint32_t)((uint64_t)nwin * x / 8);
             const uint32_t hi = (uint32_t)((uint64_t)nwin * (x + 1) / 8);
-            uint32_t *head = &b.ctr->heads[pass][x][0];
+            uint32_t *head = &b.ctr->heads[x][0];
             for (;;) {
                 // a plain read first: a drained queue needs no atomic
                 if (lo + uniform(__atomic_load_n(head, __ATOMIC_RELAXED)) >= hi) break;
@@ -1091,6 +1066,113 @@ __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
 template <int DT, bool EXACT_D, bool FILL, int KR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_query_o5(Bufs b, Knobs kn) {
     query_body<DT, EXACT_D, FILL, KR>(b, kn);
+}
+
+// ------------------------------------------------------------ short rows
+// Ascending bitonic network over N keys held in registers (compile-time
+// indices: no cross-lane traffic).
+template <int N>
+__device__ __forceinline__ void sort_regs(uint64_t (&v)[N]) {
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t a = v[i], c = v[l];
+                    const bool sw = ((i & k) == 0) ? (a > c) : (a < c);
+                    v[i] = sw ? c : a;
+                    v[l] = sw ? a : c;
+                }
+            }
+        }
+    }
+}
+
+// Every row's per-event offset, and the rows the count pass kept whole
+// (0 < length <= SC): one lane per query row, in output order, sorts the
+// row's keys in registers.  The query chunks partition each event's rows, so
+// chunk c covers global rows r0..r1-1 of one event and its output is the
+// contiguous range offs[r0]..offs[r1]; one block per chunk.  When that range
+// fits in LDS the rows are assembled there and written out coalesced; the
+// places of longer rows receive filler that the fill pass, which runs later
+// on the same stream, overwrites.
+constexpr int kShortStage = kChunkRows * 16;  // staged output pairs per block
+
+template <int N>
+__device__ __forceinline__ void place_row(uint64_t (&v)[N], uint32_t keep, bool staged, int64_t rel,
+                                          uint32_t *sidx, float *sd2, int32_t *oi, float *od) {
+    sort_regs<N>(v);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if ((uint32_t)i < keep) {
+            const uint32_t j = (uint32_t)v[i];
+            const float d = __uint_as_float((uint32_t)(v[i] >> 32));
+            if (staged) {
+                sidx[rel + i] = j;
+                sd2[rel + i] = d;
+            } else {
+                oi[i] = (int32_t)j;
+                if (od) od[i] = d;
+            }
+        }
+    }
+}
+
+template <int SC>
+__global__ void __launch_bounds__(kChunkRows) k_short_rows(Bufs b, Knobs kn) {
+    __shared__ uint32_t sidx[SC > 0 ? kShortStage : 1];
+    __shared__ float sd2[SC > 0 ? kShortStage : 1];
+    if (blockIdx.x >= (unsigned)b.bd->n_qchunks) return;
+    const Chunk ch = b.qchunks[blockIdx.x];
+    const int64_t qid = ch.r0 + (int64_t)threadIdx.x;
+    const bool row = qid < ch.r1;
+    const int e = ch.ev;
+    const int64_t off = row ? b.offs[qid] : 0;
+    if (row) b.out->offsets[qid + e + 1] = b.offs[qid + 1] - b.bases[e];
+    if constexpr (SC > 0) {
+        const int64_t base = b.offs[ch.r0];
+        const int64_t len = b.offs[ch.r1] - base;
+        const bool staged = len <= kShortStage;
+        int32_t *oi = b.out->indices + off;
+        float *od = b.out->dist2 ? b.out->dist2 + off : nullptr;
+        const uint32_t dq = row ? b.deg[qid] : 0u;
+        const bool mine = dq > 0 && dq <= (uint32_t)SC;
+        const bool full = ballot(mine && dq > (uint32_t)(SC / 2)) != 0;  // network size, per wave
+        if (mine) {
+            const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
+            const uint64_t *st = b.stash + qid * SC;
+            auto load = [&](auto &v, int n) {
+#pragma unroll
+                for (int i = 0; i < n; i += 2) {
+                    ulonglong2 t = make_ulonglong2(~0ull, ~0ull);
+                    if ((uint32_t)i < dq) t = *reinterpret_cast<const ulonglong2 *>(st + i);
+                    v[i] = t.x;
+                    v[i + 1] = (uint32_t)(i + 1) < dq ? t.y : ~0ull;
+                }
+            };
+            if (full) {
+                uint64_t v[SC];
+                load(v, SC);
+                place_row<SC>(v, keep, staged, off - base, sidx, sd2, oi, od);
+            } else {
+                uint64_t v[SC / 2];
+                load(v, SC / 2);
+                place_row<SC / 2>(v, keep, staged, off - base, sidx, sd2, oi, od);
+            }
+        }
+        if (staged) {
+            __syncthreads();
+            int32_t *gi = b.out->indices + base;
+            float *gd = b.out->dist2 ? b.out->dist2 + base : nullptr;
+            for (int i = threadIdx.x; i < (int)len; i += kChunkRows) {
+                gi[i] = (int32_t)sidx[i];
+                if (gd) gd[i] = sd2[i];
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------ long rows
@@ -1208,7 +1290,7 @@ hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t 
 }
 
 static int scan_blocks(int64_t n_cap) {
-    int64_t nb = (n_cap + 4095) / 4096;
+    int64_t nb = (n_cap + kScanThreads * kScanItems - 1) / (kScanThreads * kScanItems);
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, kScanBlocks));
 }
 
@@ -1238,7 +1320,7 @@ static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int bloc
     dim3 grid(blocks), block(64 * kWavesPerBlock);
     // register-resident candidate chunks: the count pass evaluates every
     // candidate; the fill pass only re-evaluates rows longer than the stash
-    constexpr int KR3 = 4, KR8 = 2, KR12 = 4, KRG = 2;
+    constexpr int KR3 = FILL ? 1 : 4, KR8 = FILL ? 1 : 2, KR12 = FILL ? 1 : 4, KRG = FILL ? 1 : 2;
     switch (D) {
     case 3: hipLaunchKernelGGL((k_query<3, true, FILL, KR3>), grid, block, 0, s, b, kn); break;
     case 8:
@@ -1266,6 +1348,20 @@ hipError_t launch_count(const Bufs &b, const Knobs &kn, int D, int blocks, hipSt
 
 hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
     return launch_query_t<true>(b, kn, D, blocks, s);
+}
+
+hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s) {
+    static_assert(kChunkRows == 256, "one block per chunk");
+    dim3 grid(std::max(1, nqchunks)), block(kChunkRows);
+    switch (kn.stash_cap) {
+    case 0: hipLaunchKernelGGL(k_short_rows<0>, grid, block, 0, s, b, kn); break;
+    case 8: hipLaunchKernelGGL(k_short_rows<8>, grid, block, 0, s, b, kn); break;
+    case 16: hipLaunchKernelGGL(k_short_rows<16>, grid, block, 0, s, b, kn); break;
+    case 32: hipLaunchKernelGGL(k_short_rows<32>, grid, block, 0, s, b, kn); break;
+    default: return hipErrorInvalidValue;
+    }
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
 }
 
 hipError_t launch_bases(const Bufs &b, int E, hipStream_t s) {

@@ -21,6 +21,10 @@ hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t 
 hipError_t launch_count(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
 hipError_t launch_scan_rows(const Bufs &b, const Knobs &kn, int64_t total_q, hipStream_t s);
 hipError_t launch_bases(const Bufs &b, int E, hipStream_t s);
+// rows of at most stash_cap pairs, and every row's per-event offset: one
+// block per query chunk
+hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s);
+// the windows listed by the count pass; any grid size is correct
 hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
 hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStream_t s);
 hipError_t launch_set_out(const Bufs &b, const OutDesc &v, hipStream_t s);

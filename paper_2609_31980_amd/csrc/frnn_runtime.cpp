@@ -288,8 +288,14 @@ static int64_t cell_cap_of(int64_t n, float cpp) {
     return (int64_t)c;
 }
 
-// Workgroups of the count and fill kernels: the resident grid when
-// persistent, else one wave per window of sorted queries.
+// Workgroups of the fill kernel: one wave per listed window, at most 4096
+// blocks (the waves stride over the rest).
+int fill_blocks(int64_t windows) {
+    return (int)std::min<int64_t>(std::max<int64_t>(8, (windows + kWavesPerBlock - 1) / kWavesPerBlock), 4096);
+}
+
+// Workgroups of the count kernel: the resident grid when persistent, else
+// one wave per window of sorted queries.
 int query_blocks(const frnn_opts &o, int64_t nqchunks) {
     if (o.persistent) return 256 * o.blocks_per_cu;
     const int64_t windows = nqchunks * (kChunkRows / o.queries_per_item);
@@ -449,10 +455,11 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     const int64_t tq1 = std::max<int64_t>(1, totq);
     DevBuf desc(stage, s);
     DevBuf hv(sizeof(Counters) + sizeof(int64_t) * (E + 1), s);
-    DevBuf deg(sizeof(uint32_t) * tq1, s), sdeg(sizeof(uint32_t) * tq1, s),
+    DevBuf deg(sizeof(uint32_t) * tq1, s),
         offs(sizeof(int64_t) * (tq1 + 1), s), lofs(sizeof(int64_t) * (tq1 + 1), s),
         lrows(sizeof(uint32_t) * tq1, s), part(sizeof(uint64_t) * 2 * kScanBlocks, s),
         stash(sizeof(uint64_t) * tq1 * std::max(1, op.o.stash_cap), s),
+        flist(sizeof(uint32_t) * std::max<int64_t>(1, (int64_t)nqc * (kChunkRows / op.o.queries_per_item)), s),
         outd(sizeof(OutDesc), s);
     DevBuf qs, qperm, qkey, qrank, sqkey, qcells;
     if (!selfq) {
@@ -487,11 +494,11 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     b.sqkey = selfq ? ix.skey.as<uint32_t>() : sqkey.as<uint32_t>();
     b.qcells = selfq ? ix.cells.as<uint32_t>() : qcells.as<uint32_t>();
     b.deg = deg.as<uint32_t>();
-    b.sdeg = sdeg.as<uint32_t>();
     b.offs = offs.as<int64_t>();
     b.lofs = lofs.as<int64_t>();
     b.long_rows = lrows.as<uint32_t>();
     b.stash = stash.as<uint64_t>();
+    b.fill_list = flist.as<uint32_t>();
     b.scan_part = part.as<uint64_t>();
     b.out = outd.as<OutDesc>();
 
@@ -552,7 +559,8 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     OutDesc od{reinterpret_cast<int64_t *>(ob), reinterpret_cast<int32_t *>(ob + b_off),
                want_d2 ? reinterpret_cast<float *>(ob + b_off + b_idx) : nullptr, lkeys.as<uint64_t>()};
     LAUNCH("set_out", s, launch_set_out(b, od, s));
-    LAUNCH("fill", s, launch_fill(b, kn, D, qblocks, s));
+    LAUNCH("short_rows", s, launch_short_rows(b, kn, nqc, s));
+    if (c.n_fill) LAUNCH("fill", s, launch_fill(b, kn, D, fill_blocks(c.n_fill), s));
     if (c.long_total) LAUNCH("long_sort", s, launch_long_sort(b, kn, 256, s));
 
     own->refs = E;

@@ -186,6 +186,8 @@ int prof_read(frnn_kernel_time *out, int cap, bool reset);
 
 float r2_of(float r);
 int query_blocks(const frnn_opts &o, int64_t nqchunks);
+// grid of the fill pass over `windows` listed windows (it strides past 4096 blocks)
+int fill_blocks(int64_t windows);
 
 // Graph capture in progress on this thread (per-launch timing is skipped).
 void set_capturing(bool on);
