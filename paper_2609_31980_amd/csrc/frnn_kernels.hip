@@ -874,129 +874,151 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
             }
             if (lane == 0) L.run_pref[nruns] = total;
             wave_lds_sync();
-            // the first KR*64 candidates stay in registers for every query
-            CandRow<DT> xr[KR];
-            uint32_t pr[KR], pj[KR];
-            uint64_t vmask[KR];  // lanes holding a candidate, per register chunk
+            if constexpr (!FILL) {
+                // count: candidates in chunks of 64 (one per lane), every query
+                // of the group against each chunk while the next chunk loads;
+                // lane t keeps the running count of window query t
+                uint32_t cntv = 0;
+                uint32_t pn = 0, jn = 0;
+                CandRow<DT> xn;
+                auto fetch = [&](uint32_t v0) {
+                    const uint32_t v = v0 + lane;
+                    pn = v < total ? locate(L, nruns, v) : 0u;
+                    load_row<DT, EXACT_D>(xn, b.xs + (int64_t)pn * Dp, D);
+                    jn = (uint32_t)b.perm[pn];
+                };
+                if (total > 0) fetch(0);
+                // fetch the next group's runs while this one is evaluated
+                if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nln);
+                for (uint32_t v0 = 0; v0 < total; v0 += 64) {
+                    const uint32_t pos = pn, j = jn;
+                    const CandRow<DT> x = xn;
+                    const bool valid = v0 + lane < total;
+                    if (v0 + 64 < total) fetch(v0 + 64);
+                    for (int t = gb; t < ge; ++t) {
+                        QueryRow<DT> qr;
 #pragma unroll
-            for (int k = 0; k < KR; ++k) {
-                const uint32_t v = k * 64 + lane;
-                vmask[k] = ballot(v < total);
-                pr[k] = 0;
-                pj[k] = 0;
-                if (k * 64 < (int)total) {
-                    pr[k] = v < total ? locate(L, nruns, v) : 0u;
-                    load_row<DT, EXACT_D>(xr[k], b.xs + (int64_t)pr[k] * Dp, D);
-                    pj[k] = (uint32_t)b.perm[pr[k]];
-                }
-            }
-            // fetch the next group's runs while this one is evaluated
-            if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nln);
-            for (int t = gb; t < ge; ++t) {
-                const int64_t qp = p0 + t;
-                QueryRow<DT> qr;
-#pragma unroll
-                for (int d4 = 0; d4 < DP; d4 += 4) {
-                    if (EXACT_D || d4 < Dp) {
-                        const float4 v = sq[w][t * (Dp / 4) + d4 / 4];
-                        qr.q[d4] = v.x;
-                        if (d4 + 1 < DT) qr.q[d4 + 1] = v.y;
-                        if (d4 + 2 < DT) qr.q[d4 + 2] = v.z;
-                        if (d4 + 3 < DT) qr.q[d4 + 3] = v.w;
-                    }
-                }
-                const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
-                if (!FILL) {
-                    // count; the first stash_cap hit keys are kept for the fill
-                    uint32_t cnt = 0;
-                    uint64_t *st = b.stash + qid * SC;
-                    auto tally = [&](uint64_t hm, float s, uint32_t j) {
-                        if (hm) {
-                            if ((hm >> lane) & 1) {
-                                const uint32_t slot = cnt + lanes_below(hm);
-                                if (slot < SC) st[slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                        for (int d4 = 0; d4 < DP; d4 += 4) {
+                            if (EXACT_D || d4 < Dp) {
+                                const float4 v = sq[w][t * (Dp / 4) + d4 / 4];
+                                qr.q[d4] = v.x;
+                                if (d4 + 1 < DT) qr.q[d4 + 1] = v.y;
+                                if (d4 + 2 < DT) qr.q[d4 + 2] = v.z;
+                                if (d4 + 3 < DT) qr.q[d4 + 3] = v.w;
                             }
-                            cnt += (uint32_t)__popcll(hm);
                         }
-                    };
-#pragma unroll
-                    for (int k = 0; k < KR; ++k) {
-                        if (k * 64 < (int)total) {
-                            const float s = dist2<DT, EXACT_D>(qr, xr[k], D);
-                            uint64_t hm = ballot(s <= r2) & vmask[k];
-                            if (kn.exclude_self) hm &= ~ballot(pr[k] == (uint32_t)qp);
-                            tally(hm, s, pj[k]);
-                        }
-                    }
-                    for (uint32_t v0 = KR * 64; v0 < total; v0 += 64) {
-                        const uint32_t v = v0 + lane;
-                        const bool valid = v < total;
-                        const uint32_t pos = valid ? locate(L, nruns, v) : 0u;
-                        CandRow<DT> x;
-                        load_row<DT, EXACT_D>(x, b.xs + (int64_t)pos * Dp, D);
                         const float s = dist2<DT, EXACT_D>(qr, x, D);
-                        const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == (uint32_t)qp);
-                        tally(ballot(hit), s, hit ? (uint32_t)b.perm[pos] : 0u);
-                    }
-                    if (lane == 0) b.deg[qid] = cnt;
-                    more = more || cnt > SC;
-                    my_cand += total;
-                } else {
-                    const uint32_t dq = (uint32_t)__builtin_amdgcn_readlane((int)wdeg, t);
-                    if (dq <= SC) continue;  // sorted from the stash
-                    const int64_t off = b.offs[qid];
-                    const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
-                    const bool lng = dq > (uint32_t)kn.long_cap;
-                    uint64_t *dst = lng ? long_keys + b.lofs[qid] : &shits[w][0];
-                    uint32_t nh = 0;
-                    auto emit = [&](uint64_t hm, float s, uint32_t j) {
+                        bool hit = valid && s <= r2;
+                        if (kn.exclude_self) hit = hit && pos != (uint32_t)(p0 + t);
+                        const uint64_t hm = ballot(hit);
                         if (hm) {
-                            if ((hm >> lane) & 1) {
-                                const uint32_t slot = nh + lanes_below(hm);
-                                if (slot < dq) dst[slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                            const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cntv, t);
+                            // the first SC hit keys of each query go to its stash row
+                            if (c < SC && hit) {
+                                const uint32_t slot = c + lanes_below(hm);
+                                if (slot < SC) {
+                                    const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
+                                    b.stash[qid * SC + slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                                }
                             }
-                            nh += (uint32_t)__popcll(hm);
+                            if (lane == t) cntv = c + (uint32_t)__popcll(hm);
                         }
-                    };
+                    }
+                }
+                const bool mine = lane >= gb && lane < ge;
+                if (mine) b.deg[q_off + wperm] = cntv;
+                more = more || ballot(mine && cntv > SC) != 0;
+                my_cand += (uint64_t)total * (uint64_t)(ge - gb);
+            } else {
+                // the first KR*64 candidates stay in registers for every query
+                CandRow<DT> xr[KR];
+                uint32_t pr[KR], pj[KR];
+                uint64_t vmask[KR];  // lanes holding a candidate, per register chunk
 #pragma unroll
-                    for (int k = 0; k < KR; ++k) {
-                        if (k * 64 < (int)total) {
-                            const float s = dist2<DT, EXACT_D>(qr, xr[k], D);
-                            uint64_t hm = ballot(s <= r2) & vmask[k];
-                            if (kn.exclude_self) hm &= ~ballot(pr[k] == (uint32_t)qp);
-                            emit(hm, s, pj[k]);
+                for (int k = 0; k < KR; ++k) {
+                    const uint32_t v = k * 64 + lane;
+                    vmask[k] = ballot(v < total);
+                    pr[k] = 0;
+                    pj[k] = 0;
+                    if (k * 64 < (int)total) {
+                        pr[k] = v < total ? locate(L, nruns, v) : 0u;
+                        load_row<DT, EXACT_D>(xr[k], b.xs + (int64_t)pr[k] * Dp, D);
+                        pj[k] = (uint32_t)b.perm[pr[k]];
+                    }
+                }
+                // fetch the next group's runs while this one is evaluated
+                if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nln);
+                for (int t = gb; t < ge; ++t) {
+                    const int64_t qp = p0 + t;
+                    QueryRow<DT> qr;
+#pragma unroll
+                    for (int d4 = 0; d4 < DP; d4 += 4) {
+                        if (EXACT_D || d4 < Dp) {
+                            const float4 v = sq[w][t * (Dp / 4) + d4 / 4];
+                            qr.q[d4] = v.x;
+                            if (d4 + 1 < DT) qr.q[d4 + 1] = v.y;
+                            if (d4 + 2 < DT) qr.q[d4 + 2] = v.z;
+                            if (d4 + 3 < DT) qr.q[d4 + 3] = v.w;
                         }
                     }
-                    for (uint32_t v0 = KR * 64; v0 < total; v0 += 64) {
-                        const uint32_t v = v0 + lane;
-                        const bool valid = v < total;
-                        const uint32_t pos = valid ? locate(L, nruns, v) : 0u;
-                        CandRow<DT> x;
-                        load_row<DT, EXACT_D>(x, b.xs + (int64_t)pos * Dp, D);
-                        const float s = dist2<DT, EXACT_D>(qr, x, D);
-                        const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == (uint32_t)qp);
-                        emit(ballot(hit), s, hit ? (uint32_t)b.perm[pos] : 0u);
-                    }
-                    if (nh != dq && lane == 0) atomicOr(&b.ctr->status, kStatusInternal);
-                    if (lng) {
-                        if (lane == 0) {
-                            const uint32_t li = atomicAdd(&b.ctr->n_long, 1u);
-                            b.long_rows[li] = (uint32_t)qid;
+                    const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
+                    {
+                        const uint32_t dq = (uint32_t)__builtin_amdgcn_readlane((int)wdeg, t);
+                        if (dq <= SC) continue;  // sorted from the stash
+                        const int64_t off = b.offs[qid];
+                        const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
+                        const bool lng = dq > (uint32_t)kn.long_cap;
+                        uint64_t *dst = lng ? long_keys + b.lofs[qid] : &shits[w][0];
+                        uint32_t nh = 0;
+                        auto emit = [&](uint64_t hm, float s, uint32_t j) {
+                            if (hm) {
+                                if ((hm >> lane) & 1) {
+                                    const uint32_t slot = nh + lanes_below(hm);
+                                    if (slot < dq) dst[slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                                }
+                                nh += (uint32_t)__popcll(hm);
+                            }
+                        };
+#pragma unroll
+                        for (int k = 0; k < KR; ++k) {
+                            if (k * 64 < (int)total) {
+                                const float s = dist2<DT, EXACT_D>(qr, xr[k], D);
+                                uint64_t hm = ballot(s <= r2) & vmask[k];
+                                if (kn.exclude_self) hm &= ~ballot(pr[k] == (uint32_t)qp);
+                                emit(hm, s, pj[k]);
+                            }
                         }
-                        continue;
+                        for (uint32_t v0 = KR * 64; v0 < total; v0 += 64) {
+                            const uint32_t v = v0 + lane;
+                            const bool valid = v < total;
+                            const uint32_t pos = valid ? locate(L, nruns, v) : 0u;
+                            CandRow<DT> x;
+                            load_row<DT, EXACT_D>(x, b.xs + (int64_t)pos * Dp, D);
+                            const float s = dist2<DT, EXACT_D>(qr, x, D);
+                            const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == (uint32_t)qp);
+                            emit(ballot(hit), s, hit ? (uint32_t)b.perm[pos] : 0u);
+                        }
+                        if (nh != dq && lane == 0) atomicOr(&b.ctr->status, kStatusInternal);
+                        if (lng) {
+                            if (lane == 0) {
+                                const uint32_t li = atomicAdd(&b.ctr->n_long, 1u);
+                                b.long_rows[li] = (uint32_t)qid;
+                            }
+                            continue;
+                        }
+                        wave_lds_sync();
+                        int32_t *oi = out_idx + off;
+                        float *od = out_d2 ? out_d2 + off : nullptr;
+                        if (dq <= 64)
+                            sort_and_write<1>(&shits[w][0], dq, keep, oi, od, lane);
+                        else if (dq <= 128)
+                            sort_and_write<2>(&shits[w][0], dq, keep, oi, od, lane);
+                        else if (dq <= 256)
+                            sort_and_write<4>(&shits[w][0], dq, keep, oi, od, lane);
+                        else
+                            sort_and_write<8>(&shits[w][0], dq, keep, oi, od, lane);
+                        wave_lds_sync();
                     }
-                    wave_lds_sync();
-                    int32_t *oi = out_idx + off;
-                    float *od = out_d2 ? out_d2 + off : nullptr;
-                    if (dq <= 64)
-                        sort_and_write<1>(&shits[w][0], dq, keep, oi, od, lane);
-                    else if (dq <= 128)
-                        sort_and_write<2>(&shits[w][0], dq, keep, oi, od, lane);
-                    else if (dq <= 256)
-                        sort_and_write<4>(&shits[w][0], dq, keep, oi, od, lane);
-                    else
-                        sort_and_write<8>(&shits[w][0], dq, keep, oi, od, lane);
-                    wave_lds_sync();
                 }
             }
             wave_lds_sync();
