@@ -28,7 +28,7 @@ namespace frnn {
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -656,6 +656,7 @@ __device__ __forceinline__ float dist2(const QueryRow<DT> &qr, const CandRow<DT>
 struct WaveLds {
     uint32_t run_base[kRunsMax];
     uint32_t run_pref[kRunsMax + 1];
+    unsigned long long starts;  // run starts inside the current chunk (bit per lane); zero between uses
 };
 
 // Position of candidate v (0 <= v < L) among the group's concatenated runs.
@@ -719,6 +720,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
     WaveLds &L = slds[w];
+    if (lane_id() == 0) L.starts = 0;
+    wave_lds_sync();
     const BatchDesc &bd = *b.bd;
     const int D = EXACT_D ? DT : bd.D;
     const int Dp = EXACT_D ? DP : bd.Dp;
@@ -881,9 +884,27 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 uint32_t cntv = 0;
                 uint32_t pn = 0, jn = 0;
                 CandRow<DT> xn;
+                // with at most 64 runs, lane s holds run s's first candidate
+                // number; a candidate's run is the number of runs starting at
+                // or before it, minus one (runs are non-empty, so their
+                // starts are distinct), counted with one 64-bit word of run
+                // starts per chunk
+                const bool few = nruns <= 64;
+                const uint32_t rp = (few && lane < nruns) ? L.run_pref[lane] : 0xffffffffu;
                 auto fetch = [&](uint32_t v0) {
                     const uint32_t v = v0 + lane;
-                    pn = v < total ? locate(L, nruns, v) : 0u;
+                    if (few) {
+                        if (rp >= v0 && rp - v0 < 64u) atomicOr(&L.starts, 1ull << (rp - v0));
+                        wave_lds_sync();
+                        const uint64_t sm = L.starts;
+                        wave_lds_sync();
+                        if (lane == 0) L.starts = 0;
+                        const uint32_t before = (uint32_t)__popcll(ballot(rp < v0));
+                        const uint32_t kr = before + lanes_below(sm) + (uint32_t)((sm >> lane) & 1ull) - 1u;
+                        pn = v < total ? L.run_base[kr] + (v - L.run_pref[kr]) : 0u;
+                    } else {
+                        pn = v < total ? locate(L, nruns, v) : 0u;
+                    }
                     load_row<DT, EXACT_D>(xn, b.xs + (int64_t)pn * Dp, D);
                     jn = (uint32_t)b.perm[pn];
                 };
@@ -908,8 +929,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                             }
                         }
                         const float s = dist2<DT, EXACT_D>(qr, x, D);
-                        bool hit = valid && s <= r2;
-                        if (kn.exclude_self) hit = hit && pos != (uint32_t)(p0 + t);
+                        const uint32_t self_slot = kn.exclude_self ? (uint32_t)(p0 + t) : 0xffffffffu;
+                        const bool hit = valid && s <= r2 && pos != self_slot;
                         const uint64_t hm = ballot(hit);
                         if (hm) {
                             const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cntv, t);
