@@ -148,21 +148,44 @@ __global__ void k_init(Bufs b, int32_t init_ext) {
 
 // ---------------------------------------------------------------- extent
 // Per-event per-axis min / max of the points and a finiteness check
-// (queries: finiteness only).  Thread t of a block always reads axis t % D.
-// A block keeps its running min / max across the chunks it takes and
-// publishes them (LDS, then one global atomic per axis) only when the event
-// changes, so few atomics meet on the same address.  The same launch clears
-// the cell histogram for the capacity of the run.
-__device__ __forceinline__ void flush_extent(Bufs &b, int ev, int D, int t, int stride, uint32_t mn,
-                                             uint32_t mx, uint32_t *smin, uint32_t *smax) {
+// (queries: finiteness only).  A block keeps running min / max across the
+// chunks it takes and publishes them (LDS, then one global atomic per axis)
+// only when the event changes.  Rows are read as 16-byte vectors when the
+// event's array is 16-byte aligned: thread t takes vector t + k*T4 of a
+// chunk, and since 4*T4 is a multiple of D each of its four lanes always
+// holds the same axis.  The same launch clears the cell histogram for the
+// capacity of the run.
+struct ExtentAcc {
+    uint32_t mn[4], mx[4];  // 16-byte path, axes ax[j]
+    int ax[4];
+    uint32_t smn, smx;      // unaligned path, axis t % D
+    __device__ void reset() {
+        for (int j = 0; j < 4; ++j) {
+            mn[j] = 0xffffffffu;
+            mx[j] = 0u;
+        }
+        smn = 0xffffffffu;
+        smx = 0u;
+    }
+};
+
+__device__ __forceinline__ void flush_extent(Bufs &b, int ev, int D, int t, int T4, int stride,
+                                             ExtentAcc &acc, uint32_t *smin, uint32_t *smax) {
     if (t < kDMax) {
         smin[t] = 0xffffffffu;
         smax[t] = 0u;
     }
     __syncthreads();
+    if (t < T4) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            atomicMin(&smin[acc.ax[j]], acc.mn[j]);
+            atomicMax(&smax[acc.ax[j]], acc.mx[j]);
+        }
+    }
     if (t < stride) {
-        atomicMin(&smin[t % D], mn);
-        atomicMax(&smax[t % D], mx);
+        atomicMin(&smin[t % D], acc.smn);
+        atomicMax(&smax[t % D], acc.smx);
     }
     __syncthreads();
     if (t < D) {
@@ -170,6 +193,7 @@ __device__ __forceinline__ void flush_extent(Bufs &b, int ev, int D, int t, int 
         atomicMax(&b.ext[((int64_t)ev * 2 + 1) * D + t], smax[t]);
     }
     __syncthreads();
+    acc.reset();
 }
 
 __global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries, int64_t zero_n) {
@@ -180,39 +204,83 @@ __global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries, int64_t
     const int nch = queries ? bd.n_qchunks : bd.n_pchunks;
     const Chunk *chunks = queries ? b.qchunks : b.pchunks;
     const int stride = (256 / D) * D;
+    int L = 4;  // lcm(4, D) floats
+    while (L % D) L += 4;
+    const int T4 = (256 / (L / 4)) * (L / 4);  // threads of the 16-byte path; 4*T4 is a multiple of D
     const int t = threadIdx.x;
     // clear the cell histogram (zero_n cells, the capacity)
     uint32_t *cells = queries ? b.qcells : b.cells;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + t; i < zero_n; i += (int64_t)gridDim.x * blockDim.x)
-        cells[i] = 0u;
+    {
+        const int64_t gt = (int64_t)blockIdx.x * blockDim.x + t, gs = (int64_t)gridDim.x * blockDim.x;
+        const int64_t n4 = zero_n / 4;
+        for (int64_t i = gt; i < n4; i += gs) reinterpret_cast<uint4 *>(cells)[i] = make_uint4(0u, 0u, 0u, 0u);
+        for (int64_t i = 4 * n4 + gt; i < zero_n; i += gs) cells[i] = 0u;
+    }
     if (t == 0) sbad = 0;
     __syncthreads();
-    uint32_t mn = 0xffffffffu, mx = 0u;
+    ExtentAcc acc;
+    acc.reset();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc.ax[j] = (4 * t + j) % D;
     bool bad = false;
     int cur = -1;
+    auto fold = [&](uint32_t &mn, uint32_t &mx, float x) {
+        bad |= !finite32(x);
+        const uint32_t o = f2ord(x);
+        mn = o < mn ? o : mn;
+        mx = o > mx ? o : mx;
+    };
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const Chunk ch = chunks[c];
         if (!queries && ch.ev != cur) {
-            if (cur >= 0) flush_extent(b, cur, D, t, stride, mn, mx, smin, smax);
+            if (cur >= 0) flush_extent(b, cur, D, t, T4, stride, acc, smin, smax);
             cur = ch.ev;
-            mn = 0xffffffffu;
-            mx = 0u;
         }
         const EventDev ev = b.ev[ch.ev];
         const float *src = queries ? ev.qry : ev.pts;
         const int64_t off = queries ? ev.q_off : ev.pt_off;
-        if (t < stride) {
-            const int64_t f0 = (ch.r0 - off) * D, f1 = (ch.r1 - off) * D;
-            for (int64_t f = f0 + t; f < f1; f += stride) {
-                const float x = src[f];
-                bad |= !finite32(x);
-                const uint32_t o = f2ord(x);
-                mn = o < mn ? o : mn;
-                mx = o > mx ? o : mx;
+        const int64_t f0 = (ch.r0 - off) * D, nf = (ch.r1 - ch.r0) * D;
+        if ((reinterpret_cast<uintptr_t>(src) & 15u) == 0) {
+            // chunks start at multiples of kChunkRows rows, so src + f0 is aligned too
+            const float4 *s4 = reinterpret_cast<const float4 *>(src + f0);
+            const int64_t nv = nf / 4;
+            if (t < T4) {
+                int64_t i = t;
+                for (; i + T4 < nv; i += 2 * T4) {
+                    const float4 v0 = s4[i], v1 = s4[i + T4];
+                    fold(acc.mn[0], acc.mx[0], v0.x);
+                    fold(acc.mn[1], acc.mx[1], v0.y);
+                    fold(acc.mn[2], acc.mx[2], v0.z);
+                    fold(acc.mn[3], acc.mx[3], v0.w);
+                    fold(acc.mn[0], acc.mx[0], v1.x);
+                    fold(acc.mn[1], acc.mx[1], v1.y);
+                    fold(acc.mn[2], acc.mx[2], v1.z);
+                    fold(acc.mn[3], acc.mx[3], v1.w);
+                }
+                if (i < nv) {
+                    const float4 v0 = s4[i];
+                    fold(acc.mn[0], acc.mx[0], v0.x);
+                    fold(acc.mn[1], acc.mx[1], v0.y);
+                    fold(acc.mn[2], acc.mx[2], v0.z);
+                    fold(acc.mn[3], acc.mx[3], v0.w);
+                }
             }
+            // fewer than 4 trailing floats (only in an event's last chunk)
+            if (t < nf - 4 * nv) {
+                const int64_t f = 4 * nv + t;
+                const float x = src[f0 + f];
+                bad |= !finite32(x);
+                if (!queries) {
+                    const int a = (int)(f % D);
+                    atomicMin(&b.ext[((int64_t)ch.ev * 2 + 0) * D + a], f2ord(x));
+                    atomicMax(&b.ext[((int64_t)ch.ev * 2 + 1) * D + a], f2ord(x));
+                }
+            }
+        } else if (t < stride) {
+            for (int64_t f = t; f < nf; f += stride) fold(acc.smn, acc.smx, src[f0 + f]);
         }
     }
-    if (!queries && cur >= 0) flush_extent(b, cur, D, t, stride, mn, mx, smin, smax);
+    if (!queries && cur >= 0) flush_extent(b, cur, D, t, T4, stride, acc, smin, smax);
     if (bad) sbad = 1;
     __syncthreads();
     if (t == 0 && sbad) atomicOr(&b.ctr->status, queries ? kStatusNonfiniteQry : kStatusNonfinitePts);
