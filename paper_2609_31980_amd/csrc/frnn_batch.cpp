@@ -218,13 +218,13 @@ void BatchContext::set_inputs(const frnn_event *ev, int E, hipStream_t s) {
 void BatchContext::launch_a(hipStream_t s) {
     const bool selfq = sh_.flags & FRNN_SELF_QUERY;
     const int D = sh_.D;
-    LAUNCH("init", s, launch_init(bb_, sh_.E_cap, D, true, s));
+    // build and query counters in one launch
+    LAUNCH("init", s, launch_init(bb_, sh_.E_cap, D, true, s, bq_.ctr));
     LAUNCH("extent", s, launch_extent(bb_, sh_.pch_cap, false, sh_.cells_cap + 1, s));
     LAUNCH("plan", s, launch_plan(bb_, sh_.E_cap, s));
     LAUNCH("keys", s, launch_keys(bb_, sh_.pch_cap, false, s));
     LAUNCH("scan_cells", s, launch_scan_cells(bb_, sh_.cells_cap, false, s));
     LAUNCH("scatter", s, launch_scatter(bb_, sh_.pch_cap, false, s));
-    LAUNCH("init", s, launch_init(bq_, sh_.E_cap, D, false, s));
     if (!selfq) {
         LAUNCH("extent_q", s, launch_extent(bq_, sh_.qch_cap, true, sh_.cells_cap + 1, s));
         LAUNCH("keys_q", s, launch_keys(bq_, sh_.qch_cap, true, s));
@@ -233,7 +233,6 @@ void BatchContext::launch_a(hipStream_t s) {
     }
     LAUNCH("count", s, launch_count(bq_, kn_, D, query_blocks(sh_.o, sh_.qch_cap), s));
     LAUNCH("scan_rows", s, launch_scan_rows(bq_, kn_, sh_.q_cap, s));
-    LAUNCH("bases", s, launch_bases(bq_, sh_.E_cap, s));
 }
 
 void BatchContext::launch_b(hipStream_t s) {

@@ -74,7 +74,8 @@ struct Counters {
     uint32_t n_long;       // rows sorted in global memory
     uint32_t status;       // kStatus* bits
     uint32_t n_fill;       // windows listed for the fill pass
-    uint32_t pad[8];
+    uint32_t plan_done;    // plan blocks finished (the last one scans the cell counts)
+    uint32_t pad[7];
     // persistent count-pass work queues, one per XCD, one 64-byte line each
     uint32_t heads[8][16];
 };

@@ -4,7 +4,7 @@
 // Pipeline (every size is read from device memory, see frnn_device.h):
 //   binning    k_init, k_extent (+ clears cells), k_plan, k_keys, scan, k_scatter
 //   counting   k_query<count> over windows of sorted queries, scan of the
-//              capped counts, k_bases
+//              capped counts (and the events' first output pairs)
 //   filling    k_set_out, k_short_rows (per-event offsets, rows the stash
 //              holds), k_query<fill> (windows with longer rows), k_long_sort
 //
@@ -132,11 +132,14 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&v)[KS], int lane) {
 }
 
 // ------------------------------------------------------------------ init
-__global__ void k_init(Bufs b, int32_t init_ext) {
+__global__ void k_init(Bufs b, int32_t init_ext, Counters *ctr2) {
     const BatchDesc bd = *b.bd;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
-    if (tid < (int64_t)(sizeof(Counters) / 4)) reinterpret_cast<uint32_t *>(b.ctr)[tid] = 0u;
+    if (tid < (int64_t)(sizeof(Counters) / 4)) {
+        reinterpret_cast<uint32_t *>(b.ctr)[tid] = 0u;
+        if (ctr2) reinterpret_cast<uint32_t *>(ctr2)[tid] = 0u;
+    }
     if (init_ext) {
         const int64_t ne = (int64_t)bd.E * 2 * bd.D;
         for (int64_t i = tid; i < ne; i += nthr) {
@@ -301,12 +304,29 @@ __device__ __forceinline__ double shfl_f64(double v, int src) {
     return __shfl(v, src);
 }
 
+__device__ void plan_offsets(Bufs &b, int E);
+
+__device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane);
+
+// One wave per event; the last block to finish (a ticket counter; the grid
+// has one block per four events, so few blocks meet there) then scans the
+// events' cell counts into the cell offsets.
 __global__ void __launch_bounds__(256) k_plan(Bufs b) {
+    __shared__ uint32_t s_last;
     const BatchDesc bd = *b.bd;
-    const int E = bd.E, D = bd.D;
-    const int lane = lane_id();
     const int e = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (e >= E) return;
+    if (e < bd.E) plan_event(b, bd, e, lane_id());
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&b.ctr->plan_done, 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    plan_offsets(b, bd.E);
+}
+
+__device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane) {
+    const int D = bd.D;
     const EventDev ev = b.ev[e];
     // lane d < D: extent and lower bound of coordinate d; a non-finite
     // input (reported to the host as an error) must still give an
@@ -406,10 +426,10 @@ __global__ void __launch_bounds__(256) k_plan(Bufs b) {
     }
 }
 
-// Exclusive scan of the events' cell counts -> cell offsets (one block).
-__global__ void __launch_bounds__(256) k_plan_offsets(Bufs b) {
+// Exclusive scan of the events' cell counts -> cell offsets (one block of
+// 256 threads; run by the last block of the plan grid to finish).
+__device__ void plan_offsets(Bufs &b, int E) {
     __shared__ int64_t ssum[256];
-    const int E = b.bd->E;
     const int per = (E + 255) / 256;
     const int e0 = threadIdx.x * per;
     const int e1 = min(E, e0 + per);
@@ -673,6 +693,16 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Bufs b, Knobs kn) {
             ex = add2(ex, v[k]);
         }
         run = add2(run, tot);
+    }
+    if (MODE == kScanRows) {
+        // first output pair of every event whose first row this block holds
+        // (the host reads these with the counters)
+        __syncthreads();
+        const BatchDesc &bd = *b.bd;
+        for (int e = threadIdx.x; e <= bd.E; e += blockDim.x) {
+            const int64_t q = e < bd.E ? b.ev[e].q_off : bd.total_q;
+            if ((uint64_t)q >= lo && (uint64_t)q < hi) b.bases[e] = b.offs[q];
+        }
     }
 }
 
@@ -1337,15 +1367,6 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
     }
 }
 
-// First output pair of every event (the host reads these with the counters).
-__global__ void k_bases(Bufs b) {
-    const BatchDesc bd = *b.bd;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e <= bd.E; e += gridDim.x * blockDim.x) {
-        const int64_t q = e < bd.E ? b.ev[e].q_off : bd.total_q;
-        b.bases[e] = b.offs[q];
-    }
-}
-
 // Writes the output descriptor from kernel arguments (so the values are
 // captured at launch time, unlike a copy from host memory).
 // Also writes each event's leading zero offset (offsets[q_off + e]), the
@@ -1362,10 +1383,10 @@ __global__ void k_set_out(Bufs b, OutDesc v) {
         if (e_ != hipSuccess) return e_;   \
     } while (0)
 
-hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s) {
+hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s, Counters *also) {
     int64_t n = std::max<int64_t>((int64_t)E * 2 * D, sizeof(Counters) / 4);
     int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, b, (int32_t)init_ext);
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, b, (int32_t)init_ext, also);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1380,8 +1401,6 @@ hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, int64_t zero_
 hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s) {
     hipLaunchKernelGGL(k_plan, dim3((E_cap + kWavesPerBlock - 1) / kWavesPerBlock), dim3(64 * kWavesPerBlock),
                        0, s, b);
-    FRNN_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_plan_offsets, dim3(1), dim3(256), 0, s, b);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1471,13 +1490,6 @@ hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipSt
     case 32: hipLaunchKernelGGL(k_short_rows<32>, grid, block, 0, s, b, kn); break;
     default: return hipErrorInvalidValue;
     }
-    FRNN_CHECK_LAUNCH();
-    return hipSuccess;
-}
-
-hipError_t launch_bases(const Bufs &b, int E, hipStream_t s) {
-    int blocks = std::max(1, std::min((E + 1 + 255) / 256, 64));
-    hipLaunchKernelGGL(k_bases, dim3(blocks), dim3(256), 0, s, b);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -9,7 +9,8 @@
 
 namespace frnn {
 
-hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s);
+// zeroes b.ctr (and `also`, when given) and, with init_ext, the extents
+hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s, Counters *also = nullptr);
 // also clears zero_n cells of the (point or query) cell histogram
 hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, int64_t zero_n, hipStream_t s);
 hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s);
@@ -20,7 +21,6 @@ hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t 
 // 8); persistent mode, the resident grid.
 hipError_t launch_count(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
 hipError_t launch_scan_rows(const Bufs &b, const Knobs &kn, int64_t total_q, hipStream_t s);
-hipError_t launch_bases(const Bufs &b, int E, hipStream_t s);
 // rows of at most stash_cap pairs, and every row's per-event offset: one
 // block per query chunk
 hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s);

@@ -523,7 +523,6 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     }
     LAUNCH("count", s, launch_count(b, kn, D, qblocks, s));
     LAUNCH("scan_rows", s, launch_scan_rows(b, kn, totq, s));
-    LAUNCH("bases", s, launch_bases(b, E, s));
 
     // one synchronisation: counters, event bases and the build's status
     const size_t hvb = sizeof(Counters) + sizeof(int64_t) * (E + 1);
