@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "frnn_device.h"
 #include "frnn_launch.h"
@@ -1009,11 +1010,9 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 if (total > 0) fetch(0);
                 // fetch the next group's runs while this one is evaluated
                 if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nln);
-                for (uint32_t v0 = 0; v0 < total; v0 += 64) {
-                    const uint32_t pos = pn, j = jn;
-                    const CandRow<DT> x = xn;
-                    const bool valid = v0 + lane < total;
-                    if (v0 + 64 < total) fetch(v0 + 64);
+                // one query of the group against one chunk; self-exclusion is
+                // decided once per launch (two copies of the loop)
+                auto eval_chunk = [&](auto excl, uint32_t pos, uint32_t j, const CandRow<DT> &x, float thr) {
                     for (int t = gb; t < ge; ++t) {
                         QueryRow<DT> qr;
 #pragma unroll
@@ -1027,8 +1026,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                             }
                         }
                         const float s = dist2<DT, EXACT_D>(qr, x, D);
-                        const uint32_t self_slot = kn.exclude_self ? (uint32_t)(p0 + t) : 0xffffffffu;
-                        const bool hit = valid && s <= r2 && pos != self_slot;
+                        bool hit = s <= thr;  // thr < 0 on lanes past the group's candidates
+                        if constexpr (decltype(excl)::value) hit = hit && pos != (uint32_t)(p0 + t);
                         const uint64_t hm = ballot(hit);
                         if (hm) {
                             const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cntv, t);
@@ -1043,6 +1042,16 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                             if (lane == t) cntv = c + (uint32_t)__popcll(hm);
                         }
                     }
+                };
+                for (uint32_t v0 = 0; v0 < total; v0 += 64) {
+                    const uint32_t pos = pn, j = jn;
+                    const CandRow<DT> x = xn;
+                    const float thr = v0 + lane < total ? r2 : -1.0f;
+                    if (v0 + 64 < total) fetch(v0 + 64);
+                    if (kn.exclude_self)
+                        eval_chunk(std::true_type{}, pos, j, x, thr);
+                    else
+                        eval_chunk(std::false_type{}, pos, j, x, thr);
                 }
                 const bool mine = lane >= gb && lane < ge;
                 if (mine) b.deg[q_off + wperm] = cntv;
