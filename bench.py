@@ -37,6 +37,26 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
 
+def counter_traffic():
+    """HBM bytes per launch of the count kernel, from the committed counter
+    summary (two rocprofv3 passes, FETCH_SIZE and WRITE_SIZE, each scaled by
+    what the counter reads for a plain kernel of known size).  None when that
+    summary was taken on a different kernel source than the one built here."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2609_31980_amd", "csrc", "frnn_kernels.hip")
+    md = os.path.join(ROOT, "profiles", "hbm_traffic_tracks300k_d8.md")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        line = next(l for l in open(md) if l.startswith("count-kernel-counters:"))
+    except (OSError, StopIteration):
+        return None
+    f = dict(kv.split("=", 1) for kv in line.split(":", 1)[1].split())
+    if f.get("source_sha256") != sha:
+        return None
+    return (float(f["fetch_kib"]) * float(f["fetch_factor"])
+            + float(f["write_kib"]) * float(f["write_factor"])) * 1024.0
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -312,7 +332,7 @@ def main():
     avg_s = kern[dom]["avg_ms"] * 1e-3
     achieved = ops / avg_s / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / (VALU_PEAK_OPS / 1e12), "traffic": None,
+            "frac": achieved / (VALU_PEAK_OPS / 1e12), "traffic": counter_traffic() if dom == "count" else None,
             "kernel": dom, "kernel_avg_ms": kern[dom]["avg_ms"],
             "algorithmic_ops_per_launch": ops, "candidates_per_launch": cand,
             "candidates_per_pair": cand / max(nnz, 1)}
