@@ -24,12 +24,20 @@ SEED_C2 = 1002
 SEED_C3 = 1003
 SEED_C4 = 1004
 SEED_C5 = 1005
+SEED_PAPER = 1006
 
 # Radius of the density-stress workload (12-D Zipf clusters).  Chosen so that
 # the mean number of in-radius references per query is about 100; the value
 # was fixed by running tests/golden/calibrate_c4_radius.py (brute force on a
 # seeded 2,000-query sample) and is re-checked statistically by the tests.
 C4_RADIUS = 0.15
+
+# The paper-shaped self-join (Sec. 4.1): 271,663 points in 12-D, r = 0.12,
+# K = 1000, 9,279,672 directed non-self pairs.  The cluster spread was fixed
+# by running tests/golden/calibrate_paper_sigma.py (brute force on a seeded
+# 2,000-point sample: mean non-self degree closest to 9,279,672 / 271,663).
+PAPER_N = 271_663
+PAPER_SIGMA = 0.0305
 
 
 def uniform_cube(n: int, d: int, seed: int) -> np.ndarray:
@@ -72,6 +80,7 @@ class Workload:
     queries: np.ndarray | None   # None => queries are the references
     r: float                     # radius (a float32 value)
     K: int                       # <= 0: no cap
+    exclude_self: bool = False   # self-join without the pair (i, i)
 
 
 def c1(seed: int = SEED_C1) -> Workload:
@@ -148,6 +157,16 @@ def c4(seed: int = SEED_C4, n_ref: int = 1_000_000, n_query: int = 200_000) -> W
     """Density stress: 1M references and 200k queries in 12-D, K=64."""
     x, q = clustered(n_ref, n_query, 12, 0.03, seed)
     return Workload("zipf-clusters-1m-200k-d12", x, q, float(np.float32(C4_RADIUS)), 64)
+
+
+def paper_shaped(seed: int = SEED_PAPER, n: int = PAPER_N, sigma: float | None = None) -> Workload:
+    """Stand-in for the paper's measured event (Sec. 4.1: one 12-D embedding,
+    271,663 points, r = 0.12, K = 1000, directed non-self pairs): Zipf-sized
+    Gaussian clusters in [-1, 1]^12 as in the density workload, self-join
+    without self pairs, with the cluster spread chosen so that the mean
+    non-self degree at r = 0.12 matches the paper's 9,279,672 / 271,663."""
+    x, _ = clustered(n, 0, 12, PAPER_SIGMA if sigma is None else sigma, seed)
+    return Workload("paper-shaped-271663-d12", x, None, float(np.float32(0.12)), 1000, True)
 
 
 def subset_rows(n: int, frac: float, seed: int) -> np.ndarray:

@@ -73,3 +73,15 @@ def test_c5_trace():
 def test_lattice_edge_case():
     p = inputs.lattice_on_cells(4, 2, 0.1)
     assert p.shape == (48, 2) and p.dtype == np.float32
+
+
+def test_paper_shaped_degree_near_target(orc):
+    """The calibrated spread gives the paper's mean non-self degree (34.16) on
+    a sample other than the one used for the calibration."""
+    w = inputs.paper_shaped()
+    assert w.points.shape == (271_663, 12) and w.points.dtype == np.float32
+    assert w.K == 1000 and w.exclude_self and w.queries is None
+    assert np.float32(w.r).view(np.uint32) == np.float32(0.12).view(np.uint32)
+    s = inputs.subset_rows(len(w.points), 500 / len(w.points), 5)
+    d = orc.degrees(w.points, w.r, Q=w.points[s], self_ids=s)
+    assert abs(d.mean() - 9_279_672 / 271_663) < 0.15 * 34.16
