@@ -141,6 +141,29 @@ def cpu_baseline(points, r, K, budget_s=12.0):
 
 
 # ------------------------------------------------------------ batched
+def bench_edges(frnn, x, r, K, steps=10):
+    """Undirected edge export (frnn_csr_edges) from the headline event's CSR:
+    upper-triangle and symmetrised lists, milliseconds per export."""
+    ix = frnn.build(x, r)
+    c = ix.query(None, r, K)
+    out = {}
+    for name, sym in (("upper", False), ("symmetrized", True)):
+        e = c.edges(symmetrized=sym)
+        n = e.n
+        e.release()
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e = c.edges(symmetrized=sym)
+            e.release()
+        sync()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"edges": n, "ms": dt * 1e3, "edges_per_s": n / dt}
+    c.release()
+    ix.close()
+    return out
+
+
 def bench_paper_shaped(frnn, steps=20, warmup=5):
     """The paper-shaped self-join (271,663 points, D=12, r=0.12, K=1000, self
     pairs excluded): the same graph step and eager API as the headline.  The
@@ -391,7 +414,8 @@ def main():
            "api_build_query": {"ms_per_step": dt_api / args.steps * 1e3,
                                "pairs_per_s": nnz * args.steps / dt_api,
                                "events_per_s": args.steps / dt_api},
-           "roofline": roof, "kernels": kern}
+           "roofline": roof, "kernels": kern,
+           "edge_export": bench_edges(frnn, x, w.r, w.K)}
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w.points, w.r, w.K)

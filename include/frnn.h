@@ -155,6 +155,41 @@ frnn_status frnn_csr_copy(const frnn_csr *csr, int64_t *offsets, int32_t *indice
 /* Return a CSR's buffers to the library's pool; the struct is zeroed. */
 void frnn_csr_release(frnn_csr *csr);
 
+/* ------------------------------------------------------------ edge export
+ * Undirected edge lists for graph construction (Sec. 1: the neighbour graph
+ * of a particle-tracking pipeline, built from the fixed-radius relation of
+ * Eq. 1).  The CSR must come from a self-query (row i is point i, every index
+ * < M); self pairs (j == i) are never exported.
+ *   FRNN_EDGES_UPPER       (i, j) for every j in row i with i < j.  For an
+ *                          uncapped self-join the relation is symmetric, so
+ *                          this lists every undirected edge once.
+ *   FRNN_EDGES_SYMMETRIZED every pair present in either direction, once, as
+ *                          (min, max): (i, j) with i < j from row i, and (j, i)
+ *                          from row i when j < i and i is not in row j (a K
+ *                          cap can keep one direction only).
+ * Edges come in row order, and within a row in the CSR's order.  Device
+ * pointers, library-owned until frnn_edges_release.  Errors: NULL arguments
+ * or an unknown mode give FRNN_ERR_INVALID_ARG, and so does an index outside
+ * 0..M-1 found on the device (the output is then zeroed). */
+enum { FRNN_EDGES_UPPER = 0, FRNN_EDGES_SYMMETRIZED = 1 };
+
+typedef struct {
+    int64_t n;        /* number of edges */
+    int32_t *src;     /* [n] smaller endpoint */
+    int32_t *dst;     /* [n] larger endpoint */
+    void *owner_;     /* library-private */
+} frnn_edges;
+
+frnn_status frnn_csr_edges(const frnn_csr *csr, int32_t mode, void *stream, frnn_edges *out);
+
+/* Copy an edge list into caller buffers (device, or host when to_host != 0);
+ * either destination may be NULL to skip it.  Synchronous when to_host. */
+frnn_status frnn_edges_copy(const frnn_edges *edges, int32_t *src, int32_t *dst, int32_t to_host,
+                            void *stream);
+
+/* Return an edge list's buffers to the library's pool; the struct is zeroed. */
+void frnn_edges_release(frnn_edges *edges);
+
 /* ---------------------------------------------------------------- serving
  * A request loop on its own host thread and streams.  Submitted events are
  * admitted against an HBM budget, batched with whatever else is queued into

@@ -48,6 +48,11 @@ class _CSR(ctypes.Structure):
                 ("dist2", ctypes.c_void_p), ("owner_", ctypes.c_void_p)]
 
 
+class _Edges(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("owner_", ctypes.c_void_p)]
+
+
 class _Event(ctypes.Structure):
     _fields_ = [("points", ctypes.c_void_p), ("N", ctypes.c_int64),
                 ("queries", ctypes.c_void_p), ("M", ctypes.c_int64)]
@@ -104,6 +109,9 @@ def _load():
         "frnn_query_batch": (i32, [P(_Event), i32, i32, f32, i32, u32, P(Opts), vp, P(_CSR)]),
         "frnn_csr_copy": (i32, [P(_CSR), vp, vp, vp, i32, vp]),
         "frnn_csr_release": (None, [P(_CSR)]),
+        "frnn_csr_edges": (i32, [P(_CSR), i32, vp, P(_Edges)]),
+        "frnn_edges_release": (None, [P(_Edges)]),
+        "frnn_edges_copy": (i32, [P(_Edges), vp, vp, i32, vp]),
         "frnn_server_opts_default": (None, [P(ServerOpts)]),
         "frnn_server_create": (i32, [P(ServerOpts), P(vp)]),
         "frnn_server_submit": (i32, [vp, vp, i64, P(ctypes.c_uint64)]),
@@ -201,6 +209,15 @@ class CSR:
                                   0, _stream(stream)))
         return off, idx, d2
 
+    def edges(self, symmetrized: bool = False, stream=None) -> "Edges":
+        """Undirected edges of a self-query CSR (frnn_csr_edges): (i, j) with
+        i < j from each row, or with symmetrized also the pairs present in one
+        direction only, each once as (min, max)."""
+        e = _Edges()
+        _check(_lib.frnn_csr_edges(ctypes.byref(self._raw), 1 if symmetrized else 0,
+                                   _stream(stream), ctypes.byref(e)))
+        return Edges(e)
+
     def release(self):
         if self._raw.owner_:
             _lib.frnn_csr_release(ctypes.byref(self._raw))
@@ -257,6 +274,44 @@ class Index:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+class Edges:
+    """Undirected edge list on the device (library-owned until released)."""
+
+    def __init__(self, raw: _Edges):
+        self._raw = raw
+
+    @property
+    def n(self) -> int:
+        return int(self._raw.n)
+
+    def numpy(self, stream=None):
+        """(src int32 [n], dst int32 [n]) on the host, src < dst."""
+        src = np.empty(self.n, np.int32)
+        dst = np.empty(self.n, np.int32)
+        _check(_lib.frnn_edges_copy(ctypes.byref(self._raw), src.ctypes.data_as(ctypes.c_void_p),
+                                    dst.ctypes.data_as(ctypes.c_void_p), 1, _stream(stream)))
+        return src, dst
+
+    def torch(self, stream=None):
+        """Device copies (src, dst) as int32 torch tensors."""
+        import torch
+        src = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        dst = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        _check(_lib.frnn_edges_copy(ctypes.byref(self._raw), ctypes.c_void_p(src.data_ptr()),
+                                    ctypes.c_void_p(dst.data_ptr()), 0, _stream(stream)))
+        return src, dst
+
+    def release(self):
+        if self._raw.owner_:
+            _lib.frnn_edges_release(ctypes.byref(self._raw))
+
+    def __del__(self):
+        try:
+            self.release()
         except Exception:
             pass
 
