@@ -164,6 +164,22 @@ def bench_edges(frnn, x, r, K, steps=10):
     return out
 
 
+def bench_host(frnn, pts, r, K, steps=10, warmup=2):
+    """The synchronous host-array call (frnn_query_host) on the headline
+    event: host float32 in, compact host CSR out, so the host-to-device copy
+    of the points and the device-to-host copy of the CSR are inside each call
+    (the PCIe-inclusive rate; never the headline value)."""
+    def step():
+        c = frnn.query_host(pts, r, K)
+        n = c.nnz
+        c.release()
+        return n
+    dt, nnz = time_steps(step, steps, warmup)
+    out_bytes = 8 * (len(pts) + 1) + 8 * nnz
+    return {"ms_per_call": dt / steps * 1e3, "pairs_per_s": nnz * steps / dt,
+            "bytes_in": int(pts.nbytes), "bytes_out": int(out_bytes)}
+
+
 def bench_paper_shaped(frnn, steps=20, warmup=5):
     """The paper-shaped self-join (271,663 points, D=12, r=0.12, K=1000, self
     pairs excluded): the same graph step and eager API as the headline.  The
@@ -415,7 +431,8 @@ def main():
                                "pairs_per_s": nnz * args.steps / dt_api,
                                "events_per_s": args.steps / dt_api},
            "roofline": roof, "kernels": kern,
-           "edge_export": bench_edges(frnn, x, w.r, w.K)}
+           "edge_export": bench_edges(frnn, x, w.r, w.K),
+           "host_interface": bench_host(frnn, w.points, w.r, w.K)}
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w.points, w.r, w.K)

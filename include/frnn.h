@@ -155,6 +155,31 @@ frnn_status frnn_csr_copy(const frnn_csr *csr, int64_t *offsets, int32_t *indice
 /* Return a CSR's buffers to the library's pool; the struct is zeroed. */
 void frnn_csr_release(frnn_csr *csr);
 
+/* ------------------------------------------------------- host-array calls
+ * Synchronous search on host arrays (the paper's public host interface,
+ * Sec. 4.3): the points (and queries) are copied to the device through pinned
+ * staging buffers, the host copy of one chunk overlapping the DMA of the
+ * previous one; the batched device path runs on a library stream; the CSR
+ * comes back compact, in pinned host memory owned by the library until
+ * frnn_host_csr_release.  points: host [N][D] float32; queries: host [M][D],
+ * or NULL with FRNN_SELF_QUERY (then M must equal N).  Errors as for
+ * frnn_query_batch (the output is zeroed). */
+typedef struct {
+    int64_t M;        /* rows */
+    int64_t nnz;      /* pairs */
+    int64_t *offsets; /* host [M+1] */
+    int32_t *indices; /* host [nnz] */
+    float *dist2;     /* host [nnz], or NULL without FRNN_WANT_DIST2 */
+    void *owner_;     /* library-private */
+} frnn_host_csr;
+
+frnn_status frnn_query_host(const float *points, int64_t N, const float *queries, int64_t M, int32_t D,
+                            float r, int32_t K, uint32_t flags, const frnn_opts *opts,
+                            frnn_host_csr *out);
+
+/* Free a host CSR's pinned buffers; the struct is zeroed. */
+void frnn_host_csr_release(frnn_host_csr *csr);
+
 /* ------------------------------------------------------------ edge export
  * Undirected edge lists for graph construction (Sec. 1: the neighbour graph
  * of a particle-tracking pipeline, built from the fixed-radius relation of

@@ -48,6 +48,12 @@ class _CSR(ctypes.Structure):
                 ("dist2", ctypes.c_void_p), ("owner_", ctypes.c_void_p)]
 
 
+class _HostCSR(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("indices", ctypes.c_void_p),
+                ("dist2", ctypes.c_void_p), ("owner_", ctypes.c_void_p)]
+
+
 class _Edges(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
                 ("owner_", ctypes.c_void_p)]
@@ -112,6 +118,8 @@ def _load():
         "frnn_csr_edges": (i32, [P(_CSR), i32, vp, P(_Edges)]),
         "frnn_edges_release": (None, [P(_Edges)]),
         "frnn_edges_copy": (i32, [P(_Edges), vp, vp, i32, vp]),
+        "frnn_query_host": (i32, [vp, i64, vp, i64, i32, f32, i32, u32, P(Opts), P(_HostCSR)]),
+        "frnn_host_csr_release": (None, [P(_HostCSR)]),
         "frnn_server_opts_default": (None, [P(ServerOpts)]),
         "frnn_server_create": (i32, [P(ServerOpts), P(vp)]),
         "frnn_server_submit": (i32, [vp, vp, i64, P(ctypes.c_uint64)]),
@@ -314,6 +322,76 @@ class Edges:
             self.release()
         except Exception:
             pass
+
+
+class HostCSR:
+    """Neighbour lists in pinned host memory (frnn_query_host); the numpy
+    arrays are views of the library's buffers, valid until release()."""
+
+    def __init__(self, raw: _HostCSR):
+        self._raw = raw
+        M, nnz = int(raw.M), int(raw.nnz)
+        self.offsets = _view(raw.offsets, ctypes.c_int64, M + 1, np.int64)
+        self.indices = _view(raw.indices, ctypes.c_int32, nnz, np.int32)
+        self.dist2 = _view(raw.dist2, ctypes.c_float, nnz, np.float32) if raw.dist2 else None
+
+    @property
+    def M(self) -> int:
+        return int(self._raw.M)
+
+    @property
+    def nnz(self) -> int:
+        return int(self._raw.nnz)
+
+    def numpy(self):
+        """Owned copies (offsets, indices, dist2 or None)."""
+        return (self.offsets.copy(), self.indices.copy(),
+                None if self.dist2 is None else self.dist2.copy())
+
+    def release(self):
+        if self._raw.owner_:
+            self.offsets = self.indices = self.dist2 = None
+            _lib.frnn_host_csr_release(ctypes.byref(self._raw))
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def _view(ptr, ctype, n, dtype):
+    if not n or not ptr:
+        return np.zeros(n, dtype)
+    return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctype)), shape=(n,))
+
+
+def query_host(points: np.ndarray, r: float, K: int = 0, queries: np.ndarray | None = None,
+               exclude_self: bool = False, want_dist2: bool = True,
+               opts: Opts | None = None) -> HostCSR:
+    """Synchronous search on host float32 arrays; the CSR comes back in
+    pinned host memory (frnn_query_host)."""
+    x = np.ascontiguousarray(points, dtype=np.float32)
+    if x.ndim != 2:
+        raise ValueError("points must be [N, D]")
+    flags = (WANT_DIST2 if want_dist2 else 0)
+    q = None
+    if queries is None:
+        flags |= SELF_QUERY | (EXCLUDE_SELF if exclude_self else 0)
+        M = x.shape[0]
+    else:
+        if exclude_self:
+            raise ValueError("exclude_self needs a self-query")
+        q = np.ascontiguousarray(queries, dtype=np.float32)
+        if q.ndim != 2 or q.shape[1] != x.shape[1]:
+            raise ValueError("queries must be [M, D] with the points' D")
+        M = q.shape[0]
+    out = _HostCSR()
+    _check(_lib.frnn_query_host(x.ctypes.data_as(ctypes.c_void_p), x.shape[0],
+                                q.ctypes.data_as(ctypes.c_void_p) if q is not None else None, M,
+                                x.shape[1], float(np.float32(r)), int(K), flags,
+                                ctypes.byref(opts) if opts is not None else None, ctypes.byref(out)))
+    return HostCSR(out)
 
 
 def build(points, r: float, opts: Opts | None = None, stream=None) -> Index:
