@@ -196,3 +196,17 @@ def test_repeat_runs_identical(frnn):
     a = gpu_csr(X, 0.1, 256)
     b = gpu_csr(X, 0.1, 256)
     pinlib.assert_csr_equal(a, b, "two runs")
+
+
+def test_dense_ball_rows_far_above_k(orc, frnn):
+    """Adversarial density: 3,000 points in a ball much smaller than r (rows
+    of ~3,000 pairs, far above the on-chip limit) plus a sparse background;
+    capped rows must be the first K of the full (dist2, id) order."""
+    rng = np.random.default_rng(77)
+    ball = (0.5 + 1e-3 * rng.standard_normal((3000, 3))).astype(np.float32)
+    bg = rng.random((2000, 3)).astype(np.float32)
+    X = np.concatenate([ball, bg])[rng.permutation(5000)]
+    say("dense ball")
+    for K in (0, 7, 1000):
+        check_full(orc, X, 0.05, K, what=f"dense ball K={K}")
+    check_full(orc, X, 0.05, 7, exclude_self=True, what="dense ball K=7 exclude-self")
