@@ -295,6 +295,14 @@ __global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries, int64_t
 }
 
 // ------------------------------------------------------------------ plan
+// Lane src's value (src wave-uniform), read through scalar registers.
+__device__ __forceinline__ double lane_f64(double v, int src) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // One wave per event.  Grid axes = the coordinates of largest extent; cell
 // width h = r_h / m with r_h = r (1 + 2^-16) + 2^-60 (float64); the most
 // axes (up to the limit) whose cell count stays within the cap.
@@ -305,9 +313,6 @@ __global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries, int64_t
 // Cell coordinates v = fl64(fl64(x - lo) * inv_h) carry a relative error
 // below 2^-51, far less than the 2^-16 margin in h, so |v(x) - v(y)| < m and
 // the floors differ by at most m; clamping to [0, n-1] cannot widen the gap.
-__device__ __forceinline__ double shfl_f64(double v, int src) {
-    return __shfl(v, src);
-}
 
 __device__ void plan_offsets(Bufs &b, int E);
 
@@ -321,6 +326,11 @@ __global__ void __launch_bounds__(256) k_plan(Bufs b) {
     const BatchDesc bd = *b.bd;
     const int e = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (e < bd.E) plan_event(b, bd, e, lane_id());
+    if (gridDim.x == 1) {  // every event in this block: no ticket needed
+        __syncthreads();
+        plan_offsets(b, bd.E);
+        return;
+    }
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) s_last = atomicAdd(&b.ctr->plan_done, 1u) == gridDim.x - 1 ? 1u : 0u;
@@ -348,7 +358,7 @@ __device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane) {
     // rank by decreasing extent, ties by coordinate index
     int rank = 0;
     for (int d2 = 0; d2 < D; ++d2) {
-        const double x2 = shfl_f64(x, d2);
+        const double x2 = lane_f64(x, d2);
         rank += (x2 > x || (x2 == x && d2 < lane)) ? 1 : 0;
     }
     GridDesc g;
@@ -372,8 +382,8 @@ __device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane) {
         const uint64_t hit = ballot(lane < D && rank == a);
         const int ax = __ffsll((unsigned long long)hit) - 1;
         g.axis[a] = ax;
-        cext[a] = shfl_f64(x, ax);
-        g.lo[a] = shfl_f64(lo, ax);
+        cext[a] = lane_f64(x, ax);
+        g.lo[a] = lane_f64(lo, ax);
     }
     int G = 0;
     const int W = 2 * m + 1;
