@@ -81,7 +81,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     grid.reset(sizeof(GridDesc) * Ec, s);
     runs.reset(sizeof(RunEntry) * kRunsMax * Ec, s);
     cell_off.reset(sizeof(int64_t) * (Ec + 1), s);
-    ext.reset(sizeof(uint32_t) * 2 * Ec * D, s);
+    ext.reset(sizeof(uint32_t) * 2 * sh.pch_cap * D, s);  // per-chunk extent slots
     xs.reset(sizeof(float) * sh.pts_cap * Dp_, s);
     perm.reset(sizeof(int32_t) * sh.pts_cap, s);
     key.reset(sizeof(uint32_t) * sh.pts_cap, s);
@@ -219,14 +219,14 @@ void BatchContext::launch_a(hipStream_t s) {
     const bool selfq = sh_.flags & FRNN_SELF_QUERY;
     const int D = sh_.D;
     // build and query counters in one launch
-    LAUNCH("init", s, launch_init(bb_, sh_.E_cap, D, true, s, bq_.ctr));
-    LAUNCH("extent", s, launch_extent(bb_, sh_.pch_cap, false, sh_.cells_cap + 1, s));
+    LAUNCH("init", s, launch_init(bb_, s, bq_.ctr));
+    LAUNCH("extent", s, launch_extent(bb_, sh_.pch_cap, sh_.E_cap, false, sh_.cells_cap + 1, s));
     LAUNCH("plan", s, launch_plan(bb_, sh_.E_cap, s));
     LAUNCH("keys", s, launch_keys(bb_, sh_.pch_cap, false, s));
     LAUNCH("scan_cells", s, launch_scan_cells(bb_, sh_.cells_cap, false, s));
     LAUNCH("scatter", s, launch_scatter(bb_, sh_.pch_cap, false, s));
     if (!selfq) {
-        LAUNCH("extent_q", s, launch_extent(bq_, sh_.qch_cap, true, sh_.cells_cap + 1, s));
+        LAUNCH("extent_q", s, launch_extent(bq_, sh_.qch_cap, sh_.E_cap, true, sh_.cells_cap + 1, s));
         LAUNCH("keys_q", s, launch_keys(bq_, sh_.qch_cap, true, s));
         LAUNCH("scan_cells_q", s, launch_scan_cells(bq_, sh_.cells_cap, true, s));
         LAUNCH("scatter_q", s, launch_scatter(bq_, sh_.qch_cap, true, s));

@@ -148,6 +148,7 @@ struct Bufs {
 };
 
 constexpr int kScanBlocks = 1024;
+constexpr int kExtentRows = 1024;  // rows per extent block (per-unit slots)
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
 

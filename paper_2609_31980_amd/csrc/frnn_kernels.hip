@@ -137,80 +137,30 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&v)[KS], int lane) {
 }
 
 // ------------------------------------------------------------------ init
-__global__ void k_init(Bufs b, int32_t init_ext, Counters *ctr2) {
-    const BatchDesc bd = *b.bd;
+__global__ void k_init(Bufs b, Counters *ctr2) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
     if (tid < (int64_t)(sizeof(Counters) / 4)) {
         reinterpret_cast<uint32_t *>(b.ctr)[tid] = 0u;
         if (ctr2) reinterpret_cast<uint32_t *>(ctr2)[tid] = 0u;
     }
-    if (init_ext) {
-        const int64_t ne = (int64_t)bd.E * 2 * bd.D;
-        for (int64_t i = tid; i < ne; i += nthr) {
-            int64_t w = (i / bd.D) % 2;  // 0: min, 1: max
-            b.ext[i] = w == 0 ? 0xffffffffu : 0u;
-        }
-    }
 }
 
 // ---------------------------------------------------------------- extent
-// Per-event per-axis min / max of the points and a finiteness check
-// (queries: finiteness only).  A block keeps running min / max across the
-// chunks it takes and publishes them (LDS, then one global atomic per axis)
-// only when the event changes.  Rows are read as 16-byte vectors when the
-// event's array is 16-byte aligned: thread t takes vector t + k*T4 of a
-// chunk, and since 4*T4 is a multiple of D each of its four lanes always
+// Per-unit per-axis min / max of the points and a finiteness check
+// (queries: finiteness only).  A unit is kExtentRows consecutive rows of one
+// event (the events' units in order, ceil(n / kExtentRows) each); one block
+// per unit, and the block's result goes to its own slot ext[unit][2][D] (no
+// atomics on shared addresses: the plan reduces the slots of each event).
+// Rows are read as 16-byte vectors when the event's array is 16-byte aligned:
+// thread t takes vector t + k*T4 of the unit, and since 4*T4 is a multiple of
+// D each of its four lanes always
 // holds the same axis.  The same launch clears the cell histogram for the
 // capacity of the run.
-struct ExtentAcc {
-    uint32_t mn[4], mx[4];  // 16-byte path, axes ax[j]
-    int ax[4];
-    uint32_t smn, smx;      // unaligned path, axis t % D
-    __device__ void reset() {
-        for (int j = 0; j < 4; ++j) {
-            mn[j] = 0xffffffffu;
-            mx[j] = 0u;
-        }
-        smn = 0xffffffffu;
-        smx = 0u;
-    }
-};
-
-__device__ __forceinline__ void flush_extent(Bufs &b, int ev, int D, int t, int T4, int stride,
-                                             ExtentAcc &acc, uint32_t *smin, uint32_t *smax) {
-    if (t < kDMax) {
-        smin[t] = 0xffffffffu;
-        smax[t] = 0u;
-    }
-    __syncthreads();
-    if (t < T4) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            atomicMin(&smin[acc.ax[j]], acc.mn[j]);
-            atomicMax(&smax[acc.ax[j]], acc.mx[j]);
-        }
-    }
-    if (t < stride) {
-        atomicMin(&smin[t % D], acc.smn);
-        atomicMax(&smax[t % D], acc.smx);
-    }
-    __syncthreads();
-    if (t < D) {
-        atomicMin(&b.ext[((int64_t)ev * 2 + 0) * D + t], smin[t]);
-        atomicMax(&b.ext[((int64_t)ev * 2 + 1) * D + t], smax[t]);
-    }
-    __syncthreads();
-    acc.reset();
-}
-
 __global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries, int64_t zero_n) {
     __shared__ uint32_t smin[kDMax], smax[kDMax];
     __shared__ int sbad;
     const BatchDesc bd = *b.bd;
     const int D = bd.D;
-    const int nch = queries ? bd.n_qchunks : bd.n_pchunks;
-    const Chunk *chunks = queries ? b.qchunks : b.pchunks;
     const int stride = (256 / D) * D;
     int L = 4;  // lcm(4, D) floats
     while (L % D) L += 4;
@@ -224,73 +174,102 @@ __global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries, int64_t
         for (int64_t i = gt; i < n4; i += gs) reinterpret_cast<uint4 *>(cells)[i] = make_uint4(0u, 0u, 0u, 0u);
         for (int64_t i = 4 * n4 + gt; i < zero_n; i += gs) cells[i] = 0u;
     }
+    if (t < kDMax) {
+        smin[t] = 0xffffffffu;
+        smax[t] = 0u;
+    }
     if (t == 0) sbad = 0;
     __syncthreads();
-    ExtentAcc acc;
-    acc.reset();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc.ax[j] = (4 * t + j) % D;
-    bool bad = false;
-    int cur = -1;
-    auto fold = [&](uint32_t &mn, uint32_t &mx, float x) {
-        bad |= !finite32(x);
-        const uint32_t o = f2ord(x);
-        mn = o < mn ? o : mn;
-        mx = o > mx ? o : mx;
-    };
-    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        const Chunk ch = chunks[c];
-        if (!queries && ch.ev != cur) {
-            if (cur >= 0) flush_extent(b, cur, D, t, T4, stride, acc, smin, smax);
-            cur = ch.ev;
+    // this block's unit: rows [u*kExtentRows, ...) of event ev_u, found by
+    // walking the events' unit counts ceil(n / kExtentRows)
+    __shared__ int s_ev;
+    __shared__ long long s_u;
+    if (t == 0) {
+        long long u = blockIdx.x;
+        int e = 0;
+        for (; e < bd.E; ++e) {
+            const int64_t n = queries ? b.ev[e].n_q : b.ev[e].n_pts;
+            const long long ne = (n + kExtentRows - 1) / kExtentRows;
+            if (u < ne) break;
+            u -= ne;
         }
-        const EventDev ev = b.ev[ch.ev];
+        s_ev = e;
+        s_u = u;
+    }
+    __syncthreads();
+    const int c = blockIdx.x;
+    const int ue = s_ev;
+    bool bad = false;
+    if (ue < bd.E) {
+        uint32_t mn[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[4] = {0u, 0u, 0u, 0u};
+        auto fold = [&](uint32_t &lo, uint32_t &hi, float x) {
+            bad |= !finite32(x);
+            const uint32_t o = f2ord(x);
+            lo = o < lo ? o : lo;
+            hi = o > hi ? o : hi;
+        };
+        const EventDev ev = b.ev[ue];
         const float *src = queries ? ev.qry : ev.pts;
-        const int64_t off = queries ? ev.q_off : ev.pt_off;
-        const int64_t f0 = (ch.r0 - off) * D, nf = (ch.r1 - ch.r0) * D;
+        const int64_t n = queries ? ev.n_q : ev.n_pts;
+        const int64_t r0 = (int64_t)s_u * kExtentRows, r1 = r0 + kExtentRows < n ? r0 + kExtentRows : n;
+        const int64_t f0 = r0 * D, nf = (r1 - r0) * D;
         if ((reinterpret_cast<uintptr_t>(src) & 15u) == 0) {
-            // chunks start at multiples of kChunkRows rows, so src + f0 is aligned too
+            // units start at multiples of kExtentRows rows, so src + f0 is aligned too
             const float4 *s4 = reinterpret_cast<const float4 *>(src + f0);
             const int64_t nv = nf / 4;
             if (t < T4) {
                 int64_t i = t;
-                for (; i + T4 < nv; i += 2 * T4) {
-                    const float4 v0 = s4[i], v1 = s4[i + T4];
-                    fold(acc.mn[0], acc.mx[0], v0.x);
-                    fold(acc.mn[1], acc.mx[1], v0.y);
-                    fold(acc.mn[2], acc.mx[2], v0.z);
-                    fold(acc.mn[3], acc.mx[3], v0.w);
-                    fold(acc.mn[0], acc.mx[0], v1.x);
-                    fold(acc.mn[1], acc.mx[1], v1.y);
-                    fold(acc.mn[2], acc.mx[2], v1.z);
-                    fold(acc.mn[3], acc.mx[3], v1.w);
+                for (; i + 3 * T4 < nv; i += 4 * T4) {
+                    float4 v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = s4[i + u * T4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        fold(mn[0], mx[0], v[u].x);
+                        fold(mn[1], mx[1], v[u].y);
+                        fold(mn[2], mx[2], v[u].z);
+                        fold(mn[3], mx[3], v[u].w);
+                    }
                 }
-                if (i < nv) {
+                for (; i < nv; i += T4) {
                     const float4 v0 = s4[i];
-                    fold(acc.mn[0], acc.mx[0], v0.x);
-                    fold(acc.mn[1], acc.mx[1], v0.y);
-                    fold(acc.mn[2], acc.mx[2], v0.z);
-                    fold(acc.mn[3], acc.mx[3], v0.w);
+                    fold(mn[0], mx[0], v0.x);
+                    fold(mn[1], mx[1], v0.y);
+                    fold(mn[2], mx[2], v0.z);
+                    fold(mn[3], mx[3], v0.w);
+                }
+                if (!queries) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        atomicMin(&smin[(4 * t + j) % D], mn[j]);
+                        atomicMax(&smax[(4 * t + j) % D], mx[j]);
+                    }
                 }
             }
             // fewer than 4 trailing floats (only in an event's last chunk)
             if (t < nf - 4 * nv) {
                 const int64_t f = 4 * nv + t;
-                const float x = src[f0 + f];
-                bad |= !finite32(x);
+                uint32_t lo = 0xffffffffu, hi = 0u;
+                fold(lo, hi, src[f0 + f]);
                 if (!queries) {
-                    const int a = (int)(f % D);
-                    atomicMin(&b.ext[((int64_t)ch.ev * 2 + 0) * D + a], f2ord(x));
-                    atomicMax(&b.ext[((int64_t)ch.ev * 2 + 1) * D + a], f2ord(x));
+                    atomicMin(&smin[f % D], lo);
+                    atomicMax(&smax[f % D], hi);
                 }
             }
         } else if (t < stride) {
-            for (int64_t f = t; f < nf; f += stride) fold(acc.smn, acc.smx, src[f0 + f]);
+            for (int64_t f = t; f < nf; f += stride) fold(mn[0], mx[0], src[f0 + f]);
+            if (!queries) {
+                atomicMin(&smin[t % D], mn[0]);
+                atomicMax(&smax[t % D], mx[0]);
+            }
         }
     }
-    if (!queries && cur >= 0) flush_extent(b, cur, D, t, T4, stride, acc, smin, smax);
     if (bad) sbad = 1;
     __syncthreads();
+    if (!queries && ue < bd.E && t < D) {
+        b.ext[((int64_t)c * 2 + 0) * D + t] = smin[t];
+        b.ext[((int64_t)c * 2 + 1) * D + t] = smax[t];
+    }
     if (t == 0 && sbad) atomicOr(&b.ctr->status, queries ? kStatusNonfiniteQry : kStatusNonfinitePts);
 }
 
@@ -316,16 +295,66 @@ __device__ __forceinline__ double lane_f64(double v, int src) {
 
 __device__ void plan_offsets(Bufs &b, int E);
 
-__device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane);
+__device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane, uint32_t emin, uint32_t emax);
 
-// One wave per event; the last block to finish (a ticket counter; the grid
-// has one block per four events, so few blocks meet there) then scans the
-// events' cell counts into the cell offsets.
+// One block per event: the block reduces the event's per-chunk extent slots
+// (its units follow those of the earlier events, ceil(n / kExtentRows) each;
+// slot layout [unit][min, max][D]),
+// then its first wave plans the grid.  The last block to finish (a ticket
+// counter) scans the events' cell counts into the cell offsets.
 __global__ void __launch_bounds__(256) k_plan(Bufs b) {
     __shared__ uint32_t s_last;
+    __shared__ uint32_t rmin[256];
+    __shared__ long long s_c0[256];
     const BatchDesc bd = *b.bd;
-    const int e = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (e < bd.E) plan_event(b, bd, e, lane_id());
+    const int e = blockIdx.x, D = bd.D, t = threadIdx.x;
+    if (e < bd.E) {
+        long long part = 0;
+        for (int e2 = t; e2 < e; e2 += blockDim.x) part += (b.ev[e2].n_pts + kExtentRows - 1) / kExtentRows;
+        s_c0[t] = part;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) s_c0[t] += s_c0[t + o];
+            __syncthreads();
+        }
+        const int64_t c0 = s_c0[0];
+        const int64_t nch = (b.ev[e].n_pts + kExtentRows - 1) / kExtentRows;
+        // the event's slots are one contiguous block of nch * 2D words; thread
+        // t < T reads words t + k*T, all in the same column (T is a multiple of
+        // 2D), eight loads in flight at a time
+        const int W = 2 * D, T = (256 / W) * W;
+        const int64_t nw = nch * W;
+        const uint32_t *slot = b.ext + c0 * W;
+        const bool is_min = (t % W) < D;
+        uint32_t acc = is_min ? 0xffffffffu : 0u;
+        if (t < T) {
+            int64_t i = t;
+            for (; i + 7 * T < nw; i += 8 * T) {
+                uint32_t v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = slot[i + u * T];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc = is_min ? (v[u] < acc ? v[u] : acc) : (v[u] > acc ? v[u] : acc);
+            }
+            for (; i < nw; i += T) {
+                const uint32_t v = slot[i];
+                acc = is_min ? (v < acc ? v : acc) : (v > acc ? v : acc);
+            }
+        }
+        rmin[t] = acc;
+        __syncthreads();
+        if (t < 64) {
+            uint32_t emin = 0xffffffffu, emax = 0u;
+            if (t < D) {
+                for (int s = 0; s < T / W; ++s) {
+                    const uint32_t lo = rmin[s * W + t], hi = rmin[s * W + D + t];
+                    emin = lo < emin ? lo : emin;
+                    emax = hi > emax ? hi : emax;
+                }
+            }
+            plan_event(b, bd, e, t, emin, emax);
+        }
+    }
     if (gridDim.x == 1) {  // every event in this block: no ticket needed
         __syncthreads();
         plan_offsets(b, bd.E);
@@ -340,7 +369,7 @@ __global__ void __launch_bounds__(256) k_plan(Bufs b) {
     plan_offsets(b, bd.E);
 }
 
-__device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane) {
+__device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane, uint32_t emin, uint32_t emax) {
     const int D = bd.D;
     const EventDev ev = b.ev[e];
     // lane d < D: extent and lower bound of coordinate d; a non-finite
@@ -348,8 +377,8 @@ __device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane) {
     // in-bounds grid, so its extent counts as empty
     double x = -1.0, lo = 0.0;
     if (lane < D) {
-        const float flo = ord2f(b.ext[((int64_t)e * 2 + 0) * D + lane]);
-        const float fhi = ord2f(b.ext[((int64_t)e * 2 + 1) * D + lane]);
+        const float flo = ord2f(emin);
+        const float fhi = ord2f(emax);
         x = ev.n_pts > 0 ? (double)fhi - (double)flo : 0.0;
         if (!(x >= 0.0 && x <= 1.0e39)) x = 0.0;
         lo = ev.n_pts > 0 ? (double)flo : 0.0;
@@ -1406,24 +1435,25 @@ __global__ void k_set_out(Bufs b, OutDesc v) {
         if (e_ != hipSuccess) return e_;   \
     } while (0)
 
-hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s, Counters *also) {
-    int64_t n = std::max<int64_t>((int64_t)E * 2 * D, sizeof(Counters) / 4);
-    int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, b, (int32_t)init_ext, also);
+hipError_t launch_init(const Bufs &b, hipStream_t s, Counters *also) {
+    static_assert(sizeof(Counters) / 4 <= 256, "one block clears the counters");
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, b, also);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
 
-hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, int64_t zero_n, hipStream_t s) {
-    const int blocks = std::max(1, std::min(std::max(nchunks, (int)((zero_n + 4095) / 4096)), 512));
+hipError_t launch_extent(const Bufs &b, int nchunks, int E_cap, bool queries, int64_t zero_n, hipStream_t s) {
+    // units: sum over events of ceil(n / kExtentRows) <= nchunks / 4 + E
+    static_assert(kExtentRows == 4 * kChunkRows, "unit bound");
+    const int units = (nchunks + 3) / 4 + E_cap;
+    const int blocks = std::max(1, std::max(units, (int)std::min<int64_t>((zero_n + 4095) / 4096, 4096)));
     hipLaunchKernelGGL(k_extent, dim3(blocks), dim3(256), 0, s, b, (int32_t)queries, zero_n);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
 
 hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_plan, dim3((E_cap + kWavesPerBlock - 1) / kWavesPerBlock), dim3(64 * kWavesPerBlock),
-                       0, s, b);
+    hipLaunchKernelGGL(k_plan, dim3(std::max(1, E_cap)), dim3(256), 0, s, b);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }

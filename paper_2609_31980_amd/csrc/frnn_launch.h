@@ -9,10 +9,11 @@
 
 namespace frnn {
 
-// zeroes b.ctr (and `also`, when given) and, with init_ext, the extents
-hipError_t launch_init(const Bufs &b, int E, int D, bool init_ext, hipStream_t s, Counters *also = nullptr);
-// also clears zero_n cells of the (point or query) cell histogram
-hipError_t launch_extent(const Bufs &b, int nchunks, bool queries, int64_t zero_n, hipStream_t s);
+// zeroes b.ctr (and `also`, when given)
+hipError_t launch_init(const Bufs &b, hipStream_t s, Counters *also = nullptr);
+// one block per chunk (per-chunk extent slots for the points); also clears
+// zero_n cells of the (point or query) cell histogram
+hipError_t launch_extent(const Bufs &b, int nchunks, int E_cap, bool queries, int64_t zero_n, hipStream_t s);
 hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s);
 hipError_t launch_keys(const Bufs &b, int nchunks, bool queries, hipStream_t s);
 hipError_t launch_scan_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s);

@@ -354,7 +354,7 @@ frnn_status build_index(Index &ix, const float *const *points, const int64_t *n,
     ix.grid.reset(sizeof(GridDesc) * E, s);
     ix.runs.reset(sizeof(RunEntry) * kRunsMax * E, s);
     ix.cell_off.reset(sizeof(int64_t) * (E + 1), s);
-    ix.ext.reset(sizeof(uint32_t) * 2 * E * D, s);
+    ix.ext.reset(sizeof(uint32_t) * 2 * std::max(1, ix.n_pchunks) * D, s);  // per-chunk extent slots
     ix.xs.reset(sizeof(float) * std::max<int64_t>(1, tot) * ix.Dp, s);
     ix.perm.reset(sizeof(int32_t) * std::max<int64_t>(1, tot), s);
     ix.skey.reset(sizeof(uint32_t) * std::max<int64_t>(1, tot), s);
@@ -385,8 +385,8 @@ frnn_status build_index(Index &ix, const float *const *points, const int64_t *n,
     b.cells = ix.cells.as<uint32_t>();
     b.scan_part = part.as<uint64_t>();
 
-    LAUNCH("init", s, launch_init(b, E, D, true, s));
-    LAUNCH("extent", s, launch_extent(b, ix.n_pchunks, false, ccap + 1, s));
+    LAUNCH("init", s, launch_init(b, s));
+    LAUNCH("extent", s, launch_extent(b, ix.n_pchunks, E, false, ccap + 1, s));
     LAUNCH("plan", s, launch_plan(b, E, s));
     LAUNCH("keys", s, launch_keys(b, ix.n_pchunks, false, s));
     LAUNCH("scan_cells", s, launch_scan_cells(b, ccap, false, s));
@@ -514,9 +514,9 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     kn.stash_cap = op.o.stash_cap;
     const int qblocks = query_blocks(op.o, nqc);
 
-    LAUNCH("init", s, launch_init(b, E, D, false, s));
+    LAUNCH("init", s, launch_init(b, s));
     if (!selfq) {
-        LAUNCH("extent_q", s, launch_extent(b, nqc, true, ix.cells_cap + 1, s));
+        LAUNCH("extent_q", s, launch_extent(b, nqc, E, true, ix.cells_cap + 1, s));
         LAUNCH("keys_q", s, launch_keys(b, nqc, true, s));
         LAUNCH("scan_cells_q", s, launch_scan_cells(b, ix.cells_cap, true, s));
         LAUNCH("scatter_q", s, launch_scatter(b, nqc, true, s));
