@@ -851,7 +851,7 @@ __device__ __forceinline__ void sort_and_write(const uint64_t *hits, uint32_t n,
 // (the next group's runs are fetched while this group is evaluated), keeps
 // the first KR*64 candidates' rows and ids in registers, and evaluates every
 // query of the group against them, 64 candidates per step, one per lane.
-template <int DT, bool EXACT_D, bool FILL, int KR>
+template <int DT, bool EXACT_D, bool FILL, int KR, bool PERS>
 __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     constexpr int DP = (DT + 3) & ~3;
     __shared__ WaveLds slds[kWavesPerBlock];
@@ -993,7 +993,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 L.run_base[at] = start;
                 L.run_pref[at] = total + inc - len;
             }
-            total += uniform((uint32_t)__shfl((int)inc, 63));
+            total += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
             nruns += __popcll(nz);
         };
 
@@ -1200,12 +1200,12 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         }
     };
 
-    if (FILL) {
+    if constexpr (FILL) {
         // the listed windows, grid-strided
         const uint32_t n = b.ctr->n_fill;
         const uint32_t nw = gridDim.x * kWavesPerBlock;
         for (uint32_t i = blockIdx.x * kWavesPerBlock + w; i < n; i += nw) process_window(b.fill_list[i]);
-    } else if (kn.persistent) {
+    } else if constexpr (PERS) {
         const int x0 = blockIdx.x & 7;
         for (int qx = 0; qx < 8; ++qx) {
             const int x = (x0 + qx) & 7;
@@ -1251,14 +1251,16 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
 // Two entry points with the same body: the second asks the compiler for 5
 // resident waves per SIMD (at most 96 registers), which the measurements
 // favour for the 8-dimensional kernel even with a few spilled registers.
-template <int DT, bool EXACT_D, bool FILL, int KR>
+// PERS selects the persistent scheduling at compile time, so each kernel
+// holds one copy of the window body.
+template <int DT, bool EXACT_D, bool FILL, int KR, bool PERS>
 __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
-    query_body<DT, EXACT_D, FILL, KR>(b, kn);
+    query_body<DT, EXACT_D, FILL, KR, PERS>(b, kn);
 }
 
-template <int DT, bool EXACT_D, bool FILL, int KR>
+template <int DT, bool EXACT_D, bool FILL, int KR, bool PERS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_query_o5(Bufs b, Knobs kn) {
-    query_body<DT, EXACT_D, FILL, KR>(b, kn);
+    query_body<DT, EXACT_D, FILL, KR, PERS>(b, kn);
 }
 
 // ------------------------------------------------------------ short rows
@@ -1504,22 +1506,34 @@ static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int bloc
     // register-resident candidate chunks: the count pass evaluates every
     // candidate; the fill pass only re-evaluates rows longer than the stash
     constexpr int KR3 = FILL ? 1 : 4, KR8 = FILL ? 1 : 2, KR12 = FILL ? 1 : 4, KRG = FILL ? 1 : 2;
-    switch (D) {
-    case 3: hipLaunchKernelGGL((k_query<3, true, FILL, KR3>), grid, block, 0, s, b, kn); break;
-    case 8:
-        if constexpr (FILL)
-            hipLaunchKernelGGL((k_query<8, true, true, KR8>), grid, block, 0, s, b, kn);
+    auto go = [&](auto pers) {
+        constexpr bool P = decltype(pers)::value;
+        switch (D) {
+        case 3: hipLaunchKernelGGL((k_query<3, true, FILL, KR3, P>), grid, block, 0, s, b, kn); break;
+        case 8:
+            if constexpr (FILL)
+                hipLaunchKernelGGL((k_query<8, true, true, KR8, P>), grid, block, 0, s, b, kn);
+            else
+                hipLaunchKernelGGL((k_query_o5<8, true, false, KR8, P>), grid, block, 0, s, b, kn);
+            break;
+        case 12: hipLaunchKernelGGL((k_query<12, true, FILL, KR12, P>), grid, block, 0, s, b, kn); break;
+        default:
+            if (D <= 4)
+                hipLaunchKernelGGL((k_query<4, false, FILL, KR3, P>), grid, block, 0, s, b, kn);
+            else if (D <= 16)
+                hipLaunchKernelGGL((k_query<16, false, FILL, KRG, P>), grid, block, 0, s, b, kn);
+            else
+                hipLaunchKernelGGL((k_query<32, false, FILL, 1, P>), grid, block, 0, s, b, kn);
+        }
+    };
+    // the fill pass always strides over its window list
+    if constexpr (FILL) {
+        go(std::false_type{});
+    } else {
+        if (kn.persistent)
+            go(std::true_type{});
         else
-            hipLaunchKernelGGL((k_query_o5<8, true, false, KR8>), grid, block, 0, s, b, kn);
-        break;
-    case 12: hipLaunchKernelGGL((k_query<12, true, FILL, KR12>), grid, block, 0, s, b, kn); break;
-    default:
-        if (D <= 4)
-            hipLaunchKernelGGL((k_query<4, false, FILL, KR3>), grid, block, 0, s, b, kn);
-        else if (D <= 16)
-            hipLaunchKernelGGL((k_query<16, false, FILL, KRG>), grid, block, 0, s, b, kn);
-        else
-            hipLaunchKernelGGL((k_query<32, false, FILL, 1>), grid, block, 0, s, b, kn);
+            go(std::false_type{});
     }
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
