@@ -11,6 +11,9 @@
 
 namespace frnn {
 
+// offset of the output descriptor in the descriptor block (after BatchDesc)
+constexpr size_t kOutOff = 128;
+
 static int64_t round_class(int64_t n) {
     // 2^k x {1, 1.25, 1.5, 1.75}, at least 4096
     int64_t p = 4096;
@@ -70,8 +73,9 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     Dp_ = (D + 3) & ~3;
     const bool selfq = sh.flags & FRNN_SELF_QUERY;
     const int Ec = sh.E_cap;
-    // descriptors (one block, one copy per batch): batch | events | point
-    // chunks | query chunks, each region sized for the capacity
+    // descriptors (one block, one copy per batch): batch | output | events |
+    // point chunks | query chunks, each region sized for the capacity
+    static_assert(sizeof(BatchDesc) <= kOutOff && kOutOff + sizeof(OutDesc) <= 256, "descriptor head");
     o_ev_ = 256;
     o_pc_ = o_ev_ + sizeof(EventDev) * Ec;
     o_qc_ = o_pc_ + sizeof(Chunk) * sh.pch_cap;
@@ -103,7 +107,6 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     stash.reset(sizeof(uint64_t) * sh.q_cap * std::max(1, sh.o.stash_cap), s);
     flist.reset(sizeof(uint32_t) * std::max<int64_t>(1, sh.qch_cap * (kChunkRows / sh.o.queries_per_item)), s);
     part.reset(sizeof(uint64_t) * 2 * kScanBlocks, s);
-    outd.reset(sizeof(OutDesc), s);
 
     Bufs b{};
     b.bd = desc.as<BatchDesc>();
@@ -133,7 +136,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     b.stash = stash.as<uint64_t>();
     b.fill_list = flist.as<uint32_t>();
     b.scan_part = part.as<uint64_t>();
-    b.out = outd.as<OutDesc>();
+    b.out = reinterpret_cast<OutDesc *>(desc.as<char>() + kOutOff);
     b.bases = reinterpret_cast<int64_t *>(hv.as<char>() + 2 * sizeof(Counters));
     bb_ = b;
     bb_.ctr = reinterpret_cast<Counters *>(hv.as<char>() + sizeof(Counters));
@@ -149,23 +152,30 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     kn_.long_cap = sh.o.row_cap_lds;
     kn_.persistent = sh.o.persistent;
     kn_.stash_cap = sh.o.stash_cap;
+    FRNN_HIP(hipEventCreateWithFlags(&counted_, hipEventDisableTiming));
 }
 
 void BatchContext::retarget(hipStream_t s) {
     DevBuf *all[] = {&desc, &hv, &grid, &cell_off, &ext,
                      &xs, &perm, &key, &rank, &skey, &cells, &qs, &qperm, &qkey, &qrank, &sqkey,
-                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &stash, &flist, &part, &outd};
+                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &stash, &flist, &part};
     for (DevBuf *d : all) d->set_stream(s);
 }
 
 BatchContext::~BatchContext() {
-    if (ga_) (void)hipGraphExecDestroy(ga_);
-    if (gb_) (void)hipGraphExecDestroy(gb_);
-    if (gra_) (void)hipGraphDestroy(gra_);
-    if (grb_) (void)hipGraphDestroy(grb_);
+    for (hipGraphExec_t ge : {ga_, gb_})
+        if (ge) (void)hipGraphExecDestroy(ge);
+    for (hipGraph_t g : {gra_, grb_})
+        if (g) (void)hipGraphDestroy(g);
+    if (counted_) (void)hipEventDestroy(counted_);
 }
 
 void BatchContext::set_inputs(const frnn_event *ev, int E, hipStream_t s) {
+    prepare(ev, E);
+    upload(s, nullptr);
+}
+
+void BatchContext::prepare(const frnn_event *ev, int E) {
     const bool selfq = sh_.flags & FRNN_SELF_QUERY;
     E_ = E;
     std::vector<int64_t> np(E), poff(E);
@@ -207,12 +217,19 @@ void BatchContext::set_inputs(const frnn_event *ev, int E, hipStream_t s) {
     bd.r_build = sh_.r;
     bd.total_pts = tp;
     bd.total_q = tq;
+    stage_bytes_ = o_qc_ + sizeof(Chunk) * qc.size();
     char *h = (char *)stage_.ensure(o_qc_ + sizeof(Chunk) * std::max<size_t>(1, qc.size()));
+    std::memset(h, 0, o_ev_);
     std::memcpy(h, &bd, sizeof(bd));
     std::memcpy(h + o_ev_, evh.data(), sizeof(EventDev) * E);
     if (!pc.empty()) std::memcpy(h + o_pc_, pc.data(), sizeof(Chunk) * pc.size());
     if (!qc.empty()) std::memcpy(h + o_qc_, qc.data(), sizeof(Chunk) * qc.size());
-    FRNN_HIP(hipMemcpyAsync(desc.get(), h, o_qc_ + sizeof(Chunk) * qc.size(), hipMemcpyHostToDevice, s));
+}
+
+void BatchContext::upload(hipStream_t s, const OutDesc *od) {
+    char *h = stage_.as<char>();
+    if (od) std::memcpy(h + kOutOff, od, sizeof(OutDesc));
+    FRNN_HIP(hipMemcpyAsync(desc.get(), h, stage_bytes_, hipMemcpyHostToDevice, s));
 }
 
 void BatchContext::launch_a(hipStream_t s) {
@@ -272,25 +289,38 @@ static bool capture(hipStream_t s, hipGraph_t *g, hipGraphExec_t *ge, void (*fn)
     return true;
 }
 
-void BatchContext::phase_a(hipStream_t s) {
-    if (graphs_enabled && !prof_enabled()) {
-        if (!ga_ &&
-            !capture(s, &gra_, &ga_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_a(st); }, this))
-            graphs_enabled = false;
-        if (ga_) {
-            FRNN_HIP(hipGraphLaunch(ga_, s));
-            ++replays;
-            return;
-        }
+// Replays graph *ge, capturing it from fn first; false when graphs are off
+// or capture fails (the caller then launches eagerly).
+bool BatchContext::replay(hipGraphExec_t *ge, hipGraph_t *g, void (*fn)(void *, hipStream_t), hipStream_t s) {
+    if (!graphs_enabled || prof_enabled()) return false;
+    if (!*ge && !capture(s, g, ge, fn, this)) {
+        graphs_enabled = false;
+        return false;
     }
-    launch_a(s);
+    FRNN_HIP(hipGraphLaunch(*ge, s));
+    ++replays;
+    return true;
+}
+
+void BatchContext::phase_a(hipStream_t s) {
+    if (!replay(&ga_, &gra_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_a(st); }, s))
+        launch_a(s);
 }
 
 BatchCounts BatchContext::read_counts(hipStream_t s) {
+    fetch_counts(s);
+    return wait_counts();
+}
+
+void BatchContext::fetch_counts(hipStream_t s) {
     const size_t hvb = 2 * sizeof(Counters) + sizeof(int64_t) * (E_ + 1);
-    char *p = (char *)back_.ensure(hvb);
-    FRNN_HIP(hipMemcpyAsync(p, hv.get(), hvb, hipMemcpyDeviceToHost, s));
-    FRNN_HIP(hipStreamSynchronize(s));
+    FRNN_HIP(hipMemcpyAsync(back_.ensure(hvb), hv.get(), hvb, hipMemcpyDeviceToHost, s));
+    FRNN_HIP(hipEventRecord(counted_, s));
+}
+
+BatchCounts BatchContext::wait_counts() {
+    FRNN_HIP(hipEventSynchronize(counted_));
+    const char *p = back_.as<char>();
     BatchCounts c;
     std::memcpy(&c.ctr, p, sizeof(Counters));
     Counters cb;
@@ -303,18 +333,26 @@ BatchCounts BatchContext::read_counts(hipStream_t s) {
 
 void BatchContext::phase_b(const OutDesc &od, hipStream_t s) {
     LAUNCH("set_out", s, launch_set_out(bq_, od, s));
-    if (graphs_enabled && !prof_enabled()) {
-        if (!gb_ &&
-            !capture(s, &grb_, &gb_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_b(st); }, this)) {
-            launch_b(s);
-            return;
-        }
-        if (gb_) {
-            FRNN_HIP(hipGraphLaunch(gb_, s));
-            return;
-        }
-    }
-    launch_b(s);
+    phase_b(s);
+}
+
+void BatchContext::phase_b(hipStream_t s) {
+    if (!replay(&gb_, &grb_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_b(st); }, s))
+        launch_b(s);
+}
+
+bool BatchContext::guess(int64_t *pairs, int64_t *long_keys) const {
+    if (seen_pairs_ < 0) return false;
+    // a quarter more than the previous run (batches of one class differ in
+    // size by less than that), plus a floor for tiny outputs
+    *pairs = seen_pairs_ + seen_pairs_ / 4 + 4096;
+    *long_keys = seen_long_ + seen_long_ / 4 + 4096;
+    return true;
+}
+
+void BatchContext::learn(const BatchCounts &c) {
+    seen_pairs_ = (int64_t)c.ctr.nnz;
+    seen_long_ = (int64_t)c.ctr.long_total;
 }
 
 // ---------------------------------------------------------------- cache
@@ -370,22 +408,26 @@ void return_context(std::unique_ptr<BatchContext> ctx, hipStream_t s) {
     }
 }
 
-BatchOutput alloc_output(const BatchContext &ctx, const BatchCounts &c, bool want_d2, hipStream_t s) {
+BatchOutput alloc_output(const BatchContext &ctx, int64_t pairs, int64_t long_keys, bool want_d2,
+                         hipStream_t s) {
     BatchOutput bo;
     const int E = ctx.E();
-    const int64_t nnz = (int64_t)c.ctr.nnz;
     const size_t b_off = sizeof(int64_t) * (ctx.total_q() + E);
-    const size_t b_idx = (sizeof(int32_t) * nnz + 255) / 256 * 256;
-    const size_t b_d2 = want_d2 ? sizeof(float) * nnz : 0;
+    const size_t b_idx = (sizeof(int32_t) * pairs + 255) / 256 * 256;
+    const size_t b_d2 = want_d2 ? sizeof(float) * pairs : 0;
     std::unique_ptr<OutputOwner> own(new OutputOwner());
     own->buf.reset(b_off + b_idx + b_d2, s);
-    bo.long_keys.reset(sizeof(uint64_t) * std::max<uint64_t>(1, c.ctr.long_total), s);
+    bo.long_keys.reset(sizeof(uint64_t) * std::max<int64_t>(1, long_keys), s);
     char *ob = own->buf.as<char>();
     bo.od = OutDesc{reinterpret_cast<int64_t *>(ob), reinterpret_cast<int32_t *>(ob + b_off),
                     want_d2 ? reinterpret_cast<float *>(ob + b_off + b_idx) : nullptr,
-                    bo.long_keys.as<uint64_t>()};
+                    bo.long_keys.as<uint64_t>(), pairs, long_keys};
     bo.own = own.release();
     return bo;
+}
+
+BatchOutput alloc_output(const BatchContext &ctx, const BatchCounts &c, bool want_d2, hipStream_t s) {
+    return alloc_output(ctx, (int64_t)c.ctr.nnz, (int64_t)c.ctr.long_total, want_d2, s);
 }
 
 void hand_out(const BatchContext &ctx, const BatchCounts &c, BatchOutput &bo, frnn_csr *outs) {
@@ -407,11 +449,26 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
                       const Opts &o, hipStream_t s, frnn_csr *outs) {
     BatchContext::Shape need = BatchContext::shape_for(ev, E, D, r, K, flags, o);
     std::unique_ptr<BatchContext> ctx = acquire_context(need, s);
+    const bool want_d2 = flags & FRNN_WANT_DIST2;
     frnn_status st = FRNN_OK;
     try {
-        ctx->set_inputs(ev, E, s);
+        ctx->prepare(ev, E);
+        int64_t cap_pairs = 0, cap_long = 0;
+        BatchOutput bo;
+        const bool spec = ctx->guess(&cap_pairs, &cap_long);
+        if (spec) {
+            bo = alloc_output(*ctx, cap_pairs, cap_long, want_d2, s);
+            ctx->upload(s, &bo.od);
+        } else {
+            ctx->upload(s, nullptr);
+        }
+        // the output owner is freed here unless handed out
+        std::unique_ptr<OutputOwner> own(bo.own);
+        bo.own = nullptr;
         ctx->phase_a(s);
-        BatchCounts c = ctx->read_counts(s);
+        ctx->fetch_counts(s);
+        if (spec) ctx->phase_b(s);  // runs while the host reads the counts
+        BatchCounts c = ctx->wait_counts();
         if (c.build_status & kStatusNonfinitePts) {
             st = fail(FRNN_ERR_NONFINITE, "non-finite coordinate in the points");
         } else if (c.ctr.status & kStatusNonfiniteQry) {
@@ -419,13 +476,16 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
         } else if (c.bases[E] != (int64_t)c.ctr.nnz) {
             st = fail(FRNN_ERR_INTERNAL, "pair count mismatch");
         } else {
-            BatchOutput bo = alloc_output(*ctx, c, flags & FRNN_WANT_DIST2, s);
-            try {
+            ctx->learn(c);
+            if (!spec || (int64_t)c.ctr.nnz > cap_pairs || (int64_t)c.ctr.long_total > cap_long) {
+                // exact size; a speculative fill (if any) wrote nothing
+                own.reset();
+                bo = alloc_output(*ctx, c, want_d2, s);
+                own.reset(bo.own);
+                bo.own = nullptr;
                 ctx->phase_b(bo.od, s);
-            } catch (...) {
-                delete bo.own;
-                throw;
             }
+            bo.own = own.release();
             hand_out(*ctx, c, bo, outs);
             frnn_stats stt{};
             stt.candidates = (int64_t)c.ctr.candidates;

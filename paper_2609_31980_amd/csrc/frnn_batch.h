@@ -3,11 +3,17 @@
 // A BatchContext owns device buffers sized for a capacity class (events,
 // points, queries, cells, chunks; rounded up so that similar batches share a
 // class).  Its launch sequence has fixed grid sizes and reads every actual
-// size from device memory, so it is captured once as two HIP graphs and
+// size from device memory, so it is captured once as HIP graphs and
 // replayed for any batch of its class:
 //   graph A: bin the points of every event, count every query's neighbours,
 //            scan the capped counts        (then one 8-byte-per-event read-back)
 //   graph B: fill, sort long rows, per-event offsets
+// Run exactly, A and B are separated by the read-back that sizes the output.
+// Once a context has run, its next batch is run speculatively instead: the
+// output is allocated at a capacity guessed from the previous run, and B is
+// queued right behind A and the read-back, so the host checks the counts
+// while B runs; the fill kernels write nothing when the run does not fit,
+// and only then does the host allocate the exact size and replay B.
 // The count and fill kernels are persistent: a grid of resident workgroups
 // drains one device work queue of (event, cell block) items.
 #pragma once
@@ -49,14 +55,27 @@ public:
                            const Opts &o);
     bool fits(const Shape &need) const;
 
-    // 1. descriptors of this batch (host -> device, on stream s)
+    // 1. descriptors of this batch (host -> device, on stream s); prepare
+    //    stages them in pinned memory, upload copies them (and, when given,
+    //    the output descriptor) in one transfer
     void set_inputs(const frnn_event *ev, int E, hipStream_t s);
+    void prepare(const frnn_event *ev, int E);
+    void upload(hipStream_t s, const OutDesc *od);
     // 2. bin + count + scan (graph A)
     void phase_a(hipStream_t s);
-    // 3. wait for phase A and read the counters
+    // 3. wait for phase A and read the counters (fetch_counts queues the
+    //    read-back, wait_counts waits for it)
     BatchCounts read_counts(hipStream_t s);
-    // 4. fill into the given output (graph B)
+    void fetch_counts(hipStream_t s);
+    BatchCounts wait_counts();
+    // 4. fill into the given output (graph B); without an argument, into
+    //    the output descriptor given to upload
     void phase_b(const OutDesc &od, hipStream_t s);
+    void phase_b(hipStream_t s);
+
+    // Output capacities for a speculative run (false before the first run).
+    bool guess(int64_t *pairs, int64_t *long_keys) const;
+    void learn(const BatchCounts &c);
 
     // Make every buffer's stream-ordered release follow stream s (the
     // stream of the current user, or null once the device work is done).
@@ -72,6 +91,7 @@ public:
 private:
     void launch_a(hipStream_t s);
     void launch_b(hipStream_t s);
+    bool replay(hipGraphExec_t *ge, hipGraph_t *g, void (*fn)(void *, hipStream_t), hipStream_t s);
     Shape sh_;
     int Dp_ = 0;
     int E_ = 0;
@@ -81,8 +101,11 @@ private:
     Bufs bb_{}, bq_{};  // build run and query run
     size_t o_ev_ = 0, o_pc_ = 0, o_qc_ = 0;
     DevBuf desc, hv, grid, cell_off, ext, xs, perm, key, rank,
-        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, stash, flist, part, outd;
+        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, stash, flist, part;
     Pinned stage_, back_;
+    size_t stage_bytes_ = 0;
+    int64_t seen_pairs_ = -1, seen_long_ = 0;  // the previous run's output
+    hipEvent_t counted_ = nullptr;  // recorded after the read-back
     hipGraphExec_t ga_ = nullptr, gb_ = nullptr;
     hipGraph_t gra_ = nullptr, grb_ = nullptr;
 };
@@ -102,6 +125,9 @@ struct BatchOutput {
     OutDesc od{};
     DevBuf long_keys;
 };
+// Capacities: pairs (indices and dist2) and long-row keys.
+BatchOutput alloc_output(const BatchContext &ctx, int64_t pairs, int64_t long_keys, bool want_d2,
+                         hipStream_t s);
 BatchOutput alloc_output(const BatchContext &ctx, const BatchCounts &c, bool want_d2, hipStream_t s);
 void hand_out(const BatchContext &ctx, const BatchCounts &c, BatchOutput &bo, frnn_csr *outs);
 

@@ -94,11 +94,17 @@ constexpr uint32_t kStatusNonfiniteQry = 2u;
 constexpr uint32_t kStatusInternal = 4u;
 
 // Where the fill pass writes (device-resident so graphs need not change).
+// An output may be allocated before the pair count is known, at a capacity
+// guessed from earlier runs: when the run's pairs or long-row keys exceed
+// the capacities below, the fill kernels write nothing and the host fills
+// again into an output of the exact size.
 struct OutDesc {
     int64_t *offsets;      // per-event offsets, event e at q_off + e
-    int32_t *indices;
-    float *dist2;          // may be null
-    uint64_t *long_keys;   // scratch of the rows sorted in global memory
+    int32_t *indices;      // [cap_pairs]
+    float *dist2;          // [cap_pairs] or null
+    uint64_t *long_keys;   // [cap_long] scratch of the rows sorted in global memory
+    int64_t cap_pairs;
+    int64_t cap_long;
 };
 
 // Per-run scalars passed by value.

@@ -834,6 +834,12 @@ __device__ __forceinline__ void sort_and_write(const uint64_t *hits, uint32_t n,
     }
 }
 
+// True when the run's output fits the output's capacities (every block of
+// a fill kernel reads the same counters, so a block leaves whole).
+__device__ __forceinline__ bool out_fits(const Bufs &b) {
+    return (int64_t)b.ctr->nnz <= b.out->cap_pairs && (int64_t)b.ctr->long_total <= b.out->cap_long;
+}
+
 // Work assignment.  The sorted queries of each event are cut into windows
 // of kn.window (<= 64) consecutive slots (each chunk of kChunkRows slots
 // holds kChunkRows / window of them).  A wave evaluates one window at a time.
@@ -1255,11 +1261,15 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
 // holds one copy of the window body.
 template <int DT, bool EXACT_D, bool FILL, int KR, bool PERS>
 __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
+    if constexpr (FILL)
+        if (!out_fits(b)) return;
     query_body<DT, EXACT_D, FILL, KR, PERS>(b, kn);
 }
 
 template <int DT, bool EXACT_D, bool FILL, int KR, bool PERS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_query_o5(Bufs b, Knobs kn) {
+    if constexpr (FILL)
+        if (!out_fits(b)) return;
     query_body<DT, EXACT_D, FILL, KR, PERS>(b, kn);
 }
 
@@ -1320,6 +1330,9 @@ template <int SC>
 __global__ void __launch_bounds__(kChunkRows) k_short_rows(Bufs b, Knobs kn) {
     __shared__ uint32_t sidx[SC > 0 ? kShortStage : 1];
     __shared__ float sd2[SC > 0 ? kShortStage : 1];
+    if (!out_fits(b)) return;
+    if (blockIdx.x == 0)  // each event's leading offset, the one entry no row writes
+        for (int e = threadIdx.x; e < b.bd->E; e += blockDim.x) b.out->offsets[b.ev[e].q_off + e] = 0;
     if (blockIdx.x >= (unsigned)b.bd->n_qchunks) return;
     const Chunk ch = b.qchunks[blockIdx.x];
     const int64_t qid = ch.r0 + (int64_t)threadIdx.x;
@@ -1375,6 +1388,7 @@ __global__ void __launch_bounds__(kChunkRows) k_short_rows(Bufs b, Knobs kn) {
 // all-ascending bitonic network (absent elements past n act as +infinity and
 // never move), then write the first min(n, K).
 __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
+    if (!out_fits(b)) return;
     const uint32_t n_long = b.ctr->n_long;
     for (uint32_t li = blockIdx.x; li < n_long; li += gridDim.x) {
         const uint32_t qid = b.long_rows[li];
@@ -1423,12 +1437,7 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
 
 // Writes the output descriptor from kernel arguments (so the values are
 // captured at launch time, unlike a copy from host memory).
-// Also writes each event's leading zero offset (offsets[q_off + e]), the
-// one per-event entry no query row writes.
-__global__ void k_set_out(Bufs b, OutDesc v) {
-    if (threadIdx.x == 0) *b.out = v;
-    for (int e = threadIdx.x; e < b.bd->E; e += blockDim.x) v.offsets[b.ev[e].q_off + e] = 0;
-}
+__global__ void k_set_out(Bufs b, OutDesc v) { *b.out = v; }
 
 // --------------------------------------------------------------- launches
 #define FRNN_CHECK_LAUNCH() \
@@ -1568,7 +1577,7 @@ hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStrea
 }
 
 hipError_t launch_set_out(const Bufs &b, const OutDesc &v, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_out, dim3(1), dim3(256), 0, s, b, v);
+    hipLaunchKernelGGL(k_set_out, dim3(1), dim3(1), 0, s, b, v);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }

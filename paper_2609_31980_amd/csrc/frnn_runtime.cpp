@@ -556,7 +556,8 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     char *ob = own->buf.as<char>();
     DevBuf lkeys(sizeof(uint64_t) * std::max<uint64_t>(1, c.long_total), s);
     OutDesc od{reinterpret_cast<int64_t *>(ob), reinterpret_cast<int32_t *>(ob + b_off),
-               want_d2 ? reinterpret_cast<float *>(ob + b_off + b_idx) : nullptr, lkeys.as<uint64_t>()};
+               want_d2 ? reinterpret_cast<float *>(ob + b_off + b_idx) : nullptr, lkeys.as<uint64_t>(),
+               nnz, (int64_t)c.long_total};
     LAUNCH("set_out", s, launch_set_out(b, od, s));
     LAUNCH("short_rows", s, launch_short_rows(b, kn, nqc, s));
     if (c.n_fill) LAUNCH("fill", s, launch_fill(b, kn, D, fill_blocks(c.n_fill), s));

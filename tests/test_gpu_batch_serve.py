@@ -181,3 +181,30 @@ def test_density_workload_full_size(orc, frnn):
     odeg = orc.degrees(w.points, w.r, Q=w.queries)
     assert np.array_equal(gdeg, odeg), "uncapped counts differ"
     say(f"density: mean degree {gdeg.mean():.1f}, rows over K: {(gdeg > w.K).mean():.2f}")
+
+
+def test_batch_speculative_output_overflow(orc, frnn):
+    """A context allocates its next output at a size learned from its previous
+    run; a batch of the same class with far more pairs and long rows must
+    fall back to an exact-size fill and still match the oracle, in graph
+    replay and in eager launches."""
+    n, r = 6000, 0.0625
+    sparse = inputs.uniform_cube(n, 8, seed=90)
+    dense = inputs.tracks(n, 8, track_size=700, sigma=0.002, noise_frac=0.0, seed=91)
+    want = {"sparse": pinlib.as_tuple(orc.frnn(sparse, r, 0)), "dense": pinlib.as_tuple(orc.frnn(dense, r, 0))}
+    assert len(want["dense"][1]) > 20 * len(want["sparse"][1])
+    assert np.diff(want["dense"][0]).max() > 512  # rows sorted in global memory
+    for eager in (False, True):
+        if eager:
+            frnn.profile_enable(True)
+        try:
+            for name in ("sparse", "dense", "dense", "sparse", "dense"):
+                x = sparse if name == "sparse" else dense
+                say(f"speculative batch {name} eager={eager}")
+                o = frnn.query_batch([dev(x)], r, 0)[0]
+                pinlib.assert_csr_equal(_np(o), want[name], f"{name} eager={eager}")
+                o.release()
+        finally:
+            if eager:
+                frnn.profile_enable(False)
+                frnn.profile_read()
