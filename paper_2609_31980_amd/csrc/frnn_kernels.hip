@@ -1346,29 +1346,42 @@ __global__ void __launch_bounds__(kChunkRows) k_short_rows(Bufs b, Knobs kn) {
         const bool staged = len <= kShortStage;
         int32_t *oi = b.out->indices + off;
         float *od = b.out->dist2 ? b.out->dist2 + off : nullptr;
+        // the first half of the stash row is read before the row length
+        // arrives (one memory round trip less; most rows are that short),
+        // the second half only for longer rows; entries past the length are
+        // masked afterwards
+        const uint64_t *st = b.stash + qid * SC;
+        uint64_t v[SC];
+#pragma unroll
+        for (int i = 0; i < SC; i += 2) {
+            ulonglong2 t = make_ulonglong2(~0ull, ~0ull);
+            if (row && i < SC / 2) t = *reinterpret_cast<const ulonglong2 *>(st + i);
+            v[i] = t.x;
+            v[i + 1] = t.y;
+        }
         const uint32_t dq = row ? b.deg[qid] : 0u;
         const bool mine = dq > 0 && dq <= (uint32_t)SC;
         const bool full = ballot(mine && dq > (uint32_t)(SC / 2)) != 0;  // network size, per wave
         if (mine) {
             const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
-            const uint64_t *st = b.stash + qid * SC;
-            auto load = [&](auto &v, int n) {
+            if (dq > (uint32_t)(SC / 2)) {
 #pragma unroll
-                for (int i = 0; i < n; i += 2) {
-                    ulonglong2 t = make_ulonglong2(~0ull, ~0ull);
-                    if ((uint32_t)i < dq) t = *reinterpret_cast<const ulonglong2 *>(st + i);
+                for (int i = SC / 2; i < SC; i += 2) {
+                    const ulonglong2 t = *reinterpret_cast<const ulonglong2 *>(st + i);
                     v[i] = t.x;
-                    v[i + 1] = (uint32_t)(i + 1) < dq ? t.y : ~0ull;
+                    v[i + 1] = t.y;
                 }
-            };
+            }
+#pragma unroll
+            for (int i = 0; i < SC; ++i)
+                if ((uint32_t)i >= dq) v[i] = ~0ull;
             if (full) {
-                uint64_t v[SC];
-                load(v, SC);
                 place_row<SC>(v, keep, staged, off - base, sidx, sd2, oi, od);
             } else {
-                uint64_t v[SC / 2];
-                load(v, SC / 2);
-                place_row<SC / 2>(v, keep, staged, off - base, sidx, sd2, oi, od);
+                uint64_t h[SC / 2];
+#pragma unroll
+                for (int i = 0; i < SC / 2; ++i) h[i] = v[i];
+                place_row<SC / 2>(h, keep, staged, off - base, sidx, sd2, oi, od);
             }
         }
         if (staged) {
