@@ -153,13 +153,20 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     kn_.persistent = sh.o.persistent;
     kn_.stash_cap = sh.o.stash_cap;
     FRNN_HIP(hipEventCreateWithFlags(&counted_, hipEventDisableTiming));
+    FRNN_HIP(hipEventCreateWithFlags(&done_, hipEventDisableTiming));
 }
 
 void BatchContext::retarget(hipStream_t s) {
     DevBuf *all[] = {&desc, &hv, &grid, &cell_off, &ext,
                      &xs, &perm, &key, &rank, &skey, &cells, &qs, &qperm, &qkey, &qrank, &sqkey,
-                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &stash, &flist, &part};
+                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &stash, &flist, &part, &lk_};
     for (DevBuf *d : all) d->set_stream(s);
+}
+
+uint64_t *BatchContext::long_scratch(int64_t n, hipStream_t s) {
+    const size_t need = sizeof(uint64_t) * (size_t)std::max<int64_t>(1, n);
+    if (lk_.bytes() < need) lk_.reset(need, s);
+    return lk_.as<uint64_t>();
 }
 
 BatchContext::~BatchContext() {
@@ -168,6 +175,7 @@ BatchContext::~BatchContext() {
     for (hipGraph_t g : {gra_, grb_})
         if (g) (void)hipGraphDestroy(g);
     if (counted_) (void)hipEventDestroy(counted_);
+    if (done_) (void)hipEventDestroy(done_);
 }
 
 void BatchContext::set_inputs(const frnn_event *ev, int E, hipStream_t s) {
@@ -359,7 +367,7 @@ void BatchContext::learn(const BatchCounts &c) {
 namespace {
 struct Cached {
     std::unique_ptr<BatchContext> ctx;
-    hipEvent_t done;
+    hipStream_t stream;  // stream of its last run (its done event is recorded there)
 };
 std::mutex g_cache_mu;
 // never destroyed: no HIP call may run from a static destructor at exit
@@ -379,8 +387,7 @@ std::unique_ptr<BatchContext> acquire_context(const BatchContext::Shape &need, h
             Cached c = std::move(g_cache[best]);
             g_cache.erase(g_cache.begin() + best);
             // the previous run of this context may still be on another stream
-            FRNN_HIP(hipStreamWaitEvent(s, c.done, 0));
-            (void)hipEventDestroy(c.done);
+            if (c.stream != s) FRNN_HIP(hipStreamWaitEvent(s, c.ctx->done(), 0));
             c.ctx->retarget(s);
             return std::move(c.ctx);
         }
@@ -389,27 +396,24 @@ std::unique_ptr<BatchContext> acquire_context(const BatchContext::Shape &need, h
 }
 
 void return_context(std::unique_ptr<BatchContext> ctx, hipStream_t s) {
-    hipEvent_t ev = nullptr;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, s) != hipSuccess) {
+    if (hipEventRecord(ctx->done(), s) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipStreamSynchronize(s);
-        if (ev) (void)hipEventDestroy(ev);
         ctx->retarget(nullptr);
         return;  // drop the context
     }
     std::lock_guard<std::mutex> g(g_cache_mu);
-    g_cache.push_back(Cached{std::move(ctx), ev});
+    g_cache.push_back(Cached{std::move(ctx), s});
     if (g_cache.size() > kCacheMax) {
         Cached old = std::move(g_cache.front());
         g_cache.erase(g_cache.begin());
-        (void)hipEventSynchronize(old.done);
-        (void)hipEventDestroy(old.done);
+        (void)hipEventSynchronize(old.ctx->done());
         old.ctx->retarget(nullptr);  // its work is done; its stream may be gone
     }
 }
 
 BatchOutput alloc_output(const BatchContext &ctx, int64_t pairs, int64_t long_keys, bool want_d2,
-                         hipStream_t s) {
+                         hipStream_t s, uint64_t *long_scratch) {
     BatchOutput bo;
     const int E = ctx.E();
     const size_t b_off = sizeof(int64_t) * (ctx.total_q() + E);
@@ -417,11 +421,14 @@ BatchOutput alloc_output(const BatchContext &ctx, int64_t pairs, int64_t long_ke
     const size_t b_d2 = want_d2 ? sizeof(float) * pairs : 0;
     std::unique_ptr<OutputOwner> own(new OutputOwner());
     own->buf.reset(b_off + b_idx + b_d2, s);
-    bo.long_keys.reset(sizeof(uint64_t) * std::max<int64_t>(1, long_keys), s);
+    if (!long_scratch) {
+        bo.long_keys.reset(sizeof(uint64_t) * std::max<int64_t>(1, long_keys), s);
+        long_scratch = bo.long_keys.as<uint64_t>();
+    }
     char *ob = own->buf.as<char>();
     bo.od = OutDesc{reinterpret_cast<int64_t *>(ob), reinterpret_cast<int32_t *>(ob + b_off),
                     want_d2 ? reinterpret_cast<float *>(ob + b_off + b_idx) : nullptr,
-                    bo.long_keys.as<uint64_t>(), pairs, long_keys};
+                    long_scratch, pairs, long_keys};
     bo.own = own.release();
     return bo;
 }
@@ -457,7 +464,7 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
         BatchOutput bo;
         const bool spec = ctx->guess(&cap_pairs, &cap_long);
         if (spec) {
-            bo = alloc_output(*ctx, cap_pairs, cap_long, want_d2, s);
+            bo = alloc_output(*ctx, cap_pairs, cap_long, want_d2, s, ctx->long_scratch(cap_long, s));
             ctx->upload(s, &bo.od);
         } else {
             ctx->upload(s, nullptr);

@@ -81,6 +81,10 @@ public:
     // stream of the current user, or null once the device work is done).
     void retarget(hipStream_t s);
 
+    // recorded on the stream of the last run when the context is returned
+    hipEvent_t done() const { return done_; }
+    // long-row key scratch of speculative runs, grown to at least n keys
+    uint64_t *long_scratch(int64_t n, hipStream_t s);
     int E() const { return E_; }
     const std::vector<int64_t> &q_off() const { return qoff_; }
     const std::vector<int64_t> &n_q() const { return nq_; }
@@ -106,6 +110,8 @@ private:
     size_t stage_bytes_ = 0;
     int64_t seen_pairs_ = -1, seen_long_ = 0;  // the previous run's output
     hipEvent_t counted_ = nullptr;  // recorded after the read-back
+    hipEvent_t done_ = nullptr;
+    DevBuf lk_;
     hipGraphExec_t ga_ = nullptr, gb_ = nullptr;
     hipGraph_t gra_ = nullptr, grb_ = nullptr;
 };
@@ -125,9 +131,10 @@ struct BatchOutput {
     OutDesc od{};
     DevBuf long_keys;
 };
-// Capacities: pairs (indices and dist2) and long-row keys.
+// Capacities: pairs (indices and dist2) and long-row keys (in long_scratch
+// when given, else in a buffer of the output's own).
 BatchOutput alloc_output(const BatchContext &ctx, int64_t pairs, int64_t long_keys, bool want_d2,
-                         hipStream_t s);
+                         hipStream_t s, uint64_t *long_scratch = nullptr);
 BatchOutput alloc_output(const BatchContext &ctx, const BatchCounts &c, bool want_d2, hipStream_t s);
 void hand_out(const BatchContext &ctx, const BatchCounts &c, BatchOutput &bo, frnn_csr *outs);
 

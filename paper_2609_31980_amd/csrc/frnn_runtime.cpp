@@ -75,7 +75,7 @@ void *Pool::alloc(size_t bytes, hipStream_t s) {
             hipError_t e = hipStreamWaitEvent(s, got.ready, 0);
             if (e != hipSuccess) throw Fail{FRNN_ERR_HIP, std::string("hipStreamWaitEvent: ") + hipGetErrorString(e)};
         }
-        (void)hipEventDestroy(got.ready);
+        give_event(got.ready);
         std::lock_guard<std::mutex> g(mu_);
         live_.push_back({got.p, cls});
     } else {
@@ -117,9 +117,8 @@ void Pool::free(void *p, hipStream_t s) {
         }
     }
     if (!cls) return;
-    hipEvent_t ev = nullptr;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(ev, s) != hipSuccess) {
+    hipEvent_t ev = take_event();
+    if (!ev || hipEventRecord(ev, s) != hipSuccess) {
         // cannot order the reuse: wait here instead
         (void)hipGetLastError();
         (void)hipStreamSynchronize(s);
@@ -130,6 +129,30 @@ void Pool::free(void *p, hipStream_t s) {
     in_use_ -= (int64_t)cls;
     std::lock_guard<std::mutex> g(mu_);
     free_.push_back({p, cls, ev, s});
+}
+
+hipEvent_t Pool::take_event() {
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        if (!spare_.empty()) {
+            hipEvent_t e = spare_.back();
+            spare_.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// A recorded event may be re-recorded at once: waits already queued on it
+// keep the state they captured.
+void Pool::give_event(hipEvent_t e) {
+    std::lock_guard<std::mutex> g(mu_);
+    spare_.push_back(e);
 }
 
 void Pool::trim() {

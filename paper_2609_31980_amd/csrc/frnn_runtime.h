@@ -58,8 +58,12 @@ private:
         hipStream_t stream; // stream of the free
     };
     static size_t size_class(size_t bytes);
+    // free blocks' events are recycled (creating one costs a runtime call)
+    hipEvent_t take_event();
+    void give_event(hipEvent_t e);
     std::mutex mu_;
     std::vector<Block> free_;
+    std::vector<hipEvent_t> spare_;
     std::vector<std::pair<void *, size_t>> live_;
     std::atomic<int64_t> held_{0}, in_use_{0}, peak_{0};
     std::atomic<int64_t> fail_at_{0};
