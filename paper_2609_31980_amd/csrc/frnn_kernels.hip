@@ -556,18 +556,25 @@ __global__ void __launch_bounds__(256) k_scatter(Bufs b, int32_t queries) {
         const float *src = queries ? ev.qry : ev.pts;
         const int64_t off = queries ? ev.q_off : ev.pt_off;
         const int64_t coff = b.cell_off[ch.ev];
+        // rows of a multiple of 4 floats from a 16-byte aligned array are
+        // read as float4 (the same for every row of the event)
+        const bool vec = D == Dp && (reinterpret_cast<uintptr_t>(src) & 15u) == 0;
         for (int64_t i = ch.r0 + threadIdx.x; i < ch.r1; i += blockDim.x) {
             const uint32_t k = keys[i];
             const uint32_t p = cells[coff + k] + ranks[i];
             const float *row = src + (i - off) * D;
             float4 *out = reinterpret_cast<float4 *>(dst + (int64_t)p * Dp);
-            for (int d4 = 0; d4 < Dp; d4 += 4) {
-                float4 v;
-                v.x = d4 + 0 < D ? row[d4 + 0] : 0.0f;
-                v.y = d4 + 1 < D ? row[d4 + 1] : 0.0f;
-                v.z = d4 + 2 < D ? row[d4 + 2] : 0.0f;
-                v.w = d4 + 3 < D ? row[d4 + 3] : 0.0f;
-                out[d4 / 4] = v;
+            if (vec) {
+                for (int d4 = 0; d4 < Dp; d4 += 4) out[d4 / 4] = *reinterpret_cast<const float4 *>(row + d4);
+            } else {
+                for (int d4 = 0; d4 < Dp; d4 += 4) {
+                    float4 v;
+                    v.x = d4 + 0 < D ? row[d4 + 0] : 0.0f;
+                    v.y = d4 + 1 < D ? row[d4 + 1] : 0.0f;
+                    v.z = d4 + 2 < D ? row[d4 + 2] : 0.0f;
+                    v.w = d4 + 3 < D ? row[d4 + 3] : 0.0f;
+                    out[d4 / 4] = v;
+                }
             }
             perm[p] = (int32_t)(i - off);
             skey[p] = k;

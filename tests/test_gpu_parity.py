@@ -210,3 +210,38 @@ def test_dense_ball_rows_far_above_k(orc, frnn):
     for K in (0, 7, 1000):
         check_full(orc, X, 0.05, K, what=f"dense ball K={K}")
     check_full(orc, X, 0.05, 7, exclude_self=True, what="dense ball K=7 exclude-self")
+
+
+@pytest.mark.parametrize("D", [3, 8, 12])
+def test_unaligned_point_arrays(orc, frnn, D):
+    """Point arrays that start off a 16-byte boundary (a view one float into
+    its storage) take the scalar row loads and give the same lists, through
+    the eager API and the batched graph path."""
+    import torch
+    X = inputs.tracks(5000, D, seed=300 + D)
+    Q = inputs.tracks(700, D, seed=400 + D)
+    want = pinlib.as_tuple(orc.frnn(X, 0.1, 32))
+    want_q = pinlib.as_tuple(orc.frnn(X, 0.1, 32, Q=Q))
+
+    def unaligned(a):
+        buf = torch.zeros(a.size + 1, dtype=torch.float32, device="cuda")
+        t = buf[1:].view(a.shape)
+        t.copy_(torch.from_numpy(a))
+        assert t.data_ptr() % 16 != 0 and t.is_contiguous()
+        return t
+
+    xd, qd = unaligned(X), unaligned(Q)
+    ix = frnn.build(xd, 0.1)
+    for qq, w, what in ((None, want, "self"), (qd, want_q, "queries")):
+        c = ix.query(qq, 0.1, 32)
+        pinlib.assert_csr_equal(c.numpy(), w, f"unaligned D={D} api {what}")
+        c.release()
+    ix.close()
+    for _ in range(2):  # the second run replays the graphs
+        o = frnn.query_batch([xd], 0.1, 32)[0]
+        pinlib.assert_csr_equal(o.numpy(), want, f"unaligned D={D} batch self")
+        o.release()
+        o = frnn.query_batch([xd], 0.1, 32, queries=[qd])[0]
+        pinlib.assert_csr_equal(o.numpy(), want_q, f"unaligned D={D} batch queries")
+        o.release()
+    torch.cuda.synchronize()
