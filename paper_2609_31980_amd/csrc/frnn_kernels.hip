@@ -1082,20 +1082,24 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                             }
                         }
                         const float s = dist2<DT, EXACT_D>(qr, x, D);
-                        bool hit = s <= thr;  // thr < 0 on lanes past the group's candidates
-                        if constexpr (decltype(excl)::value) hit = hit && pos != (uint32_t)(p0 + t);
-                        const uint64_t hm = ballot(hit);
+                        // thr < 0 on lanes past the group's candidates; with
+                        // self-exclusion the mask comes from two ballots of
+                        // plain compares and each lane tests its own bit
+                        const bool in = s <= thr;
+                        uint64_t hm = ballot(in);
+                        if constexpr (decltype(excl)::value) hm &= ~ballot(pos == (uint32_t)(p0 + t));
+                        const bool hit = decltype(excl)::value ? ((hm >> lane) & 1ull) != 0 : in;
                         if (hm) {
                             const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cntv, t);
                             // the first SC hit keys of each query go to its stash row
-                            if (c < SC && hit) {
+                            if (c < SC) {
                                 const uint32_t slot = c + lanes_below(hm);
-                                if (slot < SC) {
+                                if (hit && slot < SC) {
                                     const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
                                     b.stash[qid * SC + slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
                                 }
                             }
-                            if (lane == t) cntv = c + (uint32_t)__popcll(hm);
+                            cntv = lane == t ? c + (uint32_t)__popcll(hm) : cntv;
                         }
                     }
                 };
