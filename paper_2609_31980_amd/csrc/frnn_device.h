@@ -15,7 +15,7 @@ constexpr int kGMax = 6;         // most grid axes
 constexpr int kDMax = 32;        // most coordinates per point
 constexpr int kRunsMax = 256;    // neighbour runs per work item (LDS table size)
 constexpr int kCandLds = 512;    // candidate positions listed in LDS per work item
-constexpr int kRowLds = 512;     // longest row collected and sorted on chip
+constexpr int kRowLds = 512;     // longest row one wave sorts in registers
 constexpr int kChunkRows = 256;  // rows per chunk of the per-point kernels
 constexpr int kWavesPerBlock = 4;
 
@@ -68,7 +68,7 @@ struct BatchDesc {
 struct Counters {
     uint64_t total_cells;  // sum of the events' cell counts
     uint64_t nnz;          // output pairs (after the cap)
-    uint64_t long_total;   // keys of rows sorted in global memory
+    uint64_t long_total;   // keys in the scratch rows (rows longer than the stash)
     uint64_t candidates;   // distance evaluations of the count pass
     uint32_t n_groups;     // cell-block groups evaluated by the count pass
     uint32_t n_long;       // rows sorted in global memory
@@ -102,7 +102,7 @@ struct OutDesc {
     int64_t *offsets;      // per-event offsets, event e at q_off + e
     int32_t *indices;      // [cap_pairs]
     float *dist2;          // [cap_pairs] or null
-    uint64_t *long_keys;   // [cap_long] scratch of the rows sorted in global memory
+    uint64_t *long_keys;   // [cap_long] scratch rows of the fill pass
     int64_t cap_pairs;
     int64_t cap_long;
 };
@@ -145,7 +145,7 @@ struct Bufs {
     // rows
     uint32_t *deg;         // in-radius count per query (global row)
     int64_t *offs;         // [total_q+1] exclusive scan of capped counts
-    int64_t *lofs;         // [total_q+1] exclusive scan of long-row lengths
+    int64_t *lofs;         // [total_q+1] exclusive scan of the lengths of rows longer than the stash
     uint32_t *long_rows;
     uint64_t *stash;       // [total_q][stash_cap] first hit keys per query (global row)
     uint32_t *fill_list;   // windows holding rows longer than the stash

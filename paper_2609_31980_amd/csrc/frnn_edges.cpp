@@ -55,6 +55,7 @@ frnn_status edges_impl(const frnn_csr *csr, int32_t mode, hipStream_t s, frnn_ed
     Knobs kn{};
     kn.K = 0;
     kn.long_cap = INT_MAX;
+    kn.stash_cap = INT_MAX;  // the row scan's second sum stays zero
 
     EdgeArgs a{};
     a.off = csr->offsets;

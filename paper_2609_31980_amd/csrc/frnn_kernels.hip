@@ -31,6 +31,12 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+__device__ __forceinline__ int64_t readlane64(int64_t v, int t) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, t);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), t);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -612,7 +618,7 @@ __device__ __forceinline__ ulonglong2 scan_load(const Bufs &b, const Knobs &kn, 
         if (i + 1 < n) {
             uint32_t d = b.deg[i];
             v.x = (kn.K > 0 && d > (uint32_t)kn.K) ? (uint32_t)kn.K : d;
-            v.y = d > (uint32_t)kn.long_cap ? d : 0;
+            v.y = d > (uint32_t)kn.stash_cap ? d : 0;
         }
     }
     return v;
@@ -858,18 +864,18 @@ __device__ __forceinline__ bool out_fits(const Bufs &b) {
 //               help the other XCDs' queues
 //
 // Inside a window, one lane per query loads its cell key, original index and
-// (fill pass) row length, and the query rows go to LDS, all in one round of
-// parallel loads; the window's cell-block groups are the runs of equal block
-// keys (a ballot).  For each group the wave lists the neighbour key runs
-// (the next group's runs are fetched while this group is evaluated), keeps
-// the first KR*64 candidates' rows and ids in registers, and evaluates every
-// query of the group against them, 64 candidates per step, one per lane.
-template <int DT, bool EXACT_D, bool FILL, int KR, bool PERS>
+// (fill pass) row length and scratch offset, and the query rows go to LDS,
+// all in one round of parallel loads; the window's cell-block groups are the
+// runs of equal block keys (a ballot).  For each group the wave lists the
+// neighbour key runs (the next group's runs are fetched while this group is
+// evaluated) and evaluates every query of the group against each chunk of 64
+// candidates, one per lane.  The fill pass takes only the windows the count
+// pass listed, and sorts each long row of a group as soon as the group is done.
+template <int DT, bool EXACT_D, bool FILL, bool PERS>
 __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     constexpr int DP = (DT + 3) & ~3;
     __shared__ WaveLds slds[kWavesPerBlock];
     __shared__ float4 sq[kWavesPerBlock][64 * DP / 4];  // the window's query rows
-    __shared__ uint64_t shits[FILL ? kWavesPerBlock : 1][FILL ? kRowLds : 1];
     __shared__ unsigned long long s_cand[kWavesPerBlock];
     __shared__ uint32_t s_groups[kWavesPerBlock];
     const int lane = lane_id();
@@ -922,6 +928,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         const uint32_t wkey = inw ? sqkey[p0 + lane] : 0u;
         const int32_t wperm = inw ? qperm[p0 + lane] : 0;
         const uint32_t wdeg = (FILL && inw) ? b.deg[q_off + wperm] : 0u;
+        const int64_t wrow = (FILL && inw) ? b.lofs[q_off + wperm] : 0;  // scratch row (fill pass)
         uint64_t need = ballot(inw);
         if (FILL) {
             need = ballot(inw && wdeg > SC);  // rows the stash did not hold
@@ -1032,10 +1039,14 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
             }
             if (lane == 0) L.run_pref[nruns] = total;
             wave_lds_sync();
-            if constexpr (!FILL) {
-                // count: candidates in chunks of 64 (one per lane), every query
-                // of the group against each chunk while the next chunk loads;
-                // lane t keeps the running count of window query t
+            {
+                // candidates in chunks of 64 (one per lane), every query of the
+                // group against each chunk while the next chunk loads; lane t
+                // keeps the running count of window query t.  The count pass
+                // keeps each query's first SC hit keys in its stash row; the
+                // fill pass evaluates only the queries with longer rows and
+                // writes all their hit keys to their scratch rows, whose
+                // lengths are the counts
                 uint32_t cntv = 0;
                 uint32_t pn = 0, jn = 0;
                 CandRow<DT> xn;
@@ -1070,6 +1081,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 // decided once per launch (two copies of the loop)
                 auto eval_chunk = [&](auto excl, uint32_t pos, uint32_t j, const CandRow<DT> &x, float thr) {
                     for (int t = gb; t < ge; ++t) {
+                        if constexpr (FILL)
+                            if ((uint32_t)__builtin_amdgcn_readlane((int)wdeg, t) <= SC) continue;
                         QueryRow<DT> qr;
 #pragma unroll
                         for (int d4 = 0; d4 < DP; d4 += 4) {
@@ -1091,8 +1104,12 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                         const bool hit = decltype(excl)::value ? ((hm >> lane) & 1ull) != 0 : in;
                         if (hm) {
                             const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cntv, t);
-                            // the first SC hit keys of each query go to its stash row
-                            if (c < SC) {
+                            if constexpr (FILL) {
+                                const uint32_t slot = c + lanes_below(hm);
+                                if (hit && slot < (uint32_t)__builtin_amdgcn_readlane((int)wdeg, t))
+                                    long_keys[readlane64(wrow, t) + slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                            } else if (c < SC) {
+                                // the first SC hit keys of each query go to its stash row
                                 const uint32_t slot = c + lanes_below(hm);
                                 if (hit && slot < SC) {
                                     const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
@@ -1114,99 +1131,39 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                         eval_chunk(std::false_type{}, pos, j, x, thr);
                 }
                 const bool mine = lane >= gb && lane < ge;
-                if (mine) b.deg[q_off + wperm] = cntv;
-                more = more || ballot(mine && cntv > SC) != 0;
-                my_cand += (uint64_t)total * (uint64_t)(ge - gb);
-            } else {
-                // the first KR*64 candidates stay in registers for every query
-                CandRow<DT> xr[KR];
-                uint32_t pr[KR], pj[KR];
-                uint64_t vmask[KR];  // lanes holding a candidate, per register chunk
-#pragma unroll
-                for (int k = 0; k < KR; ++k) {
-                    const uint32_t v = k * 64 + lane;
-                    vmask[k] = ballot(v < total);
-                    pr[k] = 0;
-                    pj[k] = 0;
-                    if (k * 64 < (int)total) {
-                        pr[k] = v < total ? locate(L, nruns, v) : 0u;
-                        load_row<DT, EXACT_D>(xr[k], b.xs + (int64_t)pr[k] * Dp, D);
-                        pj[k] = (uint32_t)b.perm[pr[k]];
-                    }
-                }
-                // fetch the next group's runs while this one is evaluated
-                if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nln);
-                for (int t = gb; t < ge; ++t) {
-                    const int64_t qp = p0 + t;
-                    QueryRow<DT> qr;
-#pragma unroll
-                    for (int d4 = 0; d4 < DP; d4 += 4) {
-                        if (EXACT_D || d4 < Dp) {
-                            const float4 v = sq[w][t * (Dp / 4) + d4 / 4];
-                            qr.q[d4] = v.x;
-                            if (d4 + 1 < DT) qr.q[d4 + 1] = v.y;
-                            if (d4 + 2 < DT) qr.q[d4 + 2] = v.z;
-                            if (d4 + 3 < DT) qr.q[d4 + 3] = v.w;
-                        }
-                    }
-                    const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
-                    {
+                if constexpr (FILL) {
+                    // each long row received exactly its counted hits
+                    if (ballot(mine && wdeg > SC && cntv != wdeg) && lane == 0)
+                        atomicOr(&b.ctr->status, kStatusInternal);
+                    // the rows are read back by other lanes of this wave
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    for (int t = gb; t < ge; ++t) {
                         const uint32_t dq = (uint32_t)__builtin_amdgcn_readlane((int)wdeg, t);
                         if (dq <= SC) continue;  // sorted from the stash
-                        const int64_t off = b.offs[qid];
-                        const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
-                        const bool lng = dq > (uint32_t)kn.long_cap;
-                        uint64_t *dst = lng ? long_keys + b.lofs[qid] : &shits[w][0];
-                        uint32_t nh = 0;
-                        auto emit = [&](uint64_t hm, float s, uint32_t j) {
-                            if (hm) {
-                                if ((hm >> lane) & 1) {
-                                    const uint32_t slot = nh + lanes_below(hm);
-                                    if (slot < dq) dst[slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
-                                }
-                                nh += (uint32_t)__popcll(hm);
-                            }
-                        };
-#pragma unroll
-                        for (int k = 0; k < KR; ++k) {
-                            if (k * 64 < (int)total) {
-                                const float s = dist2<DT, EXACT_D>(qr, xr[k], D);
-                                uint64_t hm = ballot(s <= r2) & vmask[k];
-                                if (kn.exclude_self) hm &= ~ballot(pr[k] == (uint32_t)qp);
-                                emit(hm, s, pj[k]);
-                            }
-                        }
-                        for (uint32_t v0 = KR * 64; v0 < total; v0 += 64) {
-                            const uint32_t v = v0 + lane;
-                            const bool valid = v < total;
-                            const uint32_t pos = valid ? locate(L, nruns, v) : 0u;
-                            CandRow<DT> x;
-                            load_row<DT, EXACT_D>(x, b.xs + (int64_t)pos * Dp, D);
-                            const float s = dist2<DT, EXACT_D>(qr, x, D);
-                            const bool hit = valid && s <= r2 && !(kn.exclude_self && pos == (uint32_t)qp);
-                            emit(ballot(hit), s, hit ? (uint32_t)b.perm[pos] : 0u);
-                        }
-                        if (nh != dq && lane == 0) atomicOr(&b.ctr->status, kStatusInternal);
-                        if (lng) {
-                            if (lane == 0) {
-                                const uint32_t li = atomicAdd(&b.ctr->n_long, 1u);
-                                b.long_rows[li] = (uint32_t)qid;
-                            }
+                        const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
+                        if (dq > (uint32_t)kn.long_cap) {  // sorted in global memory
+                            if (lane == 0) b.long_rows[atomicAdd(&b.ctr->n_long, 1u)] = (uint32_t)qid;
                             continue;
                         }
-                        wave_lds_sync();
+                        const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
+                        const int64_t off = b.offs[qid];
+                        const uint64_t *h = long_keys + readlane64(wrow, t);
                         int32_t *oi = out_idx + off;
                         float *od = out_d2 ? out_d2 + off : nullptr;
                         if (dq <= 64)
-                            sort_and_write<1>(&shits[w][0], dq, keep, oi, od, lane);
+                            sort_and_write<1>(h, dq, keep, oi, od, lane);
                         else if (dq <= 128)
-                            sort_and_write<2>(&shits[w][0], dq, keep, oi, od, lane);
+                            sort_and_write<2>(h, dq, keep, oi, od, lane);
                         else if (dq <= 256)
-                            sort_and_write<4>(&shits[w][0], dq, keep, oi, od, lane);
+                            sort_and_write<4>(h, dq, keep, oi, od, lane);
                         else
-                            sort_and_write<8>(&shits[w][0], dq, keep, oi, od, lane);
-                        wave_lds_sync();
+                            sort_and_write<8>(h, dq, keep, oi, od, lane);
                     }
+                } else {
+                    if (mine) b.deg[q_off + wperm] = cntv;
+                    more = more || ballot(mine && cntv > SC) != 0;
+                    my_cand += (uint64_t)total * (uint64_t)(ge - gb);
                 }
             }
             wave_lds_sync();
@@ -1270,18 +1227,18 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
 // favour for the 8-dimensional kernel even with a few spilled registers.
 // PERS selects the persistent scheduling at compile time, so each kernel
 // holds one copy of the window body.
-template <int DT, bool EXACT_D, bool FILL, int KR, bool PERS>
+template <int DT, bool EXACT_D, bool FILL, bool PERS>
 __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
     if constexpr (FILL)
         if (!out_fits(b)) return;
-    query_body<DT, EXACT_D, FILL, KR, PERS>(b, kn);
+    query_body<DT, EXACT_D, FILL, PERS>(b, kn);
 }
 
-template <int DT, bool EXACT_D, bool FILL, int KR, bool PERS>
+template <int DT, bool EXACT_D, bool FILL, bool PERS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_query_o5(Bufs b, Knobs kn) {
     if constexpr (FILL)
         if (!out_fits(b)) return;
-    query_body<DT, EXACT_D, FILL, KR, PERS>(b, kn);
+    query_body<DT, EXACT_D, FILL, PERS>(b, kn);
 }
 
 // ------------------------------------------------------------ short rows
@@ -1536,27 +1493,24 @@ template <bool FILL>
 static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
     blocks = (blocks + 7) / 8 * 8;  // whole XCD rounds (see the window remap)
     dim3 grid(blocks), block(64 * kWavesPerBlock);
-    // register-resident candidate chunks: the count pass evaluates every
-    // candidate; the fill pass only re-evaluates rows longer than the stash
-    constexpr int KR3 = FILL ? 1 : 4, KR8 = FILL ? 1 : 2, KR12 = FILL ? 1 : 4, KRG = FILL ? 1 : 2;
     auto go = [&](auto pers) {
         constexpr bool P = decltype(pers)::value;
         switch (D) {
-        case 3: hipLaunchKernelGGL((k_query<3, true, FILL, KR3, P>), grid, block, 0, s, b, kn); break;
+        case 3: hipLaunchKernelGGL((k_query<3, true, FILL, P>), grid, block, 0, s, b, kn); break;
         case 8:
             if constexpr (FILL)
-                hipLaunchKernelGGL((k_query<8, true, true, KR8, P>), grid, block, 0, s, b, kn);
+                hipLaunchKernelGGL((k_query<8, true, true, P>), grid, block, 0, s, b, kn);
             else
-                hipLaunchKernelGGL((k_query_o5<8, true, false, KR8, P>), grid, block, 0, s, b, kn);
+                hipLaunchKernelGGL((k_query_o5<8, true, false, P>), grid, block, 0, s, b, kn);
             break;
-        case 12: hipLaunchKernelGGL((k_query<12, true, FILL, KR12, P>), grid, block, 0, s, b, kn); break;
+        case 12: hipLaunchKernelGGL((k_query<12, true, FILL, P>), grid, block, 0, s, b, kn); break;
         default:
             if (D <= 4)
-                hipLaunchKernelGGL((k_query<4, false, FILL, KR3, P>), grid, block, 0, s, b, kn);
+                hipLaunchKernelGGL((k_query<4, false, FILL, P>), grid, block, 0, s, b, kn);
             else if (D <= 16)
-                hipLaunchKernelGGL((k_query<16, false, FILL, KRG, P>), grid, block, 0, s, b, kn);
+                hipLaunchKernelGGL((k_query<16, false, FILL, P>), grid, block, 0, s, b, kn);
             else
-                hipLaunchKernelGGL((k_query<32, false, FILL, 1, P>), grid, block, 0, s, b, kn);
+                hipLaunchKernelGGL((k_query<32, false, FILL, P>), grid, block, 0, s, b, kn);
         }
     };
     // the fill pass always strides over its window list
