@@ -814,6 +814,32 @@ struct WaveLds {
     unsigned long long starts;  // run starts inside the current chunk (bit per lane); zero between uses
 };
 
+// Sorts the n <= 64 distinct keys h[0..n) of one row by rank: lane i holds
+// key i, and its place is the number of smaller keys, counted from LDS
+// broadcasts 8 keys at a time (buf: 64 keys of LDS, 16-byte aligned; lanes
+// past n hold all-ones keys, which are smaller than no key); the first keep
+// places are written.
+__device__ __forceinline__ void rank_and_write(uint64_t *buf, const uint64_t *h, uint32_t n, uint32_t keep,
+                                               int32_t *idx, float *d2, int lane) {
+    const uint64_t mine = (uint32_t)lane < n ? h[lane] : ~0ull;
+    buf[lane] = mine;
+    wave_lds_sync();
+    uint32_t rank = 0;
+    const ulonglong2 *b2 = reinterpret_cast<const ulonglong2 *>(buf);
+    for (uint32_t i = 0; i < n; i += 8) {
+        ulonglong2 k[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) k[u] = b2[i / 2 + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rank += (k[u].x < mine ? 1u : 0u) + (k[u].y < mine ? 1u : 0u);
+    }
+    wave_lds_sync();
+    if ((uint32_t)lane < n && rank < keep) {
+        idx[rank] = (int32_t)(uint32_t)mine;
+        if (d2) d2[rank] = __uint_as_float((uint32_t)(mine >> 32));
+    }
+}
+
 // Position of candidate v (0 <= v < L) among the group's concatenated runs.
 __device__ __forceinline__ uint32_t locate(const WaveLds &s, int nruns, uint32_t v) {
     int lo = 0, hi = nruns - 1;
@@ -876,6 +902,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     constexpr int DP = (DT + 3) & ~3;
     __shared__ WaveLds slds[kWavesPerBlock];
     __shared__ float4 sq[kWavesPerBlock][64 * DP / 4];  // the window's query rows
+    __shared__ __align__(16) uint64_t srow[FILL ? kWavesPerBlock : 1][64];  // fill pass: one row's keys
     __shared__ unsigned long long s_cand[kWavesPerBlock];
     __shared__ uint32_t s_groups[kWavesPerBlock];
     const int lane = lane_id();
@@ -1152,7 +1179,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                         int32_t *oi = out_idx + off;
                         float *od = out_d2 ? out_d2 + off : nullptr;
                         if (dq <= 64)
-                            sort_and_write<1>(h, dq, keep, oi, od, lane);
+                            rank_and_write(&srow[w][0], h, dq, keep, oi, od, lane);
                         else if (dq <= 128)
                             sort_and_write<2>(h, dq, keep, oi, od, lane);
                         else if (dq <= 256)
