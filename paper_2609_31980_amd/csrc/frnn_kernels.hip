@@ -808,35 +808,51 @@ __device__ __forceinline__ float dist2(const QueryRow<DT> &qr, const CandRow<DT>
     return s;
 }
 
+// Longest row the fill pass sorts itself (by rank); longer rows are listed
+// for k_long_sort.
+constexpr uint32_t kRankMax = 256;
+
 struct WaveLds {
     uint32_t run_base[kRunsMax];
     uint32_t run_pref[kRunsMax + 1];
     unsigned long long starts;  // run starts inside the current chunk (bit per lane); zero between uses
 };
 
-// Sorts the n <= 64 distinct keys h[0..n) of one row by rank: lane i holds
-// key i, and its place is the number of smaller keys, counted from LDS
-// broadcasts 8 keys at a time (buf: 64 keys of LDS, 16-byte aligned; lanes
-// past n hold all-ones keys, which are smaller than no key); the first keep
-// places are written.
+// Sorts the n <= 64*KS distinct keys h[0..n) of one row by rank: lane i
+// holds keys i, 64+i, ..., and each key's place is the number of smaller
+// keys, counted from LDS broadcasts 8 keys at a time (buf: 64*KS keys of
+// LDS, 16-byte aligned; slots past n hold all-ones keys, which are smaller
+// than no key); the first keep places are written.
+template <int KS>
 __device__ __forceinline__ void rank_and_write(uint64_t *buf, const uint64_t *h, uint32_t n, uint32_t keep,
                                                int32_t *idx, float *d2, int lane) {
-    const uint64_t mine = (uint32_t)lane < n ? h[lane] : ~0ull;
-    buf[lane] = mine;
-    wave_lds_sync();
-    uint32_t rank = 0;
-    const ulonglong2 *b2 = reinterpret_cast<const ulonglong2 *>(buf);
-    for (uint32_t i = 0; i < n; i += 8) {
-        ulonglong2 k[4];
+    uint64_t mine[KS];
+    uint32_t rank[KS];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) k[u] = b2[i / 2 + u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) rank += (k[u].x < mine ? 1u : 0u) + (k[u].y < mine ? 1u : 0u);
+    for (int k = 0; k < KS; ++k) {
+        const uint32_t e = (uint32_t)(k * 64 + lane);
+        mine[k] = e < n ? h[e] : ~0ull;
+        buf[e] = mine[k];
+        rank[k] = 0;
     }
     wave_lds_sync();
-    if ((uint32_t)lane < n && rank < keep) {
-        idx[rank] = (int32_t)(uint32_t)mine;
-        if (d2) d2[rank] = __uint_as_float((uint32_t)(mine >> 32));
+    const ulonglong2 *b2 = reinterpret_cast<const ulonglong2 *>(buf);
+    for (uint32_t i = 0; i < n; i += 8) {
+        ulonglong2 c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = b2[i / 2 + u];
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) rank[k] += (c[u].x < mine[k] ? 1u : 0u) + (c[u].y < mine[k] ? 1u : 0u);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        if ((uint32_t)(k * 64 + lane) < n && rank[k] < keep) {
+            idx[rank[k]] = (int32_t)(uint32_t)mine[k];
+            if (d2) d2[rank[k]] = __uint_as_float((uint32_t)(mine[k] >> 32));
+        }
     }
 }
 
@@ -902,7 +918,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     constexpr int DP = (DT + 3) & ~3;
     __shared__ WaveLds slds[kWavesPerBlock];
     __shared__ float4 sq[kWavesPerBlock][64 * DP / 4];  // the window's query rows
-    __shared__ __align__(16) uint64_t srow[FILL ? kWavesPerBlock : 1][64];  // fill pass: one row's keys
+    __shared__ __align__(16) uint64_t srow[FILL ? kWavesPerBlock : 1][FILL ? kRankMax : 1];  // fill: one row's keys
     __shared__ unsigned long long s_cand[kWavesPerBlock];
     __shared__ uint32_t s_groups[kWavesPerBlock];
     const int lane = lane_id();
@@ -1169,7 +1185,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                         const uint32_t dq = (uint32_t)__builtin_amdgcn_readlane((int)wdeg, t);
                         if (dq <= SC) continue;  // sorted from the stash
                         const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
-                        if (dq > (uint32_t)kn.long_cap) {  // sorted in global memory
+                        if (dq > kRankMax || dq > (uint32_t)kn.long_cap) {  // sorted by k_long_sort
                             if (lane == 0) b.long_rows[atomicAdd(&b.ctr->n_long, 1u)] = (uint32_t)qid;
                             continue;
                         }
@@ -1178,14 +1194,13 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                         const uint64_t *h = long_keys + readlane64(wrow, t);
                         int32_t *oi = out_idx + off;
                         float *od = out_d2 ? out_d2 + off : nullptr;
+                        uint64_t *buf = &srow[w][0];
                         if (dq <= 64)
-                            rank_and_write(&srow[w][0], h, dq, keep, oi, od, lane);
+                            rank_and_write<1>(buf, h, dq, keep, oi, od, lane);
                         else if (dq <= 128)
-                            sort_and_write<2>(h, dq, keep, oi, od, lane);
-                        else if (dq <= 256)
-                            sort_and_write<4>(h, dq, keep, oi, od, lane);
+                            rank_and_write<2>(buf, h, dq, keep, oi, od, lane);
                         else
-                            sort_and_write<8>(h, dq, keep, oi, od, lane);
+                            rank_and_write<4>(buf, h, dq, keep, oi, od, lane);
                     }
                 } else {
                     if (mine) b.deg[q_off + wperm] = cntv;
@@ -1259,6 +1274,14 @@ __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
     if constexpr (FILL)
         if (!out_fits(b)) return;
     query_body<DT, EXACT_D, FILL, PERS>(b, kn);
+}
+
+// The fill pass (its row sorts raise the register count) held to 4 resident
+// waves per SIMD (rows of at most 16 floats).
+template <int DT, bool EXACT_D>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_fill(Bufs b, Knobs kn) {
+    if (!out_fits(b)) return;
+    query_body<DT, EXACT_D, true, false>(b, kn);
 }
 
 template <int DT, bool EXACT_D, bool FILL, bool PERS>
@@ -1523,26 +1546,32 @@ static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int bloc
     auto go = [&](auto pers) {
         constexpr bool P = decltype(pers)::value;
         switch (D) {
-        case 3: hipLaunchKernelGGL((k_query<3, true, FILL, P>), grid, block, 0, s, b, kn); break;
-        case 8:
-            if constexpr (FILL)
-                hipLaunchKernelGGL((k_query<8, true, true, P>), grid, block, 0, s, b, kn);
-            else
-                hipLaunchKernelGGL((k_query_o5<8, true, false, P>), grid, block, 0, s, b, kn);
-            break;
-        case 12: hipLaunchKernelGGL((k_query<12, true, FILL, P>), grid, block, 0, s, b, kn); break;
+        case 3: hipLaunchKernelGGL((k_query<3, true, false, P>), grid, block, 0, s, b, kn); break;
+        case 8: hipLaunchKernelGGL((k_query_o5<8, true, false, P>), grid, block, 0, s, b, kn); break;
+        case 12: hipLaunchKernelGGL((k_query<12, true, false, P>), grid, block, 0, s, b, kn); break;
         default:
             if (D <= 4)
-                hipLaunchKernelGGL((k_query<4, false, FILL, P>), grid, block, 0, s, b, kn);
+                hipLaunchKernelGGL((k_query<4, false, false, P>), grid, block, 0, s, b, kn);
             else if (D <= 16)
-                hipLaunchKernelGGL((k_query<16, false, FILL, P>), grid, block, 0, s, b, kn);
+                hipLaunchKernelGGL((k_query<16, false, false, P>), grid, block, 0, s, b, kn);
             else
-                hipLaunchKernelGGL((k_query<32, false, FILL, P>), grid, block, 0, s, b, kn);
+                hipLaunchKernelGGL((k_query<32, false, false, P>), grid, block, 0, s, b, kn);
         }
     };
     // the fill pass always strides over its window list
     if constexpr (FILL) {
-        go(std::false_type{});
+        switch (D) {
+        case 3: hipLaunchKernelGGL((k_fill<3, true>), grid, block, 0, s, b, kn); break;
+        case 8: hipLaunchKernelGGL((k_fill<8, true>), grid, block, 0, s, b, kn); break;
+        case 12: hipLaunchKernelGGL((k_fill<12, true>), grid, block, 0, s, b, kn); break;
+        default:
+            if (D <= 4)
+                hipLaunchKernelGGL((k_fill<4, false>), grid, block, 0, s, b, kn);
+            else if (D <= 16)
+                hipLaunchKernelGGL((k_fill<16, false>), grid, block, 0, s, b, kn);
+            else  // rows of up to 32 floats: the 4-wave target does not fit
+                hipLaunchKernelGGL((k_query<32, false, true, false>), grid, block, 0, s, b, kn);
+        }
     } else {
         if (kn.persistent)
             go(std::true_type{});
