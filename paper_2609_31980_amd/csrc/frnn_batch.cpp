@@ -263,7 +263,7 @@ void BatchContext::launch_a(hipStream_t s) {
 void BatchContext::launch_b(hipStream_t s) {
     LAUNCH("short_rows", s, launch_short_rows(bq_, kn_, sh_.qch_cap, s));
     LAUNCH("fill", s, launch_fill(bq_, kn_, sh_.D, fill_blocks(sh_.qch_cap * (kChunkRows / sh_.o.queries_per_item)), s));
-    LAUNCH("long_sort", s, launch_long_sort(bq_, kn_, 256, s));
+    LAUNCH("long_sort", s, launch_long_sort(bq_, kn_, 1024, s));
 }
 
 static bool capture(hipStream_t s, hipGraph_t *g, hipGraphExec_t *ge, void (*fn)(void *, hipStream_t),

@@ -67,15 +67,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int mask) {
-    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask);
-    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
-__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
-
 // Float bits mapped so that unsigned order is float order (for atomics).
 __device__ __forceinline__ uint32_t f2ord(float f) {
     uint32_t b = __float_as_uint(f);
@@ -88,58 +79,6 @@ __device__ __forceinline__ float ord2f(uint32_t o) {
 
 __device__ __forceinline__ bool finite32(float f) {
     return (__float_as_uint(f) & 0x7f800000u) != 0x7f800000u;
-}
-
-// Sorts 64*KS keys held as v[s] at element s*64 + lane, ascending, with the
-// bitonic network in its all-ascending form (merge step: compare element i
-// with its mirror i ^ (k-1), then half-cleaners i ^ j).  Partners within a
-// slot are other lanes (cross-lane shuffles); partners across slots are the
-// same lane (register compare-exchange).
-template <int KS>
-__device__ __forceinline__ void bitonic_sort(uint64_t (&v)[KS], int lane) {
-    constexpr int N = 64 * KS;
-#pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
-        if (k <= 64) {
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                uint64_t o = shfl_xor64(v[s], k - 1);
-                bool lower = (lane & (k >> 1)) == 0;
-                v[s] = lower ? umin64(v[s], o) : umax64(v[s], o);
-            }
-        } else {
-            const int sm = k / 64 - 1;
-            uint64_t o[KS];
-#pragma unroll
-            for (int s = 0; s < KS; ++s) o[s] = shfl_xor64(v[s ^ sm], 63);
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                bool lower = (s & (k / 128)) == 0;
-                v[s] = lower ? umin64(v[s], o[s]) : umax64(v[s], o[s]);
-            }
-        }
-#pragma unroll
-        for (int j = k >> 2; j >= 1; j >>= 1) {
-            if (j >= 64) {
-                const int sj = j / 64;
-#pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    if ((s & sj) == 0) {
-                        uint64_t a = v[s], c = v[s | sj];
-                        v[s] = umin64(a, c);
-                        v[s | sj] = umax64(a, c);
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    uint64_t o = shfl_xor64(v[s], j);
-                    bool lower = (lane & j) == 0;
-                    v[s] = lower ? umin64(v[s], o) : umax64(v[s], o);
-                }
-            }
-        }
-    }
 }
 
 // ------------------------------------------------------------------ init
@@ -808,10 +747,6 @@ __device__ __forceinline__ float dist2(const QueryRow<DT> &qr, const CandRow<DT>
     return s;
 }
 
-// Longest row the fill pass sorts itself (by rank); longer rows are listed
-// for k_long_sort.
-constexpr uint32_t kRankMax = 256;
-
 struct WaveLds {
     uint32_t run_base[kRunsMax];
     uint32_t run_pref[kRunsMax + 1];
@@ -869,26 +804,6 @@ __device__ __forceinline__ uint32_t locate(const WaveLds &s, int nruns, uint32_t
     return s.run_base[lo] + (v - s.run_pref[lo]);
 }
 
-template <int KS>
-__device__ __forceinline__ void sort_and_write(const uint64_t *hits, uint32_t n, uint32_t keep,
-                                               int32_t *idx, float *d2, int lane) {
-    uint64_t v[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        uint32_t e = s * 64 + lane;
-        v[s] = e < n ? hits[e] : ~0ull;
-    }
-    bitonic_sort<KS>(v, lane);
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        uint32_t e = s * 64 + lane;
-        if (e < keep) {
-            idx[e] = (int32_t)(uint32_t)v[s];
-            if (d2) d2[e] = __uint_as_float((uint32_t)(v[s] >> 32));
-        }
-    }
-}
-
 // True when the run's output fits the output's capacities (every block of
 // a fill kernel reads the same counters, so a block leaves whole).
 __device__ __forceinline__ bool out_fits(const Bufs &b) {
@@ -918,7 +833,6 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     constexpr int DP = (DT + 3) & ~3;
     __shared__ WaveLds slds[kWavesPerBlock];
     __shared__ float4 sq[kWavesPerBlock][64 * DP / 4];  // the window's query rows
-    __shared__ __align__(16) uint64_t srow[FILL ? kWavesPerBlock : 1][FILL ? kRankMax : 1];  // fill: one row's keys
     __shared__ unsigned long long s_cand[kWavesPerBlock];
     __shared__ uint32_t s_groups[kWavesPerBlock];
     const int lane = lane_id();
@@ -935,14 +849,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     const uint32_t *sqkey = kn.self_query ? b.skey : b.sqkey;
     const float *qs = kn.self_query ? b.xs : b.qs;
     const int32_t *qperm = kn.self_query ? b.perm : b.qperm;
-    int32_t *out_idx = nullptr;
-    float *out_d2 = nullptr;
-    uint64_t *long_keys = nullptr;
-    if (FILL) {
-        out_idx = b.out->indices;
-        out_d2 = b.out->dist2;
-        long_keys = b.out->long_keys;
-    }
+    uint64_t *long_keys = FILL ? b.out->long_keys : nullptr;
     const int Wn = kn.window;
     const uint32_t wpc = kChunkRows / Wn;
     const uint32_t nwin = (uint32_t)bd.n_qchunks * wpc;
@@ -1175,33 +1082,15 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 }
                 const bool mine = lane >= gb && lane < ge;
                 if constexpr (FILL) {
-                    // each long row received exactly its counted hits
-                    if (ballot(mine && wdeg > SC && cntv != wdeg) && lane == 0)
-                        atomicOr(&b.ctr->status, kStatusInternal);
-                    // the rows are read back by other lanes of this wave
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                    for (int t = gb; t < ge; ++t) {
-                        const uint32_t dq = (uint32_t)__builtin_amdgcn_readlane((int)wdeg, t);
-                        if (dq <= SC) continue;  // sorted from the stash
-                        const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
-                        if (dq > kRankMax || dq > (uint32_t)kn.long_cap) {  // sorted by k_long_sort
-                            if (lane == 0) b.long_rows[atomicAdd(&b.ctr->n_long, 1u)] = (uint32_t)qid;
-                            continue;
-                        }
-                        const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
-                        const int64_t off = b.offs[qid];
-                        const uint64_t *h = long_keys + readlane64(wrow, t);
-                        int32_t *oi = out_idx + off;
-                        float *od = out_d2 ? out_d2 + off : nullptr;
-                        uint64_t *buf = &srow[w][0];
-                        if (dq <= 64)
-                            rank_and_write<1>(buf, h, dq, keep, oi, od, lane);
-                        else if (dq <= 128)
-                            rank_and_write<2>(buf, h, dq, keep, oi, od, lane);
-                        else
-                            rank_and_write<4>(buf, h, dq, keep, oi, od, lane);
-                    }
+                    // each long row received exactly its counted hits; the
+                    // rows are listed for the row sort (one atomic per group)
+                    const bool lst = mine && wdeg > SC;
+                    if (ballot(lst && cntv != wdeg) && lane == 0) atomicOr(&b.ctr->status, kStatusInternal);
+                    const uint64_t lm = ballot(lst);
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(&b.ctr->n_long, (uint32_t)__popcll(lm));
+                    base = uniform((uint32_t)__shfl((int)base, 0));
+                    if (lst) b.long_rows[base + lanes_below(lm)] = (uint32_t)(q_off + wperm);
                 } else {
                     if (mine) b.deg[q_off + wperm] = cntv;
                     more = more || ballot(mine && cntv > SC) != 0;
@@ -1276,13 +1165,6 @@ __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
     query_body<DT, EXACT_D, FILL, PERS>(b, kn);
 }
 
-// The fill pass (its row sorts raise the register count) held to 4 resident
-// waves per SIMD (rows of at most 16 floats).
-template <int DT, bool EXACT_D>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_fill(Bufs b, Knobs kn) {
-    if (!out_fits(b)) return;
-    query_body<DT, EXACT_D, true, false>(b, kn);
-}
 
 template <int DT, bool EXACT_D, bool FILL, bool PERS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_query_o5(Bufs b, Knobs kn) {
@@ -1415,21 +1297,43 @@ __global__ void __launch_bounds__(kChunkRows) k_short_rows(Bufs b, Knobs kn) {
 }
 
 // ------------------------------------------------------------ long rows
-// One block per long row: sort its keys in place in global memory with the
+// Rows longer than the stash, listed by the fill pass with their keys in
+// their scratch rows, one wave per row: up to the on-chip limit (at most 512
+// keys) sorted by rank, longer rows sorted in place in global memory with the
 // all-ascending bitonic network (absent elements past n act as +infinity and
-// never move), then write the first min(n, K).
+// never move).  Either way the first min(n, K) are written.
 __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
+    __shared__ __align__(16) uint64_t sbuf[kWavesPerBlock][kRowLds];
     if (!out_fits(b)) return;
     const uint32_t n_long = b.ctr->n_long;
-    for (uint32_t li = blockIdx.x; li < n_long; li += gridDim.x) {
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    const uint32_t nw = gridDim.x * kWavesPerBlock;
+    for (uint32_t li = blockIdx.x * kWavesPerBlock + w; li < n_long; li += nw) {
         const uint32_t qid = b.long_rows[li];
         const uint64_t n = b.deg[qid];
         uint64_t *a = b.out->long_keys + b.lofs[qid];
+        const uint64_t keep = (kn.K > 0 && n > (uint64_t)kn.K) ? (uint64_t)kn.K : n;
+        const int64_t off = b.offs[qid];
+        int32_t *oi = b.out->indices + off;
+        float *od = b.out->dist2 ? b.out->dist2 + off : nullptr;
+        if (n <= (uint64_t)kn.long_cap) {
+            const uint32_t n32 = (uint32_t)n, k32 = (uint32_t)keep;
+            if (n <= 64)
+                rank_and_write<1>(&sbuf[w][0], a, n32, k32, oi, od, lane);
+            else if (n <= 128)
+                rank_and_write<2>(&sbuf[w][0], a, n32, k32, oi, od, lane);
+            else if (n <= 256)
+                rank_and_write<4>(&sbuf[w][0], a, n32, k32, oi, od, lane);
+            else
+                rank_and_write<8>(&sbuf[w][0], a, n32, k32, oi, od, lane);
+            continue;
+        }
         uint64_t P = 1;
         while (P < n) P <<= 1;
         for (uint64_t k = 2; k <= P; k <<= 1) {
             const uint64_t half = k >> 1;
-            for (uint64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+            for (uint64_t t = lane; t < P / 2; t += 64) {
                 const uint64_t lo = (t / half) * k + (t % half);
                 const uint64_t hi = lo ^ (k - 1);
                 if (hi < n) {
@@ -1440,9 +1344,11 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
                     }
                 }
             }
-            __syncthreads();
+            // the wave's stores are read back by its other lanes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             for (uint64_t j = k >> 2; j >= 1; j >>= 1) {
-                for (uint64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                for (uint64_t t = lane; t < P / 2; t += 64) {
                     const uint64_t lo = (t / j) * 2 * j + (t % j);
                     const uint64_t hi = lo + j;
                     if (hi < n) {
@@ -1453,16 +1359,14 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
                         }
                     }
                 }
-                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
         }
-        const uint64_t keep = (kn.K > 0 && n > (uint64_t)kn.K) ? (uint64_t)kn.K : n;
-        const int64_t off = b.offs[qid];
-        for (uint64_t e = threadIdx.x; e < keep; e += blockDim.x) {
-            b.out->indices[off + e] = (int32_t)(uint32_t)a[e];
-            if (b.out->dist2) b.out->dist2[off + e] = __uint_as_float((uint32_t)(a[e] >> 32));
+        for (uint64_t e = lane; e < keep; e += 64) {
+            oi[e] = (int32_t)(uint32_t)a[e];
+            if (od) od[e] = __uint_as_float((uint32_t)(a[e] >> 32));
         }
-        __syncthreads();
     }
 }
 
@@ -1561,15 +1465,15 @@ static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int bloc
     // the fill pass always strides over its window list
     if constexpr (FILL) {
         switch (D) {
-        case 3: hipLaunchKernelGGL((k_fill<3, true>), grid, block, 0, s, b, kn); break;
-        case 8: hipLaunchKernelGGL((k_fill<8, true>), grid, block, 0, s, b, kn); break;
-        case 12: hipLaunchKernelGGL((k_fill<12, true>), grid, block, 0, s, b, kn); break;
+        case 3: hipLaunchKernelGGL((k_query<3, true, true, false>), grid, block, 0, s, b, kn); break;
+        case 8: hipLaunchKernelGGL((k_query<8, true, true, false>), grid, block, 0, s, b, kn); break;
+        case 12: hipLaunchKernelGGL((k_query<12, true, true, false>), grid, block, 0, s, b, kn); break;
         default:
             if (D <= 4)
-                hipLaunchKernelGGL((k_fill<4, false>), grid, block, 0, s, b, kn);
+                hipLaunchKernelGGL((k_query<4, false, true, false>), grid, block, 0, s, b, kn);
             else if (D <= 16)
-                hipLaunchKernelGGL((k_fill<16, false>), grid, block, 0, s, b, kn);
-            else  // rows of up to 32 floats: the 4-wave target does not fit
+                hipLaunchKernelGGL((k_query<16, false, true, false>), grid, block, 0, s, b, kn);
+            else
                 hipLaunchKernelGGL((k_query<32, false, true, false>), grid, block, 0, s, b, kn);
         }
     } else {

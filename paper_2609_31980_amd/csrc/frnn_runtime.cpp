@@ -584,7 +584,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     LAUNCH("set_out", s, launch_set_out(b, od, s));
     LAUNCH("short_rows", s, launch_short_rows(b, kn, nqc, s));
     if (c.n_fill) LAUNCH("fill", s, launch_fill(b, kn, D, fill_blocks(c.n_fill), s));
-    if (c.long_total) LAUNCH("long_sort", s, launch_long_sort(b, kn, 256, s));
+    if (c.long_total) LAUNCH("long_sort", s, launch_long_sort(b, kn, 1024, s));
 
     own->refs = E;
     for (int e = 0; e < E; ++e) {
