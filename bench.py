@@ -207,6 +207,14 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
     stats = frnn.last_stats()
     dt_api, nnz_api = time_steps(step_api, steps, warmup)
     assert nnz_api == nnz
+    # per-launch HIP events (eager launches) for the kernel durations
+    frnn.profile_enable(True)
+    frnn.profile_read(reset=True)
+    for _ in range(5):
+        step_graph()
+    sync()
+    prof = frnn.profile_read(reset=True)
+    frnn.profile_enable(False)
     del x
     return {"workload": "paper-shaped-271663-d12: Zipf-sized Gaussian clusters in [-1,1]^12, "
                         "sigma 0.0305 (calibrated to the paper's mean non-self degree), r=0.12, "
@@ -215,6 +223,7 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
             "pairs_per_s": nnz * steps / dt, "events_per_s": steps / dt,
             "api_ms_per_step": dt_api / steps * 1e3,
             "candidates_per_pair": stats["candidates"] / max(nnz, 1),
+            "kernels_us": {k: round(v[1] / max(v[0], 1) * 1e3, 1) for k, v in prof.items()},
             "paper_context": {"exact_device_p50_ms": 267.829, "rerun_device_p50_ms": 207.299,
                               "gpu": "RTX 2070 SUPER", "pairs": 9279672,
                               "note": "different hardware and the real event; context, not a target"}}
@@ -380,6 +389,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
+    ap.add_argument("--paper-only", action="store_true",
+                    help="run only the paper-shaped self-join and print its JSON (a profiling aid)")
     ap.add_argument("--serve-events", type=int, default=600)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also write and then read this many MiB with plain kernels (to scale HBM counters)")
@@ -392,6 +403,9 @@ def main():
     import torch
     from paper_2609_31980_amd import frnn, inputs
 
+    if args.paper_only:
+        print(json.dumps({"paper_shaped": bench_paper_shaped(frnn, args.steps, args.warmup)}), flush=True)
+        return
     if args.calib_copy_mib:
         # a plain write kernel and a plain read kernel of known size, to
         # scale the HBM byte counters (FETCH_SIZE, WRITE_SIZE)

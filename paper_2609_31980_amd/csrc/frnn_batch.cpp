@@ -104,6 +104,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     offs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
     lofs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
     lrows.reset(sizeof(uint32_t) * sh.q_cap, s);
+    lat.reset(sizeof(int64_t) * 2 * sh.q_cap, s);
     stash.reset(sizeof(uint64_t) * sh.q_cap * std::max(1, sh.o.stash_cap), s);
     flist.reset(sizeof(uint32_t) * std::max<int64_t>(1, sh.qch_cap * (kChunkRows / sh.o.queries_per_item)), s);
     part.reset(sizeof(uint64_t) * 2 * kScanBlocks, s);
@@ -133,6 +134,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     b.offs = offs.as<int64_t>();
     b.lofs = lofs.as<int64_t>();
     b.long_rows = lrows.as<uint32_t>();
+    b.long_at = lat.as<int64_t>();
     b.stash = stash.as<uint64_t>();
     b.fill_list = flist.as<uint32_t>();
     b.scan_part = part.as<uint64_t>();
@@ -159,7 +161,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
 void BatchContext::retarget(hipStream_t s) {
     DevBuf *all[] = {&desc, &hv, &grid, &cell_off, &ext,
                      &xs, &perm, &key, &rank, &skey, &cells, &qs, &qperm, &qkey, &qrank, &sqkey,
-                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &stash, &flist, &part, &lk_};
+                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &lat, &stash, &flist, &part, &lk_};
     for (DevBuf *d : all) d->set_stream(s);
 }
 
@@ -263,7 +265,7 @@ void BatchContext::launch_a(hipStream_t s) {
 void BatchContext::launch_b(hipStream_t s) {
     LAUNCH("short_rows", s, launch_short_rows(bq_, kn_, sh_.qch_cap, s));
     LAUNCH("fill", s, launch_fill(bq_, kn_, sh_.D, fill_blocks(sh_.qch_cap * (kChunkRows / sh_.o.queries_per_item)), s));
-    LAUNCH("long_sort", s, launch_long_sort(bq_, kn_, 1024, s));
+    LAUNCH("long_sort", s, launch_long_sort(bq_, kn_, 1536, s));
 }
 
 static bool capture(hipStream_t s, hipGraph_t *g, hipGraphExec_t *ge, void (*fn)(void *, hipStream_t),

@@ -105,7 +105,7 @@ private:
     Bufs bb_{}, bq_{};  // build run and query run
     size_t o_ev_ = 0, o_pc_ = 0, o_qc_ = 0;
     DevBuf desc, hv, grid, cell_off, ext, xs, perm, key, rank,
-        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, stash, flist, part;
+        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, lat, stash, flist, part;
     Pinned stage_, back_;
     size_t stage_bytes_ = 0;
     int64_t seen_pairs_ = -1, seen_long_ = 0;  // the previous run's output

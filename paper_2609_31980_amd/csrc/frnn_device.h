@@ -146,7 +146,8 @@ struct Bufs {
     uint32_t *deg;         // in-radius count per query (global row)
     int64_t *offs;         // [total_q+1] exclusive scan of capped counts
     int64_t *lofs;         // [total_q+1] exclusive scan of the lengths of rows longer than the stash
-    uint32_t *long_rows;
+    uint32_t *long_rows;   // [total_q] length of each row listed for the row sort
+    int64_t *long_at;      // [2*total_q] its scratch offset and output offset
     uint64_t *stash;       // [total_q][stash_cap] first hit keys per query (global row)
     uint32_t *fill_list;   // windows holding rows longer than the stash
     uint64_t *scan_part;   // scan block partials (2 x kScanBlocks)

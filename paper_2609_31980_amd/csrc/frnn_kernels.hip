@@ -753,42 +753,51 @@ struct WaveLds {
     unsigned long long starts;  // run starts inside the current chunk (bit per lane); zero between uses
 };
 
-// Sorts the n <= 64*KS distinct keys h[0..n) of one row by rank: lane i
-// holds keys i, 64+i, ..., and each key's place is the number of smaller
-// keys, counted from LDS broadcasts 8 keys at a time (buf: 64*KS keys of
-// LDS, 16-byte aligned; slots past n hold all-ones keys, which are smaller
-// than no key); the first keep places are written.
+// Sorts the n <= 64*KS distinct keys h[0..n) of one row by rank: the keys
+// are staged in LDS (buf: 64*KS keys, 16-byte aligned; slots past n hold
+// all-ones keys, which are smaller than no key), then each lane takes keys
+// i, 64+i, ... in rounds of up to four and counts, for each, the smaller
+// keys of the row from LDS broadcasts 8 at a time; a key's count is its
+// place (the keys of a row are distinct).  The first keep places are written.
 template <int KS>
 __device__ __forceinline__ void rank_and_write(uint64_t *buf, const uint64_t *h, uint32_t n, uint32_t keep,
                                                int32_t *idx, float *d2, int lane) {
-    uint64_t mine[KS];
-    uint32_t rank[KS];
+    constexpr int R = KS < 4 ? KS : 4;  // keys per lane per round
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const uint32_t e = (uint32_t)(k * 64 + lane);
-        mine[k] = e < n ? h[e] : ~0ull;
-        buf[e] = mine[k];
-        rank[k] = 0;
+        buf[e] = e < n ? h[e] : ~0ull;
     }
     wave_lds_sync();
     const ulonglong2 *b2 = reinterpret_cast<const ulonglong2 *>(buf);
-    for (uint32_t i = 0; i < n; i += 8) {
-        ulonglong2 c[4];
+#pragma unroll 1
+    for (int k0 = 0; k0 < KS; k0 += R) {
+        uint64_t mine[R];
+        uint32_t rank[R];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = b2[i / 2 + u];
+        for (int k = 0; k < R; ++k) {
+            mine[k] = buf[(k0 + k) * 64 + lane];
+            rank[k] = 0;
+        }
+#pragma unroll 1
+        for (uint32_t i = 0; i < n; i += 8) {
+            ulonglong2 c[4];
 #pragma unroll
-        for (int k = 0; k < KS; ++k)
+            for (int u = 0; u < 4; ++u) c[u] = b2[i / 2 + u];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) rank[k] += (c[u].x < mine[k] ? 1u : 0u) + (c[u].y < mine[k] ? 1u : 0u);
-    }
-    wave_lds_sync();
+            for (int k = 0; k < R; ++k)
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-        if ((uint32_t)(k * 64 + lane) < n && rank[k] < keep) {
-            idx[rank[k]] = (int32_t)(uint32_t)mine[k];
-            if (d2) d2[rank[k]] = __uint_as_float((uint32_t)(mine[k] >> 32));
+                for (int u = 0; u < 4; ++u) rank[k] += (c[u].x < mine[k] ? 1u : 0u) + (c[u].y < mine[k] ? 1u : 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if ((uint32_t)((k0 + k) * 64 + lane) < n && rank[k] < keep) {
+                idx[rank[k]] = (int32_t)(uint32_t)mine[k];
+                if (d2) d2[rank[k]] = __uint_as_float((uint32_t)(mine[k] >> 32));
+            }
         }
     }
+    wave_lds_sync();
 }
 
 // Position of candidate v (0 <= v < L) among the group's concatenated runs.
@@ -879,6 +888,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         const int32_t wperm = inw ? qperm[p0 + lane] : 0;
         const uint32_t wdeg = (FILL && inw) ? b.deg[q_off + wperm] : 0u;
         const int64_t wrow = (FILL && inw) ? b.lofs[q_off + wperm] : 0;  // scratch row (fill pass)
+        const int64_t woffs = (FILL && inw) ? b.offs[q_off + wperm] : 0;  // output row (fill pass)
         uint64_t need = ballot(inw);
         if (FILL) {
             need = ballot(inw && wdeg > SC);  // rows the stash did not hold
@@ -1090,7 +1100,11 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                     uint32_t base = 0;
                     if (lane == 0) base = atomicAdd(&b.ctr->n_long, (uint32_t)__popcll(lm));
                     base = uniform((uint32_t)__shfl((int)base, 0));
-                    if (lst) b.long_rows[base + lanes_below(lm)] = (uint32_t)(q_off + wperm);
+                    if (lst) {
+                        const uint32_t li = base + lanes_below(lm);
+                        b.long_rows[li] = wdeg;
+                        *reinterpret_cast<longlong2 *>(b.long_at + 2 * (int64_t)li) = make_longlong2(wrow, woffs);
+                    }
                 } else {
                     if (mine) b.deg[q_off + wperm] = cntv;
                     more = more || ballot(mine && cntv > SC) != 0;
@@ -1310,11 +1324,11 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
     const int w = threadIdx.x >> 6;
     const uint32_t nw = gridDim.x * kWavesPerBlock;
     for (uint32_t li = blockIdx.x * kWavesPerBlock + w; li < n_long; li += nw) {
-        const uint32_t qid = b.long_rows[li];
-        const uint64_t n = b.deg[qid];
-        uint64_t *a = b.out->long_keys + b.lofs[qid];
+        const uint64_t n = b.long_rows[li];
+        const longlong2 at = *reinterpret_cast<const longlong2 *>(b.long_at + 2 * (int64_t)li);
+        uint64_t *a = b.out->long_keys + at.x;
         const uint64_t keep = (kn.K > 0 && n > (uint64_t)kn.K) ? (uint64_t)kn.K : n;
-        const int64_t off = b.offs[qid];
+        const int64_t off = at.y;
         int32_t *oi = b.out->indices + off;
         float *od = b.out->dist2 ? b.out->dist2 + off : nullptr;
         if (n <= (uint64_t)kn.long_cap) {
@@ -1334,7 +1348,7 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
         for (uint64_t k = 2; k <= P; k <<= 1) {
             const uint64_t half = k >> 1;
             for (uint64_t t = lane; t < P / 2; t += 64) {
-                const uint64_t lo = (t / half) * k + (t % half);
+                const uint64_t lo = ((t & ~(half - 1)) << 1) | (t & (half - 1));  // half: a power of two
                 const uint64_t hi = lo ^ (k - 1);
                 if (hi < n) {
                     uint64_t x = a[lo], y = a[hi];
@@ -1349,7 +1363,7 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             for (uint64_t j = k >> 2; j >= 1; j >>= 1) {
                 for (uint64_t t = lane; t < P / 2; t += 64) {
-                    const uint64_t lo = (t / j) * 2 * j + (t % j);
+                    const uint64_t lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // j: a power of two
                     const uint64_t hi = lo + j;
                     if (hi < n) {
                         uint64_t x = a[lo], y = a[hi];

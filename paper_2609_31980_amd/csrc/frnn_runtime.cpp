@@ -480,7 +480,8 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     DevBuf hv(sizeof(Counters) + sizeof(int64_t) * (E + 1), s);
     DevBuf deg(sizeof(uint32_t) * tq1, s),
         offs(sizeof(int64_t) * (tq1 + 1), s), lofs(sizeof(int64_t) * (tq1 + 1), s),
-        lrows(sizeof(uint32_t) * tq1, s), part(sizeof(uint64_t) * 2 * kScanBlocks, s),
+        lrows(sizeof(uint32_t) * tq1, s), lat(sizeof(int64_t) * 2 * tq1, s),
+        part(sizeof(uint64_t) * 2 * kScanBlocks, s),
         stash(sizeof(uint64_t) * tq1 * std::max(1, op.o.stash_cap), s),
         flist(sizeof(uint32_t) * std::max<int64_t>(1, (int64_t)nqc * (kChunkRows / op.o.queries_per_item)), s),
         outd(sizeof(OutDesc), s);
@@ -520,6 +521,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     b.offs = offs.as<int64_t>();
     b.lofs = lofs.as<int64_t>();
     b.long_rows = lrows.as<uint32_t>();
+    b.long_at = lat.as<int64_t>();
     b.stash = stash.as<uint64_t>();
     b.fill_list = flist.as<uint32_t>();
     b.scan_part = part.as<uint64_t>();
@@ -584,7 +586,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     LAUNCH("set_out", s, launch_set_out(b, od, s));
     LAUNCH("short_rows", s, launch_short_rows(b, kn, nqc, s));
     if (c.n_fill) LAUNCH("fill", s, launch_fill(b, kn, D, fill_blocks(c.n_fill), s));
-    if (c.long_total) LAUNCH("long_sort", s, launch_long_sort(b, kn, 1024, s));
+    if (c.long_total) LAUNCH("long_sort", s, launch_long_sort(b, kn, 1536, s));
 
     own->refs = E;
     for (int e = 0; e < E; ++e) {
