@@ -81,13 +81,13 @@ typedef struct {
     int32_t grid_axes_max;    /* most coordinates the cell grid may use (0..6) */
     float cells_per_point;    /* cap on grid cells per indexed point */
     int32_t cell_multiple;    /* m: cell width about r/m, reach +-m cells (1..3) */
-    int32_t cells_per_item;   /* grid cells along the first grid axis per work item (1..8) */
+    int32_t cells_per_item;   /* grid cells along the first grid axis per work item (1..8; default 2) */
     int32_t queries_per_item; /* queries evaluated per work item (1..64) */
     int32_t persistent;       /* 1: persistent kernel draining a device work queue */
     int32_t blocks_per_cu;    /* persistent grid size = 256 CUs x this (1..16) */
     int32_t row_cap_lds;      /* rows longer than this sort in global memory (1..512) */
-    int32_t stash_cap;        /* hits per query kept by the count pass (0, 8, 16, 32); the
-                                 fill pass only re-evaluates rows longer than this */
+    int32_t stash_cap;        /* hits per query kept by the count pass (0, 8, 16, 32; default 32);
+                                 the fill pass only re-evaluates rows longer than this */
 } frnn_opts;
 
 void frnn_opts_default(frnn_opts *opts);

@@ -73,12 +73,12 @@ void frnn_opts_default(frnn_opts *o) {
     o->grid_axes_max = 6;
     o->cells_per_point = 2.0f;
     o->cell_multiple = 1;
-    o->cells_per_item = 1;
+    o->cells_per_item = 2;
     o->queries_per_item = 32;
     o->persistent = 0;
     o->blocks_per_cu = 8;
     o->row_cap_lds = kRowLds;
-    o->stash_cap = 16;
+    o->stash_cap = 32;
 }
 
 const char *frnn_status_str(frnn_status s) {

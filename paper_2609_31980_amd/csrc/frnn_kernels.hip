@@ -1242,6 +1242,9 @@ __device__ __forceinline__ void place_row(uint64_t (&v)[N], uint32_t keep, bool 
 
 template <int SC>
 __global__ void __launch_bounds__(kChunkRows) k_short_rows(Bufs b, Knobs kn) {
+    // rows of up to LM keys: one lane per row; longer stash rows (up to SC):
+    // one wave per row, ranked
+    constexpr int LM = SC < 16 ? SC : 16;
     __shared__ uint32_t sidx[SC > 0 ? kShortStage : 1];
     __shared__ float sd2[SC > 0 ? kShortStage : 1];
     if (!out_fits(b)) return;
@@ -1260,42 +1263,69 @@ __global__ void __launch_bounds__(kChunkRows) k_short_rows(Bufs b, Knobs kn) {
         const bool staged = len <= kShortStage;
         int32_t *oi = b.out->indices + off;
         float *od = b.out->dist2 ? b.out->dist2 + off : nullptr;
-        // the first half of the stash row is read before the row length
-        // arrives (one memory round trip less; most rows are that short),
-        // the second half only for longer rows; entries past the length are
-        // masked afterwards
+        // the first LM/2 keys of the stash row are read before the row
+        // length arrives (one memory round trip less; most rows are that
+        // short), the next LM/2 only for longer rows; entries past the
+        // length are masked afterwards
         const uint64_t *st = b.stash + qid * SC;
-        uint64_t v[SC];
+        uint64_t v[LM];
 #pragma unroll
-        for (int i = 0; i < SC; i += 2) {
+        for (int i = 0; i < LM; i += 2) {
             ulonglong2 t = make_ulonglong2(~0ull, ~0ull);
-            if (row && i < SC / 2) t = *reinterpret_cast<const ulonglong2 *>(st + i);
+            if (row && i < LM / 2) t = *reinterpret_cast<const ulonglong2 *>(st + i);
             v[i] = t.x;
             v[i + 1] = t.y;
         }
         const uint32_t dq = row ? b.deg[qid] : 0u;
-        const bool mine = dq > 0 && dq <= (uint32_t)SC;
-        const bool full = ballot(mine && dq > (uint32_t)(SC / 2)) != 0;  // network size, per wave
+        const bool mine = dq > 0 && dq <= (uint32_t)LM;
+        const bool full = ballot(mine && dq > (uint32_t)(LM / 2)) != 0;  // network size, per wave
         if (mine) {
             const uint32_t keep = (kn.K > 0 && dq > (uint32_t)kn.K) ? (uint32_t)kn.K : dq;
-            if (dq > (uint32_t)(SC / 2)) {
+            if (dq > (uint32_t)(LM / 2)) {
 #pragma unroll
-                for (int i = SC / 2; i < SC; i += 2) {
+                for (int i = LM / 2; i < LM; i += 2) {
                     const ulonglong2 t = *reinterpret_cast<const ulonglong2 *>(st + i);
                     v[i] = t.x;
                     v[i + 1] = t.y;
                 }
             }
 #pragma unroll
-            for (int i = 0; i < SC; ++i)
+            for (int i = 0; i < LM; ++i)
                 if ((uint32_t)i >= dq) v[i] = ~0ull;
             if (full) {
-                place_row<SC>(v, keep, staged, off - base, sidx, sd2, oi, od);
+                place_row<LM>(v, keep, staged, off - base, sidx, sd2, oi, od);
             } else {
-                uint64_t h[SC / 2];
+                uint64_t h[LM / 2];
 #pragma unroll
-                for (int i = 0; i < SC / 2; ++i) h[i] = v[i];
-                place_row<SC / 2>(h, keep, staged, off - base, sidx, sd2, oi, od);
+                for (int i = 0; i < LM / 2; ++i) h[i] = v[i];
+                place_row<LM / 2>(h, keep, staged, off - base, sidx, sd2, oi, od);
+            }
+        }
+        if constexpr (SC > LM) {
+            // stash rows of LM+1..SC keys, one at a time by the whole wave:
+            // lane i holds key i and counts the smaller keys of the row
+            // (keys of a row are distinct, so the counts are the places)
+            const int lane = lane_id(), wv = threadIdx.x >> 6;
+            for (uint64_t mid = ballot(row && dq > (uint32_t)LM && dq <= (uint32_t)SC); mid; mid &= mid - 1) {
+                const int t = __ffsll((unsigned long long)mid) - 1;
+                const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)dq, t);
+                const int64_t qt = ch.r0 + wv * 64 + t;
+                const int64_t ot = readlane64(off, t);
+                const uint32_t keep = (kn.K > 0 && n > (uint32_t)kn.K) ? (uint32_t)kn.K : n;
+                const uint64_t key = (uint32_t)lane < n ? b.stash[qt * SC + lane] : ~0ull;
+                uint32_t rank = 0;
+                for (uint32_t i = 0; i < n; ++i) rank += (uint64_t)readlane64((int64_t)key, (int)i) < key ? 1u : 0u;
+                if ((uint32_t)lane < n && rank < keep) {
+                    const uint32_t j = (uint32_t)key;
+                    const float d = __uint_as_float((uint32_t)(key >> 32));
+                    if (staged) {
+                        sidx[ot - base + rank] = j;
+                        sd2[ot - base + rank] = d;
+                    } else {
+                        b.out->indices[ot + rank] = (int32_t)j;
+                        if (b.out->dist2) b.out->dist2[ot + rank] = d;
+                    }
+                }
             }
         }
         if (staged) {
