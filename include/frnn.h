@@ -286,7 +286,7 @@ typedef struct {
     int64_t candidates;   /* (query, reference) pairs whose distance was evaluated */
     int64_t work_items;
     int64_t pairs;        /* output pairs (after the cap) */
-    int64_t long_row_keys; /* keys of rows sorted by the global-memory path */
+    int64_t long_row_keys; /* keys of the rows longer than the stash (scratch rows of the fill pass) */
 } frnn_stats;
 
 frnn_status frnn_last_stats(frnn_stats *out);
