@@ -1306,24 +1306,43 @@ __global__ void __launch_bounds__(kChunkRows) k_short_rows(Bufs b, Knobs kn) {
             // lane i holds key i and counts the smaller keys of the row
             // (keys of a row are distinct, so the counts are the places)
             const int lane = lane_id(), wv = threadIdx.x >> 6;
-            for (uint64_t mid = ballot(row && dq > (uint32_t)LM && dq <= (uint32_t)SC); mid; mid &= mid - 1) {
-                const int t = __ffsll((unsigned long long)mid) - 1;
-                const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)dq, t);
-                const int64_t qt = ch.r0 + wv * 64 + t;
-                const int64_t ot = readlane64(off, t);
-                const uint32_t keep = (kn.K > 0 && n > (uint32_t)kn.K) ? (uint32_t)kn.K : n;
-                const uint64_t key = (uint32_t)lane < n ? b.stash[qt * SC + lane] : ~0ull;
-                uint32_t rank = 0;
-                for (uint32_t i = 0; i < n; ++i) rank += (uint64_t)readlane64((int64_t)key, (int)i) < key ? 1u : 0u;
-                if ((uint32_t)lane < n && rank < keep) {
-                    const uint32_t j = (uint32_t)key;
-                    const float d = __uint_as_float((uint32_t)(key >> 32));
-                    if (staged) {
-                        sidx[ot - base + rank] = j;
-                        sd2[ot - base + rank] = d;
-                    } else {
-                        b.out->indices[ot + rank] = (int32_t)j;
-                        if (b.out->dist2) b.out->dist2[ot + rank] = d;
+            // four rows at a time, their key loads issued together
+            constexpr int RB = 4;
+            uint64_t mid = ballot(row && dq > (uint32_t)LM && dq <= (uint32_t)SC);
+            while (mid) {
+                int tr[RB];
+                uint64_t key[RB];
+#pragma unroll
+                for (int k = 0; k < RB; ++k) {
+                    tr[k] = -1;
+                    key[k] = ~0ull;
+                    if (mid) {
+                        tr[k] = __ffsll((unsigned long long)mid) - 1;
+                        mid &= mid - 1;
+                        const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)dq, tr[k]);
+                        if ((uint32_t)lane < n) key[k] = b.stash[(ch.r0 + wv * 64 + tr[k]) * SC + lane];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < RB; ++k) {
+                    if (tr[k] < 0) break;
+                    const int t = tr[k];
+                    const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)dq, t);
+                    const int64_t ot = readlane64(off, t);
+                    const uint32_t keep = (kn.K > 0 && n > (uint32_t)kn.K) ? (uint32_t)kn.K : n;
+                    uint32_t rank = 0;
+                    for (uint32_t i = 0; i < n; ++i)
+                        rank += (uint64_t)readlane64((int64_t)key[k], (int)i) < key[k] ? 1u : 0u;
+                    if ((uint32_t)lane < n && rank < keep) {
+                        const uint32_t j = (uint32_t)key[k];
+                        const float d = __uint_as_float((uint32_t)(key[k] >> 32));
+                        if (staged) {
+                            sidx[ot - base + rank] = j;
+                            sd2[ot - base + rank] = d;
+                        } else {
+                            b.out->indices[ot + rank] = (int32_t)j;
+                            if (b.out->dist2) b.out->dist2[ot + rank] = d;
+                        }
                     }
                 }
             }
