@@ -6,7 +6,9 @@
 //   counting   k_query<count> over windows of sorted queries, scan of the
 //              capped counts (and the events' first output pairs)
 //   filling    k_set_out, k_short_rows (per-event offsets, rows the stash
-//              holds), k_query<fill> (windows with longer rows), k_long_sort
+//              holds), k_query<fill> (hit keys of longer rows into scratch
+//              rows, for the windows the count pass listed), k_long_sort
+//              (those rows sorted, one wave per row)
 //
 // Exactness: the squared distance is computed in float32 as
 //   s = +0; for d in 0..D-1: t = q_d - x_d; u = t*t; s = s + u
@@ -1212,7 +1214,9 @@ __device__ __forceinline__ void sort_regs(uint64_t (&v)[N]) {
 
 // Every row's per-event offset, and the rows the count pass kept whole
 // (0 < length <= SC): one lane per query row, in output order, sorts the
-// row's keys in registers.  The query chunks partition each event's rows, so
+// row's keys in registers (rows of up to 16 keys); rows of 17..SC keys (the
+// 32-key stash) are ranked by the whole wave.  The query chunks partition
+// each event's rows, so
 // chunk c covers global rows r0..r1-1 of one event and its output is the
 // contiguous range offs[r0]..offs[r1]; one block per chunk.  When that range
 // fits in LDS the rows are assembled there and written out coalesced; the
