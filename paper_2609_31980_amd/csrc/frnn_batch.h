@@ -55,9 +55,9 @@ public:
                            const Opts &o);
     bool fits(const Shape &need) const;
 
-    // 1. descriptors of this batch (host -> device, on stream s); prepare
-    //    stages them in pinned memory, upload copies them (and, when given,
-    //    the output descriptor) in one transfer
+    // 1. descriptors of this batch; prepare writes them to the context's
+    //    pinned, device-mapped stage, upload adds the output descriptor when
+    //    given; the first kernel of phase A copies the stage to the device
     void set_inputs(const frnn_event *ev, int E, hipStream_t s);
     void prepare(const frnn_event *ev, int E);
     void upload(hipStream_t s, const OutDesc *od);
@@ -106,8 +106,10 @@ private:
     size_t o_ev_ = 0, o_pc_ = 0, o_qc_ = 0;
     DevBuf desc, hv, grid, cell_off, ext, xs, perm, key, rank,
         skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, lat, stash, flist, part;
-    Pinned stage_, back_;
-    size_t stage_bytes_ = 0;
+    Pinned back_;
+    char *hstage_ = nullptr;      // descriptors, host side (coherent, device-mapped)
+    const void *hstage_dev_ = nullptr;
+    size_t stage_cap_ = 0;        // bytes, the capacity of the descriptor block
     int64_t seen_pairs_ = -1, seen_long_ = 0;  // the previous run's output
     hipEvent_t counted_ = nullptr;  // recorded after the read-back
     hipEvent_t done_ = nullptr;

@@ -84,11 +84,30 @@ __device__ __forceinline__ bool finite32(float f) {
 }
 
 // ------------------------------------------------------------------ init
-__global__ void k_init(Bufs b, Counters *ctr2) {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid < (int64_t)(sizeof(Counters) / 4)) {
-        reinterpret_cast<uint32_t *>(b.ctr)[tid] = 0u;
-        if (ctr2) reinterpret_cast<uint32_t *>(ctr2)[tid] = 0u;
+// Clears the counters (block 0) and, when src is given, copies n16 16-byte
+// words of descriptors from device-mapped host memory to dst, every block
+// taking a contiguous part with kFetchUnroll loads in flight per thread.
+constexpr int kFetchUnroll = 1;
+
+__global__ void __launch_bounds__(256) k_init(Bufs b, Counters *ctr2, const uint4 *src, uint4 *dst, int64_t n16) {
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(Counters) / 4) {
+        reinterpret_cast<uint32_t *>(b.ctr)[threadIdx.x] = 0u;
+        if (ctr2) reinterpret_cast<uint32_t *>(ctr2)[threadIdx.x] = 0u;
+    }
+    if (!src) return;
+    const int64_t per = (int64_t)blockDim.x * kFetchUnroll;
+    for (int64_t base = (int64_t)blockIdx.x * per; base < n16; base += (int64_t)gridDim.x * per) {
+        uint4 v[kFetchUnroll];
+#pragma unroll
+        for (int u = 0; u < kFetchUnroll; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
+            if (i < n16) v[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kFetchUnroll; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
+            if (i < n16) dst[i] = v[u];
+        }
     }
 }
 
@@ -1448,9 +1467,13 @@ __global__ void k_set_out(Bufs b, OutDesc v) { *b.out = v; }
         if (e_ != hipSuccess) return e_;   \
     } while (0)
 
-hipError_t launch_init(const Bufs &b, hipStream_t s, Counters *also) {
+hipError_t launch_init(const Bufs &b, hipStream_t s, Counters *also, const void *src, void *dst, int64_t bytes) {
     static_assert(sizeof(Counters) / 4 <= 256, "one block clears the counters");
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, b, also);
+    const int64_t n16 = src ? (bytes + 15) / 16 : 0;
+    const int64_t per = 256 * kFetchUnroll;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, (n16 + per - 1) / per));
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, b, also, reinterpret_cast<const uint4 *>(src),
+                       reinterpret_cast<uint4 *>(dst), n16);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -9,8 +9,11 @@
 
 namespace frnn {
 
-// zeroes b.ctr (and `also`, when given)
-hipError_t launch_init(const Bufs &b, hipStream_t s, Counters *also = nullptr);
+// zeroes b.ctr (and `also`, when given); with src, also copies `bytes` of
+// descriptors from device-mapped host memory src to device memory dst (both
+// 16-byte aligned, bytes rounded up to 16)
+hipError_t launch_init(const Bufs &b, hipStream_t s, Counters *also = nullptr, const void *src = nullptr,
+                       void *dst = nullptr, int64_t bytes = 0);
 // one block per chunk (per-chunk extent slots for the points); also clears
 // zero_n cells of the (point or query) cell histogram
 hipError_t launch_extent(const Bufs &b, int nchunks, int E_cap, bool queries, int64_t zero_n, hipStream_t s);
