@@ -83,13 +83,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     desc.reset(stage_cap_, s);
     // the host writes each batch's descriptors here and the first kernel of
     // phase A reads them (coherent: no stale copy in a GPU cache)
-    if (hipHostMalloc((void **)&hstage_, stage_cap_, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
-        hstage_ = nullptr;
-        (void)hipGetLastError();
-        throw Fail{FRNN_ERR_OOM, "hipHostMalloc failed"};
-    }
-    std::memset(hstage_, 0, stage_cap_);
-    FRNN_HIP(hipHostGetDevicePointer((void **)&hstage_dev_, hstage_, 0));
+    stage_.reset(stage_cap_);
     // read-back block: query counters | build counters | event bases
     hv.reset(2 * sizeof(Counters) + sizeof(int64_t) * (Ec + 1), s);
     grid.reset(sizeof(GridDesc) * Ec, s);
@@ -187,7 +181,6 @@ BatchContext::~BatchContext() {
     for (hipGraph_t g : {gra_, grb_})
         if (g) (void)hipGraphDestroy(g);
     if (counted_) (void)hipEventDestroy(counted_);
-    if (hstage_) (void)hipHostFree(hstage_);
     if (done_) (void)hipEventDestroy(done_);
 }
 
@@ -240,7 +233,7 @@ void BatchContext::prepare(const frnn_event *ev, int E) {
     bd.total_q = tq;
     // the previous batch's phase A has read the stage: its counts were read
     // back before this context was handed out again
-    char *h = hstage_;
+    char *h = stage_.host();
     std::memset(h, 0, o_ev_);
     std::memcpy(h, &bd, sizeof(bd));
     std::memcpy(h + o_ev_, evh.data(), sizeof(EventDev) * E);
@@ -249,14 +242,14 @@ void BatchContext::prepare(const frnn_event *ev, int E) {
 }
 
 void BatchContext::upload(hipStream_t, const OutDesc *od) {
-    if (od) std::memcpy(hstage_ + kOutOff, od, sizeof(OutDesc));
+    if (od) std::memcpy(stage_.host() + kOutOff, od, sizeof(OutDesc));
 }
 
 void BatchContext::launch_a(hipStream_t s) {
     const bool selfq = sh_.flags & FRNN_SELF_QUERY;
     const int D = sh_.D;
     // build and query counters in one launch
-    LAUNCH("init", s, launch_init(bb_, s, bq_.ctr, hstage_dev_, desc.get(), (int64_t)stage_cap_));
+    LAUNCH("init", s, launch_init(bb_, s, bq_.ctr, stage_.dev(), desc.get(), (int64_t)stage_cap_));
     LAUNCH("extent", s, launch_extent(bb_, sh_.pch_cap, sh_.E_cap, false, sh_.cells_cap + 1, s));
     LAUNCH("plan", s, launch_plan(bb_, sh_.E_cap, s));
     LAUNCH("keys", s, launch_keys(bb_, sh_.pch_cap, false, s));

@@ -107,8 +107,7 @@ private:
     DevBuf desc, hv, grid, cell_off, ext, xs, perm, key, rank,
         skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, lat, stash, flist, part;
     Pinned back_;
-    char *hstage_ = nullptr;      // descriptors, host side (coherent, device-mapped)
-    const void *hstage_dev_ = nullptr;
+    MappedHost stage_;            // descriptors, host side, read by the first kernel
     size_t stage_cap_ = 0;        // bytes, the capacity of the descriptor block
     int64_t seen_pairs_ = -1, seen_long_ = 0;  // the previous run's output
     hipEvent_t counted_ = nullptr;  // recorded after the read-back

@@ -169,6 +169,28 @@ void Pool::trim() {
     }
 }
 
+MappedHost::~MappedHost() {
+    if (h_) (void)hipHostFree(h_);
+}
+
+void MappedHost::reset(size_t bytes) {
+    if (h_) (void)hipHostFree(h_);
+    h_ = nullptr;
+    d_ = nullptr;
+    if (hipHostMalloc((void **)&h_, bytes ? bytes : 16, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        h_ = nullptr;
+        (void)hipGetLastError();
+        throw Fail{FRNN_ERR_OOM, "hipHostMalloc failed"};
+    }
+    std::memset(h_, 0, bytes ? bytes : 16);
+    if (hipHostGetDevicePointer(&d_, h_, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h_);
+        h_ = nullptr;
+        throw Fail{FRNN_ERR_HIP, "hipHostGetDevicePointer failed"};
+    }
+}
+
 Pinned::~Pinned() {
     if (p_) (void)hipHostFree(p_);
 }

@@ -125,6 +125,23 @@ private:
     size_t bytes_ = 0;
 };
 
+// Pinned host memory mapped into the device's address space, coherent (the
+// device reads and writes it without caching), of a fixed size.
+class MappedHost {
+public:
+    MappedHost() = default;
+    ~MappedHost();
+    MappedHost(const MappedHost &) = delete;
+    MappedHost &operator=(const MappedHost &) = delete;
+    void reset(size_t bytes);  // zero-filled; throws on failure
+    char *host() const { return h_; }
+    void *dev() const { return d_; }
+
+private:
+    char *h_ = nullptr;
+    void *d_ = nullptr;
+};
+
 // ---------------------------------------------------------- instrumentation
 void prof_begin(const char *name, hipStream_t s, bool capturing);
 void prof_end(hipStream_t s, bool capturing);
