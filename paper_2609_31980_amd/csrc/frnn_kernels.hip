@@ -1102,10 +1102,16 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                     }
                 };
                 for (uint32_t v0 = 0; v0 < total; v0 += 64) {
+                    // rows of more than 8 floats: no next-chunk prefetch (one
+                    // candidate row live instead of two keeps the D = 12 count
+                    // kernel at 5 waves per SIMD without spills)
+                    if constexpr (DT > 8)
+                        if (v0 > 0) fetch(v0);
                     const uint32_t pos = pn, j = jn;
                     const CandRow<DT> x = xn;
                     const float thr = v0 + lane < total ? r2 : -1.0f;
-                    if (v0 + 64 < total) fetch(v0 + 64);
+                    if constexpr (DT <= 8)
+                        if (v0 + 64 < total) fetch(v0 + 64);
                     if (kn.exclude_self)
                         eval_chunk(std::true_type{}, pos, j, x, thr);
                     else
@@ -1189,8 +1195,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
 }
 
 // Two entry points with the same body: the second asks the compiler for 5
-// resident waves per SIMD (at most 96 registers), which the measurements
-// favour for the 8-dimensional kernel even with a few spilled registers.
+// resident waves per SIMD (at most 96 registers), used for the count pass
+// at D = 8 and D = 12 where it fits without spilling.
 // PERS selects the persistent scheduling at compile time, so each kernel
 // holds one copy of the window body.
 template <int DT, bool EXACT_D, bool FILL, bool PERS>
@@ -1542,7 +1548,7 @@ static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int bloc
         switch (D) {
         case 3: hipLaunchKernelGGL((k_query<3, true, false, P>), grid, block, 0, s, b, kn); break;
         case 8: hipLaunchKernelGGL((k_query_o5<8, true, false, P>), grid, block, 0, s, b, kn); break;
-        case 12: hipLaunchKernelGGL((k_query<12, true, false, P>), grid, block, 0, s, b, kn); break;
+        case 12: hipLaunchKernelGGL((k_query_o5<12, true, false, P>), grid, block, 0, s, b, kn); break;
         default:
             if (D <= 4)
                 hipLaunchKernelGGL((k_query<4, false, false, P>), grid, block, 0, s, b, kn);
