@@ -1102,15 +1102,16 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                     }
                 };
                 for (uint32_t v0 = 0; v0 < total; v0 += 64) {
-                    // rows of more than 8 floats: no next-chunk prefetch (one
-                    // candidate row live instead of two keeps the D = 12 count
-                    // kernel at 5 waves per SIMD without spills)
-                    if constexpr (DT > 8)
+                    // rows of 8 floats or more: no next-chunk prefetch (one
+                    // candidate row live instead of two gives the count
+                    // kernel 6 resident waves per SIMD at D = 8 and 5 at
+                    // D = 12, without spills, which hides more latency)
+                    if constexpr (DT >= 8)
                         if (v0 > 0) fetch(v0);
                     const uint32_t pos = pn, j = jn;
                     const CandRow<DT> x = xn;
                     const float thr = v0 + lane < total ? r2 : -1.0f;
-                    if constexpr (DT <= 8)
+                    if constexpr (DT < 8)
                         if (v0 + 64 < total) fetch(v0 + 64);
                     if (kn.exclude_self)
                         eval_chunk(std::true_type{}, pos, j, x, thr);
@@ -1194,9 +1195,9 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     }
 }
 
-// Two entry points with the same body: the second asks the compiler for 5
-// resident waves per SIMD (at most 96 registers), used for the count pass
-// at D = 8 and D = 12 where it fits without spilling.
+// Two entry points with the same body: the second asks the compiler for at
+// least 5 resident waves per SIMD (at most 96 registers), used for the
+// count pass at D = 8 (6 waves) and D = 12 where it fits without spilling.
 // PERS selects the persistent scheduling at compile time, so each kernel
 // holds one copy of the window body.
 template <int DT, bool EXACT_D, bool FILL, bool PERS>
