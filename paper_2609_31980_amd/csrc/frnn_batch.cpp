@@ -176,9 +176,9 @@ uint64_t *BatchContext::long_scratch(int64_t n, hipStream_t s) {
 }
 
 BatchContext::~BatchContext() {
-    for (hipGraphExec_t ge : {ga_, gb_})
+    for (hipGraphExec_t ge : {ga_, gbs_, gbl_})
         if (ge) (void)hipGraphExecDestroy(ge);
-    for (hipGraph_t g : {gra_, grb_})
+    for (hipGraph_t g : {gra_, grbs_, grbl_})
         if (g) (void)hipGraphDestroy(g);
     if (counted_) (void)hipEventDestroy(counted_);
     if (done_) (void)hipEventDestroy(done_);
@@ -265,8 +265,11 @@ void BatchContext::launch_a(hipStream_t s) {
     LAUNCH("scan_rows", s, launch_scan_rows(bq_, kn_, sh_.q_cap, s));
 }
 
-void BatchContext::launch_b(hipStream_t s) {
+void BatchContext::launch_b_short(hipStream_t s) {
     LAUNCH("short_rows", s, launch_short_rows(bq_, kn_, sh_.qch_cap, s));
+}
+
+void BatchContext::launch_b_long(hipStream_t s) {
     LAUNCH("fill", s, launch_fill(bq_, kn_, sh_.D, fill_blocks(sh_.qch_cap * (kChunkRows / sh_.o.queries_per_item)), s));
     LAUNCH("long_sort", s, launch_long_sort(bq_, kn_, 1536, s));
 }
@@ -344,14 +347,20 @@ BatchCounts BatchContext::wait_counts() {
     return c;
 }
 
-void BatchContext::phase_b(const OutDesc &od, hipStream_t s) {
+void BatchContext::phase_b(const OutDesc &od, bool long_rows, hipStream_t s) {
     LAUNCH("set_out", s, launch_set_out(bq_, od, s));
-    phase_b(s);
+    phase_b_short(s);
+    if (long_rows) phase_b_long(s);
 }
 
-void BatchContext::phase_b(hipStream_t s) {
-    if (!replay(&gb_, &grb_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_b(st); }, s))
-        launch_b(s);
+void BatchContext::phase_b_short(hipStream_t s) {
+    if (!replay(&gbs_, &grbs_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_b_short(st); }, s))
+        launch_b_short(s);
+}
+
+void BatchContext::phase_b_long(hipStream_t s) {
+    if (!replay(&gbl_, &grbl_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_b_long(st); }, s))
+        launch_b_long(s);
 }
 
 bool BatchContext::guess(int64_t *pairs, int64_t *long_keys) const {
@@ -479,7 +488,17 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
         bo.own = nullptr;
         ctx->phase_a(s);
         ctx->fetch_counts(s);
-        if (spec) ctx->phase_b(s);  // runs while the host reads the counts
+        // the fill runs while the host reads the counts; its long-row part
+        // only when the previous run had long rows (else after the counts,
+        // if needed: the two parts write different rows)
+        bool long_queued = false;
+        if (spec) {
+            ctx->phase_b_short(s);
+            if (ctx->expect_long()) {
+                ctx->phase_b_long(s);
+                long_queued = true;
+            }
+        }
         BatchCounts c = ctx->wait_counts();
         if (c.build_status & kStatusNonfinitePts) {
             st = fail(FRNN_ERR_NONFINITE, "non-finite coordinate in the points");
@@ -489,13 +508,16 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
             st = fail(FRNN_ERR_INTERNAL, "pair count mismatch");
         } else {
             ctx->learn(c);
+            const bool long_rows = c.ctr.long_total > 0;
             if (!spec || (int64_t)c.ctr.nnz > cap_pairs || (int64_t)c.ctr.long_total > cap_long) {
                 // exact size; a speculative fill (if any) wrote nothing
                 own.reset();
                 bo = alloc_output(*ctx, c, want_d2, s);
                 own.reset(bo.own);
                 bo.own = nullptr;
-                ctx->phase_b(bo.od, s);
+                ctx->phase_b(bo.od, long_rows, s);
+            } else if (long_rows && !long_queued) {
+                ctx->phase_b_long(s);
             }
             bo.own = own.release();
             hand_out(*ctx, c, bo, outs);

@@ -7,7 +7,8 @@
 // replayed for any batch of its class:
 //   graph A: bin the points of every event, count every query's neighbours,
 //            scan the capped counts        (then one 8-byte-per-event read-back)
-//   graph B: fill, sort long rows, per-event offsets
+//   graph B: short rows and per-event offsets; then, only when some row is
+//            longer than the stash, the fill pass and the long-row sort
 // Run exactly, A and B are separated by the read-back that sizes the output.
 // Once a context has run, its next batch is run speculatively instead: the
 // output is allocated at a capacity guessed from the previous run, and B is
@@ -68,10 +69,14 @@ public:
     BatchCounts read_counts(hipStream_t s);
     void fetch_counts(hipStream_t s);
     BatchCounts wait_counts();
-    // 4. fill into the given output (graph B); without an argument, into
-    //    the output descriptor given to upload
-    void phase_b(const OutDesc &od, hipStream_t s);
-    void phase_b(hipStream_t s);
+    // 4. fill into the given output (graph B: the short rows, then, when
+    //    some row is longer than the stash, the long rows); the parts alone
+    //    fill into the output descriptor given to upload
+    void phase_b(const OutDesc &od, bool long_rows, hipStream_t s);
+    void phase_b_short(hipStream_t s);
+    void phase_b_long(hipStream_t s);
+    // whether the previous run had rows longer than the stash
+    bool expect_long() const { return seen_long_ > 0; }
 
     // Output capacities for a speculative run (false before the first run).
     bool guess(int64_t *pairs, int64_t *long_keys) const;
@@ -94,7 +99,8 @@ public:
 
 private:
     void launch_a(hipStream_t s);
-    void launch_b(hipStream_t s);
+    void launch_b_short(hipStream_t s);
+    void launch_b_long(hipStream_t s);
     bool replay(hipGraphExec_t *ge, hipGraph_t *g, void (*fn)(void *, hipStream_t), hipStream_t s);
     Shape sh_;
     int Dp_ = 0;
@@ -113,8 +119,8 @@ private:
     hipEvent_t counted_ = nullptr;  // recorded after the read-back
     hipEvent_t done_ = nullptr;
     DevBuf lk_;
-    hipGraphExec_t ga_ = nullptr, gb_ = nullptr;
-    hipGraph_t gra_ = nullptr, grb_ = nullptr;
+    hipGraphExec_t ga_ = nullptr, gbs_ = nullptr, gbl_ = nullptr;
+    hipGraph_t gra_ = nullptr, grbs_ = nullptr, grbl_ = nullptr;
 };
 
 // Check a context of a fitting class out of the shared cache (or make one);

@@ -153,7 +153,7 @@ void frnn_server_s::worker(int id) {
                 std::shared_ptr<BudgetLedger> bud = budget;
                 bo.own->on_release = [bud, outb]() { bud->release(outb); };
                 try {
-                    ctx->phase_b(bo.od, s);
+                    ctx->phase_b(bo.od, c.ctr.long_total > 0, s);
                 } catch (...) {
                     delete bo.own;  // returns the reservation
                     throw;

@@ -208,3 +208,37 @@ def test_batch_speculative_output_overflow(orc, frnn):
             if eager:
                 frnn.profile_enable(False)
                 frnn.profile_read()
+
+
+def test_batch_long_rows_after_short_run(orc, frnn):
+    """A context whose previous run had no row longer than the stash does not
+    queue the long-row passes with the short rows; when the next batch of its
+    class fits the learned capacity but has long rows, they are filled after
+    the counts are read.  Graph replay and eager launches."""
+    n, r = 6000, 0.0625
+    short = inputs.tracks(n, 8, track_size=20, sigma=0.002, noise_frac=0.0, seed=95)
+    rng = np.random.default_rng(96)
+    # two clusters of 40: 80 rows of 40 keys, 3,200 long-row keys (within the
+    # 4,096-key floor of a context that has seen no long rows)
+    mixed = np.concatenate([inputs.tracks(80, 8, track_size=40, sigma=0.002, noise_frac=0.0, seed=97),
+                            inputs.uniform_cube(n - 80, 8, seed=98)])
+    mixed = np.ascontiguousarray(mixed[rng.permutation(n)])
+    want = {"short": pinlib.as_tuple(orc.frnn(short, r, 0)), "mixed": pinlib.as_tuple(orc.frnn(mixed, r, 0))}
+    dm = np.diff(want["mixed"][0])
+    assert np.diff(want["short"][0]).max() <= 32 < dm.max()
+    assert dm[dm > 32].sum() <= 4096
+    assert len(want["mixed"][1]) < len(want["short"][1])  # fits the capacity learned from "short"
+    for eager in (False, True):
+        if eager:
+            frnn.profile_enable(True)
+        try:
+            for name in ("short", "mixed", "short", "mixed", "mixed"):
+                x = short if name == "short" else mixed
+                say(f"long rows after short run: {name} eager={eager}")
+                o = frnn.query_batch([dev(x)], r, 0)[0]
+                pinlib.assert_csr_equal(_np(o), want[name], f"{name} eager={eager}")
+                o.release()
+        finally:
+            if eager:
+                frnn.profile_enable(False)
+                frnn.profile_read()
