@@ -774,48 +774,110 @@ struct WaveLds {
     unsigned long long starts;  // run starts inside the current chunk (bit per lane); zero between uses
 };
 
-// Sorts the n <= 64*KS distinct keys h[0..n) of one row by rank: the keys
-// are staged in LDS (buf: 64*KS keys, 16-byte aligned; slots past n hold
-// all-ones keys, which are smaller than no key), then each lane takes keys
-// i, 64+i, ... in rounds of up to four and counts, for each, the smaller
-// keys of the row from LDS broadcasts 8 at a time; a key's count is its
-// place (the keys of a row are distinct).  The first keep places are written.
+// Sorts the n <= 64*KS distinct keys h[0..n) of one row by rank and writes
+// the first keep places.  The keys are staged in LDS (buf: 64*KS keys,
+// 16-byte aligned; slots past n hold all-ones keys, which are smaller than
+// no key of the row) as KS blocks of 64; lane i takes keys i, 64+i, ...
+// A key's place is the number of smaller keys of the row (the keys of a row
+// are distinct).  With one block it is counted from LDS broadcasts, 8 keys a
+// step.  With two or four, each key is first ranked within its own block the
+// same way, the blocks are rewritten in sorted order, and the smaller keys of
+// each other block are counted by a binary search in it.  With eight (rare
+// rows; fewer live registers) each key is counted against the whole row, in
+// rounds of four keys per lane.
 template <int KS>
 __device__ __forceinline__ void rank_and_write(uint64_t *buf, const uint64_t *h, uint32_t n, uint32_t keep,
                                                int32_t *idx, float *d2, int lane) {
-    constexpr int R = KS < 4 ? KS : 4;  // keys per lane per round
+    if constexpr (KS > 4) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const uint32_t e = (uint32_t)(k * 64 + lane);
+            buf[e] = e < n ? h[e] : ~0ull;
+        }
+        wave_lds_sync();
+        const ulonglong2 *w2 = reinterpret_cast<const ulonglong2 *>(buf);
+#pragma unroll 1
+        for (int k0 = 0; k0 < KS; k0 += 4) {
+            uint64_t mine[4];
+            uint32_t rk[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                mine[k] = buf[(k0 + k) * 64 + lane];
+                rk[k] = 0;
+            }
+#pragma unroll 1
+            for (uint32_t i = 0; i < n; i += 8) {
+                ulonglong2 c[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) c[u] = w2[i / 2 + u];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) rk[k] += (c[u].x < mine[k] ? 1u : 0u) + (c[u].y < mine[k] ? 1u : 0u);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((uint32_t)((k0 + k) * 64 + lane) < n && rk[k] < keep) {
+                    idx[rk[k]] = (int32_t)(uint32_t)mine[k];
+                    if (d2) d2[rk[k]] = __uint_as_float((uint32_t)(mine[k] >> 32));
+                }
+            }
+        }
+        wave_lds_sync();
+        return;
+    }
+    uint64_t key[KS];
+    uint32_t rank[KS];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const uint32_t e = (uint32_t)(k * 64 + lane);
-        buf[e] = e < n ? h[e] : ~0ull;
+        key[k] = e < n ? h[e] : ~0ull;
+        buf[e] = key[k];
+        rank[k] = 0;
     }
     wave_lds_sync();
     const ulonglong2 *b2 = reinterpret_cast<const ulonglong2 *>(buf);
-#pragma unroll 1
-    for (int k0 = 0; k0 < KS; k0 += R) {
-        uint64_t mine[R];
-        uint32_t rank[R];
+    // rank within the key's own block (the whole row when KS == 1)
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            mine[k] = buf[(k0 + k) * 64 + lane];
-            rank[k] = 0;
-        }
+    for (int k = 0; k < KS; ++k) {
+        const uint32_t len = KS == 1 ? n : 64u;
 #pragma unroll 1
-        for (uint32_t i = 0; i < n; i += 8) {
+        for (uint32_t i = 0; i < len; i += 8) {
             ulonglong2 c[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) c[u] = b2[i / 2 + u];
+            for (int u = 0; u < 4; ++u) c[u] = b2[(k * 64 + i) / 2 + u];
 #pragma unroll
-            for (int k = 0; k < R; ++k)
-#pragma unroll
-                for (int u = 0; u < 4; ++u) rank[k] += (c[u].x < mine[k] ? 1u : 0u) + (c[u].y < mine[k] ? 1u : 0u);
+            for (int u = 0; u < 4; ++u) rank[k] += (c[u].x < key[k] ? 1u : 0u) + (c[u].y < key[k] ? 1u : 0u);
         }
+    }
+    if constexpr (KS > 1) {
+        // each block in sorted order (the all-ones padding keys share one
+        // place; slots after it are never read)
+        wave_lds_sync();
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            if ((uint32_t)((k0 + k) * 64 + lane) < n && rank[k] < keep) {
-                idx[rank[k]] = (int32_t)(uint32_t)mine[k];
-                if (d2) d2[rank[k]] = __uint_as_float((uint32_t)(mine[k] >> 32));
+        for (int k = 0; k < KS; ++k) buf[k * 64 + rank[k]] = key[k];
+        wave_lds_sync();
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+#pragma unroll
+            for (int c = 0; c < KS; ++c) {
+                if (c == k) continue;
+                const int64_t rest = (int64_t)n - c * 64;
+                const uint32_t len = rest <= 0 ? 0u : (rest >= 64 ? 64u : (uint32_t)rest);
+                const uint64_t *blk = buf + c * 64;
+                uint32_t pos = 0;  // keys of block c smaller than key[k]
+#pragma unroll
+                for (uint32_t step = 64; step >= 1; step >>= 1)
+                    if (pos + step <= len && blk[pos + step - 1] < key[k]) pos += step;
+                rank[k] += pos;
             }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        if ((uint32_t)(k * 64 + lane) < n && rank[k] < keep) {
+            idx[rank[k]] = (int32_t)(uint32_t)key[k];
+            if (d2) d2[rank[k]] = __uint_as_float((uint32_t)(key[k] >> 32));
         }
     }
     wave_lds_sync();
