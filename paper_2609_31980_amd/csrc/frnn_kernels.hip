@@ -920,7 +920,7 @@ __device__ __forceinline__ bool out_fits(const Bufs &b) {
 // evaluated) and evaluates every query of the group against each chunk of 64
 // candidates, one per lane.  The fill pass takes only the windows the count
 // pass listed, and sorts each long row of a group as soon as the group is done.
-template <int DT, bool EXACT_D, bool FILL, bool PERS>
+template <int DT, bool EXACT_D, bool FILL, bool PERS, bool EXCL>
 __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     constexpr int DP = (DT + 3) & ~3;
     __shared__ WaveLds slds[kWavesPerBlock];
@@ -1175,10 +1175,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                     const float thr = v0 + lane < total ? r2 : -1.0f;
                     if constexpr (DT < 8)
                         if (v0 + 64 < total) fetch(v0 + 64);
-                    if (kn.exclude_self)
-                        eval_chunk(std::true_type{}, pos, j, x, thr);
-                    else
-                        eval_chunk(std::false_type{}, pos, j, x, thr);
+                    eval_chunk(std::integral_constant<bool, EXCL>{}, pos, j, x, thr);
                 }
                 const bool mine = lane >= gb && lane < ge;
                 if constexpr (FILL) {
@@ -1262,19 +1259,19 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
 // count pass at D = 8 (6 waves) and D = 12 where it fits without spilling.
 // PERS selects the persistent scheduling at compile time, so each kernel
 // holds one copy of the window body.
-template <int DT, bool EXACT_D, bool FILL, bool PERS>
+template <int DT, bool EXACT_D, bool FILL, bool PERS, bool EXCL>
 __global__ void __launch_bounds__(256) k_query(Bufs b, Knobs kn) {
     if constexpr (FILL)
         if (!out_fits(b)) return;
-    query_body<DT, EXACT_D, FILL, PERS>(b, kn);
+    query_body<DT, EXACT_D, FILL, PERS, EXCL>(b, kn);
 }
 
 
-template <int DT, bool EXACT_D, bool FILL, bool PERS>
+template <int DT, bool EXACT_D, bool FILL, bool PERS, bool EXCL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_query_o5(Bufs b, Knobs kn) {
     if constexpr (FILL)
         if (!out_fits(b)) return;
-    query_body<DT, EXACT_D, FILL, PERS>(b, kn);
+    query_body<DT, EXACT_D, FILL, PERS, EXCL>(b, kn);
 }
 
 // ------------------------------------------------------------ short rows
@@ -1606,41 +1603,54 @@ template <bool FILL>
 static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
     blocks = (blocks + 7) / 8 * 8;  // whole XCD rounds (see the window remap)
     dim3 grid(blocks), block(64 * kWavesPerBlock);
-    auto go = [&](auto pers) {
-        constexpr bool P = decltype(pers)::value;
-        switch (D) {
-        case 3: hipLaunchKernelGGL((k_query<3, true, false, P>), grid, block, 0, s, b, kn); break;
-        case 8: hipLaunchKernelGGL((k_query_o5<8, true, false, P>), grid, block, 0, s, b, kn); break;
-        case 12: hipLaunchKernelGGL((k_query_o5<12, true, false, P>), grid, block, 0, s, b, kn); break;
-        default:
-            if (D <= 4)
-                hipLaunchKernelGGL((k_query<4, false, false, P>), grid, block, 0, s, b, kn);
-            else if (D <= 16)
-                hipLaunchKernelGGL((k_query<16, false, false, P>), grid, block, 0, s, b, kn);
-            else
-                hipLaunchKernelGGL((k_query<32, false, false, P>), grid, block, 0, s, b, kn);
+    // self-exclusion and persistent scheduling are compile-time choices, so
+    // each kernel holds one copy of the evaluation loop
+    auto go = [&](auto pers, auto excl) {
+        constexpr bool P = decltype(pers)::value, X = decltype(excl)::value;
+        if constexpr (FILL) {
+            switch (D) {
+            case 3: hipLaunchKernelGGL((k_query<3, true, true, false, X>), grid, block, 0, s, b, kn); break;
+            case 8: hipLaunchKernelGGL((k_query<8, true, true, false, X>), grid, block, 0, s, b, kn); break;
+            case 12:  // 5 waves per SIMD fit without spilling only without self-exclusion
+                if constexpr (X)
+                    hipLaunchKernelGGL((k_query<12, true, true, false, X>), grid, block, 0, s, b, kn);
+                else
+                    hipLaunchKernelGGL((k_query_o5<12, true, true, false, X>), grid, block, 0, s, b, kn);
+                break;
+            default:
+                if (D <= 4)
+                    hipLaunchKernelGGL((k_query<4, false, true, false, X>), grid, block, 0, s, b, kn);
+                else if (D <= 16)
+                    hipLaunchKernelGGL((k_query<16, false, true, false, X>), grid, block, 0, s, b, kn);
+                else
+                    hipLaunchKernelGGL((k_query<32, false, true, false, X>), grid, block, 0, s, b, kn);
+            }
+        } else {
+            switch (D) {
+            case 3: hipLaunchKernelGGL((k_query<3, true, false, P, X>), grid, block, 0, s, b, kn); break;
+            case 8: hipLaunchKernelGGL((k_query_o5<8, true, false, P, X>), grid, block, 0, s, b, kn); break;
+            case 12: hipLaunchKernelGGL((k_query_o5<12, true, false, P, X>), grid, block, 0, s, b, kn); break;
+            default:
+                if (D <= 4)
+                    hipLaunchKernelGGL((k_query<4, false, false, P, X>), grid, block, 0, s, b, kn);
+                else if (D <= 16)
+                    hipLaunchKernelGGL((k_query<16, false, false, P, X>), grid, block, 0, s, b, kn);
+                else
+                    hipLaunchKernelGGL((k_query<32, false, false, P, X>), grid, block, 0, s, b, kn);
+            }
         }
     };
-    // the fill pass always strides over its window list
-    if constexpr (FILL) {
-        switch (D) {
-        case 3: hipLaunchKernelGGL((k_query<3, true, true, false>), grid, block, 0, s, b, kn); break;
-        case 8: hipLaunchKernelGGL((k_query<8, true, true, false>), grid, block, 0, s, b, kn); break;
-        case 12: hipLaunchKernelGGL((k_query<12, true, true, false>), grid, block, 0, s, b, kn); break;
-        default:
-            if (D <= 4)
-                hipLaunchKernelGGL((k_query<4, false, true, false>), grid, block, 0, s, b, kn);
-            else if (D <= 16)
-                hipLaunchKernelGGL((k_query<16, false, true, false>), grid, block, 0, s, b, kn);
-            else
-                hipLaunchKernelGGL((k_query<32, false, true, false>), grid, block, 0, s, b, kn);
-        }
-    } else {
-        if (kn.persistent)
-            go(std::true_type{});
+    auto go_x = [&](auto pers) {
+        if (kn.exclude_self)
+            go(pers, std::true_type{});
         else
-            go(std::false_type{});
-    }
+            go(pers, std::false_type{});
+    };
+    // the fill pass always strides over its window list
+    if (!FILL && kn.persistent)
+        go_x(std::true_type{});
+    else
+        go_x(std::false_type{});
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
