@@ -772,6 +772,7 @@ struct WaveLds {
     uint32_t run_base[kRunsMax];
     uint32_t run_pref[kRunsMax + 1];
     unsigned long long starts;  // run starts inside the current chunk (bit per lane); zero between uses
+    int32_t cw[kGMax - 1][64];  // grid coordinates 1.. of each window query's cell
 };
 
 // Sorts the n <= 64*KS distinct keys h[0..n) of one row by rank and writes
@@ -983,18 +984,25 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
             for (int i = lane; i < nwq * (Dp / 4); i += 64) dst[i] = src[i];
         }
         // grid coordinates of each lane's query cell, decoded once per window
-        int cw[kGMax] = {0, 0, 0, 0, 0, 0};
+        // (coordinate 0 stays in a register; the others go to LDS and are read
+        // back per group, which keeps them out of the registers of the loop)
+        int cw0 = 0;
         {
             uint32_t rem = wkey;
 #pragma unroll
             for (int a = 0; a < kGMax; ++a) {
+                int ca = 0;
                 if (a < G) {
-                    cw[a] = (int)(rem % (uint32_t)g.n[a]);
+                    ca = (int)(rem % (uint32_t)g.n[a]);
                     rem /= (uint32_t)g.n[a];
                 }
+                if (a == 0)
+                    cw0 = ca;
+                else
+                    L.cw[a - 1][lane] = ca;
             }
         }
-        const uint32_t c0 = (uint32_t)cw[0];
+        const uint32_t c0 = (uint32_t)cw0;
         const uint32_t bkey = wkey - c0 + (c0 / R) * R;  // key of the cell block's first cell
         const uint32_t prev = (uint32_t)__shfl_up((int)bkey, 1);
         const uint64_t starts = ballot(inw && (lane == 0 || bkey != prev));
@@ -1022,7 +1030,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
             const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)wkey, gb);
             int cc[kGMax];
 #pragma unroll
-            for (int a = 0; a < kGMax; ++a) cc[a] = __builtin_amdgcn_readlane(cw[a], gb);
+            for (int a = 0; a < kGMax; ++a)
+                cc[a] = a == 0 ? __builtin_amdgcn_readlane(cw0, gb) : (int)uniform((uint32_t)L.cw[a - 1][gb]);
             int lo0 = 0, hi0 = 0;
             uint32_t kbase = key;
             if (G > 0) {
