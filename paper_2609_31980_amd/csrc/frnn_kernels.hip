@@ -1020,9 +1020,10 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         // neighbour runs of the group whose first query is window lane gb:
         // lane s < runs probes run s (start, length)
         // one run-table entry per lane, loaded once per window (tables with
-        // more than 64 runs are read per group instead)
+        // more than 64 runs, and rows of more than 8 floats, where the four
+        // registers buy a resident wave, are read per group instead)
         RunEntry wre{};
-        if (lane < runs) wre = rtab[lane];
+        if (DT <= 8 && lane < runs) wre = rtab[lane];
         auto probe = [&](int gb, int s, uint32_t &start, uint32_t &len) {
             start = 0;
             len = 0;
@@ -1041,7 +1042,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 lo0 = max(b0 - m, 0);
                 hi0 = min(b1 + m, n0 - 1);
             }
-            const RunEntry re = runs <= 64 ? wre : rtab[s];
+            const RunEntry re = (DT <= 8 && runs <= 64) ? wre : rtab[s];
             bool ok = true;
 #pragma unroll
             for (int a = 1; a < kGMax; ++a) {
