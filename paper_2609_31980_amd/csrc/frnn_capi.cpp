@@ -78,7 +78,7 @@ void frnn_opts_default(frnn_opts *o) {
     o->persistent = 0;
     o->blocks_per_cu = 8;
     o->row_cap_lds = kRowLds;
-    o->stash_cap = 32;
+    o->stash_cap = 64;
 }
 
 const char *frnn_status_str(frnn_status s) {

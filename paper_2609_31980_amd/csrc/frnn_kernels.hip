@@ -240,6 +240,10 @@ __global__ void __launch_bounds__(256) k_extent(Bufs b, int32_t queries, int64_t
 }
 
 // ------------------------------------------------------------------ plan
+// Slot words per thread that the plan loads together (one batch covers 8,192
+// words, the slots of about 524,000 points at D = 8).
+constexpr int kPlanBatch = 32;
+
 // Lane src's value (src wave-uniform), read through scalar registers.
 __device__ __forceinline__ double lane_f64(double v, int src) {
     const uint64_t u = (uint64_t)__double_as_longlong(v);
@@ -294,17 +298,17 @@ __global__ void __launch_bounds__(256) k_plan(Bufs b) {
         const bool is_min = (t % W) < D;
         uint32_t acc = is_min ? 0xffffffffu : 0u;
         if (t < T) {
-            int64_t i = t;
-            for (; i + 7 * T < nw; i += 8 * T) {
-                uint32_t v[8];
+            // batches of kPlanBatch words per thread, all loads of a batch in
+            // flight at once (the slots were written by other XCDs, so each
+            // round trip goes past this XCD's L2); a position past the end
+            // reads word i again, of the same column, which min / max ignore
+            for (int64_t i = t; i < nw; i += kPlanBatch * T) {
+                uint32_t v[kPlanBatch];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = slot[i + u * T];
+                for (int u = 0; u < kPlanBatch; ++u) v[u] = slot[i + u * T < nw ? i + u * T : i];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc = is_min ? (v[u] < acc ? v[u] : acc) : (v[u] > acc ? v[u] : acc);
-            }
-            for (; i < nw; i += T) {
-                const uint32_t v = slot[i];
-                acc = is_min ? (v < acc ? v : acc) : (v > acc ? v : acc);
+                for (int u = 0; u < kPlanBatch; ++u)
+                    acc = is_min ? (v[u] < acc ? v[u] : acc) : (v[u] > acc ? v[u] : acc);
             }
         }
         rmin[t] = acc;
@@ -372,22 +376,33 @@ __device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane, uint32
     if (cap > ((int64_t)1 << 30)) cap = (int64_t)1 << 30;
     if (cap > ev.cell_cap) cap = ev.cell_cap;
     const int gmax = min(bd.grid_axes_max, min(D, kGMax));
+    // (every per-axis loop below runs over all kGMax axes with a guard, so
+    // the arrays are indexed by constants and stay in registers)
     double cext[kGMax];
-    for (int a = 0; a < gmax; ++a) {
-        const uint64_t hit = ballot(lane < D && rank == a);
-        const int ax = __ffsll((unsigned long long)hit) - 1;
-        g.axis[a] = ax;
-        cext[a] = lane_f64(x, ax);
-        g.lo[a] = lane_f64(lo, ax);
+#pragma unroll
+    for (int a = 0; a < kGMax; ++a) {
+        cext[a] = 0.0;
+        if (a < gmax) {
+            const uint64_t hit = ballot(lane < D && rank == a);
+            const int ax = __ffsll((unsigned long long)hit) - 1;
+            g.axis[a] = ax;
+            cext[a] = lane_f64(x, ax);
+            g.lo[a] = lane_f64(lo, ax);
+        }
     }
     int G = 0;
     const int W = 2 * m + 1;
     for (int gg = gmax; gg >= 1; --gg) {
         int64_t runs = 1;
-        for (int a = 1; a < gg; ++a) runs *= W;
-        if (runs > kRunsMax) continue;
         double C = 1.0;
-        for (int a = 0; a < gg; ++a) C *= floor(cext[a] * inv_h) + 1.0;
+#pragma unroll
+        for (int a = 0; a < kGMax; ++a) {
+            if (a < gg) {
+                if (a >= 1) runs *= W;
+                C *= floor(cext[a] * inv_h) + 1.0;
+            }
+        }
+        if (runs > kRunsMax) continue;
         if (C <= (double)cap) {
             G = gg;
             break;
@@ -407,13 +422,16 @@ __device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane, uint32
     g.h = inv_h > 0.0 ? 1.0 / inv_h : 0.0;
     uint32_t C = 1;
     int runs = 1;
-    for (int a = 0; a < G; ++a) {
-        double na = floor(cext[a] * inv_h) + 1.0;
-        if (na > (double)cap) na = (double)cap;
-        g.n[a] = (int32_t)na;
-        g.stride[a] = C;
-        C *= (uint32_t)g.n[a];
-        if (a >= 1) runs *= W;
+#pragma unroll
+    for (int a = 0; a < kGMax; ++a) {
+        if (a < G) {
+            double na = floor(cext[a] * inv_h) + 1.0;
+            if (na > (double)cap) na = (double)cap;
+            g.n[a] = (int32_t)na;
+            g.stride[a] = C;
+            C *= (uint32_t)g.n[a];
+            if (a >= 1) runs *= W;
+        }
     }
     g.C = C;
     g.runs = runs;
@@ -423,14 +441,19 @@ __device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane, uint32
     for (int s = lane; s < runs; s += 64) {
         RunEntry re;
         re.koff = 0;
+#pragma unroll
         for (int a = 0; a < kGMax; ++a) re.o[a] = 0;
+#pragma unroll
         for (int a = 0; a < 6; ++a) re.pad[a] = 0;
         int t = s;
-        for (int a = 1; a < G; ++a) {
-            const int o = t % W - m;
-            t /= W;
-            re.o[a] = (int8_t)o;
-            re.koff += o * (int32_t)g.stride[a];
+#pragma unroll
+        for (int a = 1; a < kGMax; ++a) {
+            if (a < G) {
+                const int o = t % W - m;
+                t /= W;
+                re.o[a] = (int8_t)o;
+                re.koff += o * (int32_t)g.stride[a];
+            }
         }
         b.runs[(int64_t)e * kRunsMax + s] = re;
     }
@@ -1310,7 +1333,7 @@ __device__ __forceinline__ void sort_regs(uint64_t (&v)[N]) {
 // Every row's per-event offset, and the rows the count pass kept whole
 // (0 < length <= SC): one lane per query row, in output order, sorts the
 // row's keys in registers (rows of up to 16 keys); rows of 17..SC keys (the
-// 32-key stash) are ranked by the whole wave.  The query chunks partition
+// 32- and 64-key stashes; one key per lane) are ranked by the whole wave.  The query chunks partition
 // each event's rows, so
 // chunk c covers global rows r0..r1-1 of one event and its output is the
 // contiguous range offs[r0]..offs[r1]; one block per chunk.  When that range
@@ -1681,6 +1704,7 @@ hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipSt
     case 8: hipLaunchKernelGGL(k_short_rows<8>, grid, block, 0, s, b, kn); break;
     case 16: hipLaunchKernelGGL(k_short_rows<16>, grid, block, 0, s, b, kn); break;
     case 32: hipLaunchKernelGGL(k_short_rows<32>, grid, block, 0, s, b, kn); break;
+    case 64: hipLaunchKernelGGL(k_short_rows<64>, grid, block, 0, s, b, kn); break;
     default: return hipErrorInvalidValue;
     }
     FRNN_CHECK_LAUNCH();

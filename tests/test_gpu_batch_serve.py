@@ -214,8 +214,10 @@ def test_batch_long_rows_after_short_run(orc, frnn):
     """A context whose previous run had no row longer than the stash does not
     queue the long-row passes with the short rows; when the next batch of its
     class fits the learned capacity but has long rows, they are filled after
-    the counts are read.  Graph replay and eager launches."""
+    the counts are read.  Graph replay and eager launches, with a 32-key
+    stash."""
     n, r = 6000, 0.0625
+    o32 = frnn.default_opts(stash_cap=32)
     short = inputs.tracks(n, 8, track_size=20, sigma=0.002, noise_frac=0.0, seed=95)
     rng = np.random.default_rng(96)
     # two clusters of 40: 80 rows of 40 keys, 3,200 long-row keys (within the
@@ -235,7 +237,7 @@ def test_batch_long_rows_after_short_run(orc, frnn):
             for name in ("short", "mixed", "short", "mixed", "mixed"):
                 x = short if name == "short" else mixed
                 say(f"long rows after short run: {name} eager={eager}")
-                o = frnn.query_batch([dev(x)], r, 0)[0]
+                o = frnn.query_batch([dev(x)], r, 0, opts=o32)[0]
                 pinlib.assert_csr_equal(_np(o), want[name], f"{name} eager={eager}")
                 o.release()
         finally:
