@@ -1340,7 +1340,9 @@ __device__ __forceinline__ void sort_regs(uint64_t (&v)[N]) {
 // fits in LDS the rows are assembled there and written out coalesced; the
 // places of longer rows receive filler that the fill pass, which runs later
 // on the same stream, overwrites.
-constexpr int kShortStage = kChunkRows * 16;  // staged output pairs per block
+// Staged output pairs per block: with the mid-row list and the four rank
+// buffers the block stays within 32 KB of LDS (five blocks per CU).
+constexpr int kShortStage = kChunkRows * 29 / 2;
 
 template <int N>
 __device__ __forceinline__ void place_row(uint64_t (&v)[N], uint32_t keep, bool staged, int64_t rel,
@@ -1363,12 +1365,15 @@ __device__ __forceinline__ void place_row(uint64_t (&v)[N], uint32_t keep, bool 
 }
 
 template <int SC>
-__global__ void __launch_bounds__(kChunkRows) k_short_rows(Bufs b, Knobs kn) {
+__global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu(5))) k_short_rows(Bufs b, Knobs kn) {
     // rows of up to LM keys: one lane per row; longer stash rows (up to SC):
     // one wave per row, ranked
     constexpr int LM = SC < 16 ? SC : 16;
     __shared__ uint32_t sidx[SC > 0 ? kShortStage : 1];
     __shared__ float sd2[SC > 0 ? kShortStage : 1];
+    __shared__ uint16_t s_mid[SC > LM ? kChunkRows : 1];                     // rows of LM+1..SC keys
+    __shared__ __align__(16) uint64_t s_rank[SC > LM ? kChunkRows / 64 : 1][64];  // one row per wave
+    __shared__ uint32_t s_nmid;
     if (!out_fits(b)) return;
     if (blockIdx.x == 0)  // each event's leading offset, the one entry no row writes
         for (int e = threadIdx.x; e < b.bd->E; e += blockDim.x) b.out->offsets[b.ev[e].q_off + e] = 0;
@@ -1424,46 +1429,72 @@ __global__ void __launch_bounds__(kChunkRows) k_short_rows(Bufs b, Knobs kn) {
             }
         }
         if constexpr (SC > LM) {
-            // stash rows of LM+1..SC keys, one at a time by the whole wave:
-            // lane i holds key i and counts the smaller keys of the row
-            // (keys of a row are distinct, so the counts are the places)
+            // stash rows of LM+1..SC keys: the block lists them in LDS and its
+            // waves take them in turn (a block of dense rows keeps all four
+            // busy); a wave ranks one row at a time, lane i holding key i and
+            // counting the smaller keys of the row from LDS broadcasts, eight
+            // a step (keys of a row are distinct, so the counts are places)
             const int lane = lane_id(), wv = threadIdx.x >> 6;
-            // four rows at a time, their key loads issued together
+            if (threadIdx.x == 0) s_nmid = 0;
+            __syncthreads();
+            const bool midr = row && dq > (uint32_t)LM && dq <= (uint32_t)SC;
+            const uint64_t mm = ballot(midr);
+            if (mm) {
+                uint32_t at = 0;
+                if (lane == 0) at = atomicAdd(&s_nmid, (uint32_t)__popcll(mm));
+                at = uniform((uint32_t)__shfl((int)at, 0));
+                if (midr) s_mid[at + lanes_below(mm)] = (uint16_t)threadIdx.x;
+            }
+            __syncthreads();
+            const uint32_t nmid = s_nmid;
+            uint64_t *rb = &s_rank[wv][0];
+            const ulonglong2 *rb2 = reinterpret_cast<const ulonglong2 *>(rb);
+            // four rows per round, their lengths, offsets and keys loaded
+            // together (a lane past SC reads nothing: the stash row ends there)
             constexpr int RB = 4;
-            uint64_t mid = ballot(row && dq > (uint32_t)LM && dq <= (uint32_t)SC);
-            while (mid) {
-                int tr[RB];
+            constexpr uint32_t NW = kChunkRows / 64;
+            for (uint32_t m0 = wv; m0 < nmid; m0 += RB * NW) {
+                uint32_t n[RB];
+                int64_t ot[RB];
                 uint64_t key[RB];
 #pragma unroll
                 for (int k = 0; k < RB; ++k) {
-                    tr[k] = -1;
+                    const uint32_t m = m0 + k * NW;
+                    n[k] = 0;
+                    ot[k] = 0;
                     key[k] = ~0ull;
-                    if (mid) {
-                        tr[k] = __ffsll((unsigned long long)mid) - 1;
-                        mid &= mid - 1;
-                        const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)dq, tr[k]);
-                        if ((uint32_t)lane < n) key[k] = b.stash[(ch.r0 + wv * 64 + tr[k]) * SC + lane];
+                    if (m < nmid) {
+                        const int64_t qr = ch.r0 + (int64_t)uniform((uint32_t)s_mid[m]);
+                        n[k] = b.deg[qr];
+                        ot[k] = b.offs[qr];
+                        if (lane < SC) key[k] = b.stash[qr * SC + lane];
                     }
                 }
 #pragma unroll
                 for (int k = 0; k < RB; ++k) {
-                    if (tr[k] < 0) break;
-                    const int t = tr[k];
-                    const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)dq, t);
-                    const int64_t ot = readlane64(off, t);
-                    const uint32_t keep = (kn.K > 0 && n > (uint32_t)kn.K) ? (uint32_t)kn.K : n;
+                    if (n[k] == 0) break;
+                    const uint64_t kk = (uint32_t)lane < n[k] ? key[k] : ~0ull;
+                    rb[lane] = kk;
+                    wave_lds_sync();
                     uint32_t rank = 0;
-                    for (uint32_t i = 0; i < n; ++i)
-                        rank += (uint64_t)readlane64((int64_t)key[k], (int)i) < key[k] ? 1u : 0u;
-                    if ((uint32_t)lane < n && rank < keep) {
-                        const uint32_t j = (uint32_t)key[k];
-                        const float d = __uint_as_float((uint32_t)(key[k] >> 32));
+                    for (uint32_t i = 0; i < n[k]; i += 8) {
+                        ulonglong2 c[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) c[u] = rb2[i / 2 + u];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) rank += (c[u].x < kk ? 1u : 0u) + (c[u].y < kk ? 1u : 0u);
+                    }
+                    wave_lds_sync();
+                    const uint32_t keep = (kn.K > 0 && n[k] > (uint32_t)kn.K) ? (uint32_t)kn.K : n[k];
+                    if ((uint32_t)lane < n[k] && rank < keep) {
+                        const uint32_t j = (uint32_t)kk;
+                        const float d = __uint_as_float((uint32_t)(kk >> 32));
                         if (staged) {
-                            sidx[ot - base + rank] = j;
-                            sd2[ot - base + rank] = d;
+                            sidx[ot[k] - base + rank] = j;
+                            sd2[ot[k] - base + rank] = d;
                         } else {
-                            b.out->indices[ot + rank] = (int32_t)j;
-                            if (b.out->dist2) b.out->dist2[ot + rank] = d;
+                            b.out->indices[ot[k] + rank] = (int32_t)j;
+                            if (b.out->dist2) b.out->dist2[ot[k] + rank] = d;
                         }
                     }
                 }
