@@ -944,6 +944,13 @@ __device__ __forceinline__ bool out_fits(const Bufs &b) {
 // evaluated) and evaluates every query of the group against each chunk of 64
 // candidates, one per lane.  The fill pass takes only the windows the count
 // pass listed, and sorts each long row of a group as soon as the group is done.
+// rows of fewer floats than this load the next candidate chunk while the
+// current one is evaluated
+constexpr int kPrefetchBelow = 8;
+// rows of at least this many floats run the window bookkeeping and the
+// per-query loop on scalar registers
+constexpr int kScalarWaveFrom = 12;
+
 template <int DT, bool EXACT_D, bool FILL, bool PERS, bool EXCL>
 __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     constexpr int DP = (DT + 3) & ~3;
@@ -952,7 +959,9 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     __shared__ unsigned long long s_cand[kWavesPerBlock];
     __shared__ uint32_t s_groups[kWavesPerBlock];
     const int lane = lane_id();
-    const int w = threadIdx.x >> 6;
+    // the wave's index; read through a scalar register, everything derived
+    // from it (window, chunk, group bounds, the query loop) is scalar
+    const int w = DT >= kScalarWaveFrom ? (int)uniform(threadIdx.x >> 6) : (int)(threadIdx.x >> 6);
     WaveLds &L = slds[w];
     if (lane_id() == 0) L.starts = 0;
     wave_lds_sync();
@@ -1201,12 +1210,12 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                     // candidate row live instead of two gives the count
                     // kernel 6 resident waves per SIMD at D = 8 and 5 at
                     // D = 12, without spills, which hides more latency)
-                    if constexpr (DT >= 8)
+                    if constexpr (DT >= kPrefetchBelow)
                         if (v0 > 0) fetch(v0);
                     const uint32_t pos = pn, j = jn;
                     const CandRow<DT> x = xn;
                     const float thr = v0 + lane < total ? r2 : -1.0f;
-                    if constexpr (DT < 8)
+                    if constexpr (DT < kPrefetchBelow)
                         if (v0 + 64 < total) fetch(v0 + 64);
                     eval_chunk(std::integral_constant<bool, EXCL>{}, pos, j, x, thr);
                 }
