@@ -1005,6 +1005,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         const uint32_t wdeg = (FILL && inw) ? b.deg[q_off + wperm] : 0u;
         const int64_t wrow = (FILL && inw) ? b.lofs[q_off + wperm] : 0;  // scratch row (fill pass)
         const int64_t woffs = (FILL && inw) ? b.offs[q_off + wperm] : 0;  // output row (fill pass)
+        const int64_t wst = (!FILL && inw) ? (q_off + wperm) * (int64_t)SC : 0;  // stash row (count pass)
         uint64_t need = ballot(inw);
         if (FILL) {
             need = ballot(inw && wdeg > SC);  // rows the stash did not hold
@@ -1165,7 +1166,10 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 // one query of the group against one chunk; self-exclusion is
                 // decided once per launch (two copies of the loop)
                 auto eval_chunk = [&](auto excl, uint32_t pos, uint32_t j, const CandRow<DT> &x, float thr) {
-                    for (int t = gb; t < ge; ++t) {
+                    // the group's query range through scalar registers: the
+                    // loop index is then scalar
+                    const int tb = (int)uniform((uint32_t)gb), te = (int)uniform((uint32_t)ge);
+                    for (int t = tb; t < te; ++t) {
                         if constexpr (FILL)
                             if ((uint32_t)__builtin_amdgcn_readlane((int)wdeg, t) <= SC) continue;
                         QueryRow<DT> qr;
@@ -1197,8 +1201,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                                 // the first SC hit keys of each query go to its stash row
                                 const uint32_t slot = c + lanes_below(hm);
                                 if (hit && slot < SC) {
-                                    const int64_t qid = q_off + __builtin_amdgcn_readlane(wperm, t);
-                                    b.stash[qid * SC + slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                                    b.stash[readlane64(wst, t) + slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
                                 }
                             }
                             cntv = lane == t ? c + (uint32_t)__popcll(hm) : cntv;
