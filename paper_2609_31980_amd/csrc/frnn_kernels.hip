@@ -951,11 +951,14 @@ constexpr int kPrefetchBelow = 8;
 // per-query loop on scalar registers
 constexpr int kScalarWaveFrom = 12;
 
+// The query rows of each wave's window (window x DP floats per wave), in the
+// launch's dynamic LDS, so that the block's LDS follows the window size.
+extern __shared__ float4 q_rows_lds[];
+
 template <int DT, bool EXACT_D, bool FILL, bool PERS, bool EXCL>
 __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     constexpr int DP = (DT + 3) & ~3;
     __shared__ WaveLds slds[kWavesPerBlock];
-    __shared__ float4 sq[kWavesPerBlock][64 * DP / 4];  // the window's query rows
     __shared__ unsigned long long s_cand[kWavesPerBlock];
     __shared__ uint32_t s_groups[kWavesPerBlock];
     const int lane = lane_id();
@@ -976,6 +979,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     const int32_t *qperm = kn.self_query ? b.perm : b.qperm;
     uint64_t *long_keys = FILL ? b.out->long_keys : nullptr;
     const int Wn = kn.window;
+    float4 *const sq = q_rows_lds + (int64_t)w * Wn * (DP / 4);  // this wave's rows
     const uint32_t wpc = kChunkRows / Wn;
     const uint32_t nwin = (uint32_t)bd.n_qchunks * wpc;
     uint64_t my_cand = 0;
@@ -1013,7 +1017,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         }
         {
             const float4 *src = reinterpret_cast<const float4 *>(qs + p0 * Dp);
-            float4 *dst = &sq[w][0];
+            float4 *dst = sq;
             for (int i = lane; i < nwq * (Dp / 4); i += 64) dst[i] = src[i];
         }
         // grid coordinates of each lane's query cell, decoded once per window
@@ -1176,7 +1180,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
 #pragma unroll
                         for (int d4 = 0; d4 < DP; d4 += 4) {
                             if (EXACT_D || d4 < Dp) {
-                                const float4 v = sq[w][t * (Dp / 4) + d4 / 4];
+                                const float4 v = sq[t * (Dp / 4) + d4 / 4];
                                 qr.q[d4] = v.x;
                                 if (d4 + 1 < DT) qr.q[d4 + 1] = v.y;
                                 if (d4 + 2 < DT) qr.q[d4 + 2] = v.z;
@@ -1681,38 +1685,41 @@ static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int bloc
     dim3 grid(blocks), block(64 * kWavesPerBlock);
     // self-exclusion and persistent scheduling are compile-time choices, so
     // each kernel holds one copy of the evaluation loop
+    // dynamic LDS: the query rows of a window per wave (rows padded to a
+    // multiple of 4 floats)
+    auto lds = [&](int dt) { return (size_t)kWavesPerBlock * kn.window * ((dt + 3) & ~3) * sizeof(float); };
     auto go = [&](auto pers, auto excl) {
         constexpr bool P = decltype(pers)::value, X = decltype(excl)::value;
         if constexpr (FILL) {
             switch (D) {
-            case 3: hipLaunchKernelGGL((k_query<3, true, true, false, X>), grid, block, 0, s, b, kn); break;
-            case 8: hipLaunchKernelGGL((k_query<8, true, true, false, X>), grid, block, 0, s, b, kn); break;
-            case 12:  // 5 waves per SIMD fit without spilling only without self-exclusion
+            case 3: hipLaunchKernelGGL((k_query<3, true, true, false, X>), grid, block, lds(3), s, b, kn); break;
+            case 8: hipLaunchKernelGGL((k_query<8, true, true, false, X>), grid, block, lds(8), s, b, kn); break;
+            case 12:  // the launch bound of 5 waves per SIMD, only without self-exclusion
                 if constexpr (X)
-                    hipLaunchKernelGGL((k_query<12, true, true, false, X>), grid, block, 0, s, b, kn);
+                    hipLaunchKernelGGL((k_query<12, true, true, false, X>), grid, block, lds(12), s, b, kn);
                 else
-                    hipLaunchKernelGGL((k_query_o5<12, true, true, false, X>), grid, block, 0, s, b, kn);
+                    hipLaunchKernelGGL((k_query_o5<12, true, true, false, X>), grid, block, lds(12), s, b, kn);
                 break;
             default:
                 if (D <= 4)
-                    hipLaunchKernelGGL((k_query<4, false, true, false, X>), grid, block, 0, s, b, kn);
+                    hipLaunchKernelGGL((k_query<4, false, true, false, X>), grid, block, lds(4), s, b, kn);
                 else if (D <= 16)
-                    hipLaunchKernelGGL((k_query<16, false, true, false, X>), grid, block, 0, s, b, kn);
+                    hipLaunchKernelGGL((k_query<16, false, true, false, X>), grid, block, lds(16), s, b, kn);
                 else
-                    hipLaunchKernelGGL((k_query<32, false, true, false, X>), grid, block, 0, s, b, kn);
+                    hipLaunchKernelGGL((k_query<32, false, true, false, X>), grid, block, lds(32), s, b, kn);
             }
         } else {
             switch (D) {
-            case 3: hipLaunchKernelGGL((k_query<3, true, false, P, X>), grid, block, 0, s, b, kn); break;
-            case 8: hipLaunchKernelGGL((k_query_o5<8, true, false, P, X>), grid, block, 0, s, b, kn); break;
-            case 12: hipLaunchKernelGGL((k_query_o5<12, true, false, P, X>), grid, block, 0, s, b, kn); break;
+            case 3: hipLaunchKernelGGL((k_query<3, true, false, P, X>), grid, block, lds(3), s, b, kn); break;
+            case 8: hipLaunchKernelGGL((k_query_o5<8, true, false, P, X>), grid, block, lds(8), s, b, kn); break;
+            case 12: hipLaunchKernelGGL((k_query_o5<12, true, false, P, X>), grid, block, lds(12), s, b, kn); break;
             default:
                 if (D <= 4)
-                    hipLaunchKernelGGL((k_query<4, false, false, P, X>), grid, block, 0, s, b, kn);
+                    hipLaunchKernelGGL((k_query<4, false, false, P, X>), grid, block, lds(4), s, b, kn);
                 else if (D <= 16)
-                    hipLaunchKernelGGL((k_query<16, false, false, P, X>), grid, block, 0, s, b, kn);
+                    hipLaunchKernelGGL((k_query<16, false, false, P, X>), grid, block, lds(16), s, b, kn);
                 else
-                    hipLaunchKernelGGL((k_query<32, false, false, P, X>), grid, block, 0, s, b, kn);
+                    hipLaunchKernelGGL((k_query<32, false, false, P, X>), grid, block, lds(32), s, b, kn);
             }
         }
     };
