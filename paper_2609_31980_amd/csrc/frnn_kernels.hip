@@ -1057,8 +1057,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         // neighbour runs of the group whose first query is window lane gb:
         // lane s < runs probes run s (start, length)
         // one run-table entry per lane, loaded once per window (tables with
-        // more than 64 runs, and rows of more than 8 floats, where the four
-        // registers buy a resident wave, are read per group instead)
+        // more than 64 runs, and rows of more than 8 floats, are read per
+        // group instead: there it was measured faster)
         RunEntry wre{};
         if (DT <= 8 && lane < runs) wre = rtab[lane];
         auto probe = [&](int gb, int s, uint32_t &start, uint32_t &len) {
@@ -1214,9 +1214,9 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 };
                 for (uint32_t v0 = 0; v0 < total; v0 += 64) {
                     // rows of 8 floats or more: no next-chunk prefetch (one
-                    // candidate row live instead of two gives the count
-                    // kernel 6 resident waves per SIMD at D = 8 and 5 at
-                    // D = 12, without spills, which hides more latency)
+                    // candidate row live instead of two; measured faster at
+                    // D = 8 and D = 12, where the extra resident waves hide
+                    // the load instead)
                     if constexpr (DT >= kPrefetchBelow)
                         if (v0 > 0) fetch(v0);
                     const uint32_t pos = pn, j = jn;
@@ -1305,7 +1305,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
 
 // Two entry points with the same body: the second asks the compiler for at
 // least 5 resident waves per SIMD (at most 96 registers), used for the
-// count pass at D = 8 (6 waves) and D = 12 where it fits without spilling.
+// count pass at D = 8 and D = 12 and the D = 12 fill without self-exclusion,
+// each of which fits that bound without spilling.
 // PERS selects the persistent scheduling at compile time, so each kernel
 // holds one copy of the window body.
 template <int DT, bool EXACT_D, bool FILL, bool PERS, bool EXCL>
