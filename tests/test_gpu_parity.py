@@ -83,6 +83,22 @@ def test_dimensions(orc, frnn, D):
     check_full(orc, X, r, 5, what=f"D={D} K=5")
 
 
+@pytest.mark.parametrize("D", [12, 32])
+def test_window_sizes_by_dimension(orc, frnn, D):
+    """The window's query rows take LDS in proportion to the window size and
+    the row width: windows of 1, 8 and 64 queries at D = 12 and D = 32 (the
+    largest row template), with and without self-exclusion."""
+    rng = np.random.default_rng(300 + D)
+    X = rng.random((3000, D), dtype=np.float32)
+    # about 13 neighbours per row, the longest above the 64-key stash at D = 32
+    r = float(np.float32({12: 0.74, 32: 1.65}[D]))
+    for qpi in (1, 8, 64):
+        o = frnn.default_opts(queries_per_item=qpi)
+        say(f"D={D} window {qpi}")
+        check_full(orc, X, r, 0, opts=o, what=f"D={D} window {qpi}")
+        check_full(orc, X, r, 7, exclude_self=True, opts=o, what=f"D={D} window {qpi} K=7 exclude")
+
+
 def test_empty_and_single(orc, frnn):
     X = np.zeros((1, 3), np.float32)
     check_full(orc, X, 0.1, 0, what="N=1")
