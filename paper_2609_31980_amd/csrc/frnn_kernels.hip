@@ -33,6 +33,11 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Writes value into lane `lane` (wave-uniform) of old and returns the rest
+// of old unchanged: one v_writelane (the compiler's own intrinsic, reached
+// by name, so its wait states are handled as for any other instruction).
+extern "C" __device__ int frnn_writelane_i32(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 __device__ __forceinline__ int64_t readlane64(int64_t v, int t) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, t);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), t);
@@ -1208,7 +1213,13 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                                     b.stash[readlane64(wst, t) + slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
                                 }
                             }
-                            cntv = lane == t ? c + (uint32_t)__popcll(hm) : cntv;
+                            // query t's count lives in lane t (t is scalar; every
+                            // lane is active here); a single lane write measured
+                            // faster for rows of 12 floats or more, the same at 8
+                            if constexpr (DT >= kScalarWaveFrom)
+                                cntv = (uint32_t)frnn_writelane_i32((int)(c + (uint32_t)__popcll(hm)), t, (int)cntv);
+                            else
+                                cntv = lane == t ? c + (uint32_t)__popcll(hm) : cntv;
                         }
                     }
                 };
