@@ -69,7 +69,10 @@ struct frnn_server_s {
         const int64_t D = o.D, Dp = (o.D + 3) & ~3;
         const double cpp = opts.o.cells_per_point;
         // input + sorted rows + 4 per-point arrays + cells + per-query work
-        return N * (4 * D + 4 * Dp + 16 + 40) + (int64_t)(4.0 * cpp * (double)N) + 4096;
+        // (degree, two row scans, long-row record, and the stash row of
+        // stash_cap 8-byte keys)
+        const int64_t stash = 8 * (int64_t)std::max(1, opts.o.stash_cap);
+        return N * (4 * D + 4 * Dp + 16 + 40 + stash) + (int64_t)(4.0 * cpp * (double)N) + 4096;
     }
     void worker(int id);
 };

@@ -122,8 +122,9 @@ def test_server_alone_and_in_the_mix(orc, frnn):
 
 def test_server_budget_admission(frnn):
     ev = inputs.tracks(20000, 8, seed=5)
-    # room for about two events at a time: later ones wait for releases
-    srv = frnn.Server(8, 0.1, 256, hbm_budget_bytes=8_000_000, max_batch_events=8, max_inflight=2)
+    # room for about two events at a time (each reserves about 12.8 MB at
+    # admission with the default 64-key stash): later ones wait for releases
+    srv = frnn.Server(8, 0.1, 256, hbm_budget_bytes=30_000_000, max_batch_events=8, max_inflight=2)
     ts = [srv.submit(ev) for _ in range(6)]
     ref = None
     for t in ts:
