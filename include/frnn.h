@@ -86,7 +86,7 @@ typedef struct {
     int32_t persistent;       /* 1: persistent kernel draining a device work queue */
     int32_t blocks_per_cu;    /* persistent grid size = 256 CUs x this (1..16) */
     int32_t row_cap_lds;      /* rows longer than this sort in global memory (1..512) */
-    int32_t stash_cap;        /* hits per query kept by the count pass (0, 8, 16, 32, 64; default 64);
+    int32_t stash_cap;        /* hits per query kept by the count pass (0, 8, 16, 32, 64, 128; default 64);
                                  the fill pass only re-evaluates rows longer than this */
 } frnn_opts;
 

@@ -1361,7 +1361,7 @@ __device__ __forceinline__ void sort_regs(uint64_t (&v)[N]) {
 // Every row's per-event offset, and the rows the count pass kept whole
 // (0 < length <= SC): one lane per query row, in output order, sorts the
 // row's keys in registers (rows of up to 16 keys); rows of 17..SC keys (the
-// 32- and 64-key stashes; one key per lane) are ranked by the whole wave.  The query chunks partition
+// 32-, 64- and 128-key stashes) are ranked by the whole wave.  The query chunks partition
 // each event's rows, so
 // chunk c covers global rows r0..r1-1 of one event and its output is the
 // contiguous range offs[r0]..offs[r1]; one block per chunk.  When that range
@@ -1369,8 +1369,9 @@ __device__ __forceinline__ void sort_regs(uint64_t (&v)[N]) {
 // places of longer rows receive filler that the fill pass, which runs later
 // on the same stream, overwrites.
 // Staged output pairs per block: with the mid-row list and the four rank
-// buffers the block stays within 32 KB of LDS (five blocks per CU).
-constexpr int kShortStage = kChunkRows * 29 / 2;
+// buffers (64 keys each, 128 for the 128-key stash) the block stays within
+// 32 KB of LDS (five blocks per CU).
+constexpr int short_stage(int sc) { return sc > 64 ? kChunkRows * 27 / 2 : kChunkRows * 29 / 2; }
 
 template <int N>
 __device__ __forceinline__ void place_row(uint64_t (&v)[N], uint32_t keep, bool staged, int64_t rel,
@@ -1397,10 +1398,12 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
     // rows of up to LM keys: one lane per row; longer stash rows (up to SC):
     // one wave per row, ranked
     constexpr int LM = SC < 16 ? SC : 16;
+    constexpr int KP = SC > 64 ? 2 : 1;  // keys per lane in the wave rank
+    constexpr int kShortStage = short_stage(SC);
     __shared__ uint32_t sidx[SC > 0 ? kShortStage : 1];
     __shared__ float sd2[SC > 0 ? kShortStage : 1];
-    __shared__ uint16_t s_mid[SC > LM ? kChunkRows : 1];                     // rows of LM+1..SC keys
-    __shared__ __align__(16) uint64_t s_rank[SC > LM ? kChunkRows / 64 : 1][64];  // one row per wave
+    __shared__ uint16_t s_mid[SC > LM ? kChunkRows : 1];  // rows of LM+1..SC keys
+    __shared__ __align__(16) uint64_t s_rank[SC > LM ? kChunkRows / 64 : 1][64 * KP];  // one row per wave
     __shared__ uint32_t s_nmid;
     if (!out_fits(b)) return;
     if (blockIdx.x == 0)  // each event's leading offset, the one entry no row writes
@@ -1459,9 +1462,10 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
         if constexpr (SC > LM) {
             // stash rows of LM+1..SC keys: the block lists them in LDS and its
             // waves take them in turn (a block of dense rows keeps all four
-            // busy); a wave ranks one row at a time, lane i holding key i and
-            // counting the smaller keys of the row from LDS broadcasts, eight
-            // a step (keys of a row are distinct, so the counts are places)
+            // busy); a wave ranks one row at a time, lane i holding keys i
+            // (and 64 + i for the 128-key stash) and counting the smaller
+            // keys of the row from LDS broadcasts, eight a step (keys of a
+            // row are distinct, so the counts are places)
             const int lane = lane_id(), wv = threadIdx.x >> 6;
             if (threadIdx.x == 0) s_nmid = 0;
             __syncthreads();
@@ -1477,52 +1481,66 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
             const uint32_t nmid = s_nmid;
             uint64_t *rb = &s_rank[wv][0];
             const ulonglong2 *rb2 = reinterpret_cast<const ulonglong2 *>(rb);
-            // four rows per round, their lengths, offsets and keys loaded
-            // together (a lane past SC reads nothing: the stash row ends there)
-            constexpr int RB = 4;
+            // RB rows per round, their lengths, offsets and keys loaded
+            // together (a key past SC is not read: the stash row ends there)
+            constexpr int RB = KP == 1 ? 4 : 2;
             constexpr uint32_t NW = kChunkRows / 64;
             for (uint32_t m0 = wv; m0 < nmid; m0 += RB * NW) {
                 uint32_t n[RB];
                 int64_t ot[RB];
-                uint64_t key[RB];
+                uint64_t key[RB][KP];
 #pragma unroll
                 for (int k = 0; k < RB; ++k) {
                     const uint32_t m = m0 + k * NW;
                     n[k] = 0;
                     ot[k] = 0;
-                    key[k] = ~0ull;
+#pragma unroll
+                    for (int p = 0; p < KP; ++p) key[k][p] = ~0ull;
                     if (m < nmid) {
                         const int64_t qr = ch.r0 + (int64_t)uniform((uint32_t)s_mid[m]);
                         n[k] = b.deg[qr];
                         ot[k] = b.offs[qr];
-                        if (lane < SC) key[k] = b.stash[qr * SC + lane];
+#pragma unroll
+                        for (int p = 0; p < KP; ++p)
+                            if (lane + 64 * p < SC) key[k][p] = b.stash[qr * SC + lane + 64 * p];
                     }
                 }
 #pragma unroll
                 for (int k = 0; k < RB; ++k) {
                     if (n[k] == 0) break;
-                    const uint64_t kk = (uint32_t)lane < n[k] ? key[k] : ~0ull;
-                    rb[lane] = kk;
+                    uint64_t kk[KP];
+                    uint32_t rank[KP];
+#pragma unroll
+                    for (int p = 0; p < KP; ++p) {
+                        kk[p] = (uint32_t)(lane + 64 * p) < n[k] ? key[k][p] : ~0ull;
+                        rb[lane + 64 * p] = kk[p];
+                        rank[p] = 0;
+                    }
                     wave_lds_sync();
-                    uint32_t rank = 0;
                     for (uint32_t i = 0; i < n[k]; i += 8) {
                         ulonglong2 c[4];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) c[u] = rb2[i / 2 + u];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) rank += (c[u].x < kk ? 1u : 0u) + (c[u].y < kk ? 1u : 0u);
+                        for (int p = 0; p < KP; ++p)
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                rank[p] += (c[u].x < kk[p] ? 1u : 0u) + (c[u].y < kk[p] ? 1u : 0u);
                     }
                     wave_lds_sync();
                     const uint32_t keep = (kn.K > 0 && n[k] > (uint32_t)kn.K) ? (uint32_t)kn.K : n[k];
-                    if ((uint32_t)lane < n[k] && rank < keep) {
-                        const uint32_t j = (uint32_t)kk;
-                        const float d = __uint_as_float((uint32_t)(kk >> 32));
-                        if (staged) {
-                            sidx[ot[k] - base + rank] = j;
-                            sd2[ot[k] - base + rank] = d;
-                        } else {
-                            b.out->indices[ot[k] + rank] = (int32_t)j;
-                            if (b.out->dist2) b.out->dist2[ot[k] + rank] = d;
+#pragma unroll
+                    for (int p = 0; p < KP; ++p) {
+                        if ((uint32_t)(lane + 64 * p) < n[k] && rank[p] < keep) {
+                            const uint32_t j = (uint32_t)kk[p];
+                            const float d = __uint_as_float((uint32_t)(kk[p] >> 32));
+                            if (staged) {
+                                sidx[ot[k] - base + rank[p]] = j;
+                                sd2[ot[k] - base + rank[p]] = d;
+                            } else {
+                                b.out->indices[ot[k] + rank[p]] = (int32_t)j;
+                                if (b.out->dist2) b.out->dist2[ot[k] + rank[p]] = d;
+                            }
                         }
                     }
                 }
@@ -1767,6 +1785,7 @@ hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipSt
     case 16: hipLaunchKernelGGL(k_short_rows<16>, grid, block, 0, s, b, kn); break;
     case 32: hipLaunchKernelGGL(k_short_rows<32>, grid, block, 0, s, b, kn); break;
     case 64: hipLaunchKernelGGL(k_short_rows<64>, grid, block, 0, s, b, kn); break;
+    case 128: hipLaunchKernelGGL(k_short_rows<128>, grid, block, 0, s, b, kn); break;
     default: return hipErrorInvalidValue;
     }
     FRNN_CHECK_LAUNCH();

@@ -303,8 +303,9 @@ frnn_status Opts::validate(std::string *why) const {
         return bad("queries_per_item must be a power of two in 1..64");
     if (o.blocks_per_cu < 1 || o.blocks_per_cu > 16) return bad("blocks_per_cu out of 1..16");
     if (o.row_cap_lds < 1 || o.row_cap_lds > kRowLds) return bad("row_cap_lds out of 1..512");
-    if (o.stash_cap != 0 && o.stash_cap != 8 && o.stash_cap != 16 && o.stash_cap != 32 && o.stash_cap != 64)
-        return bad("stash_cap must be 0, 8, 16, 32 or 64");
+    if (o.stash_cap != 0 && o.stash_cap != 8 && o.stash_cap != 16 && o.stash_cap != 32 && o.stash_cap != 64 &&
+        o.stash_cap != 128)
+        return bad("stash_cap must be 0, 8, 16, 32, 64 or 128");
     return FRNN_OK;
 }
 
