@@ -14,7 +14,7 @@ Default run (about two minutes):
   * serving: Poisson arrivals of log-normal-size events through the
     continuous-batching server vs a FIFO of plain per-event calls.
 
-Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -396,8 +396,8 @@ def main():
                     help="also write and then read this many MiB with plain kernels (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
-              "(events shard across GPUs with no collectives; see the design notes)", file=sys.stderr)
+        print("bench.py: the benchmark measures one GPU only; multi-GPU runs are not supported "
+              "(events would shard across GPUs, one process each, with no collectives)", file=sys.stderr)
         sys.exit(2)
 
     import torch
