@@ -204,6 +204,12 @@ def pin_exact_small(o, seed=7):
             assert csr_rows(o.frnn(X, r, K, Q=Q)) == exact_rows(X, r, K, Q=Q), f"Q D={D} K={K}"
         assert csr_rows(o.frnn(X, r, 0, exclude_self=True)) == \
             exact_rows(X, r, 0, exclude_self=True), f"exclude D={D}"
+        # counts only: the exact row lengths, with separate queries and
+        # with self-exclusion given as explicit ids
+        lens = [len(row) for row in exact_rows(X, r, 0, Q=Q)]
+        assert o.degrees(X, r, Q=Q).tolist() == lens, f"degrees Q D={D}"
+        lens = [len(row) for row in exact_rows(X, r, 0, exclude_self=True)]
+        assert o.degrees(X, r, Q=X, self_ids=np.arange(len(X))).tolist() == lens, f"degrees excl D={D}"
 
 
 def pin_numpy_bitwise(o, X, r, K=0, Q=None, self_ids=None):
@@ -211,6 +217,38 @@ def pin_numpy_bitwise(o, X, r, K=0, Q=None, self_ids=None):
     want = numpy_csr(X, r, K, Q=Q, self_ids=self_ids)
     got = o.frnn(X, r, K, Q=Q, self_ids=self_ids)
     assert_csr_equal(as_tuple(got), want, "numpy route")
+
+
+def numpy_degrees(X, r, Q=None, self_ids=None) -> np.ndarray:
+    """Uncapped in-radius counts per query from the float32 per-axis NumPy
+    route (numpy_dist2), leaving out self_ids[i] from row i when given."""
+    Qa = X if Q is None else Q
+    r32 = np.float32(r)
+    r2 = np.multiply(r32, r32, dtype=np.float32)
+    out = np.zeros(len(Qa), np.int64)
+    for a in range(0, len(Qa), 512):
+        hit = numpy_dist2(Qa[a:a + 512], X) <= r2
+        if self_ids is not None:
+            k = np.arange(hit.shape[0])
+            sid = np.asarray(self_ids[a:a + 512], np.int64)
+            ok = (sid >= 0) & (sid < X.shape[0])
+            hit[k[ok], sid[ok]] = False
+        out[a:a + 512] = hit.sum(axis=1)
+    return out
+
+
+def pin_degrees(o, X, r, Q=None, self_ids=None, caps=(0, 4)):
+    """The counts-only entry point and the CSR's degree field: both equal
+    the uncapped row lengths of the independent NumPy route (Eq. 1 counted
+    before the K cap), and the CSR's row lengths equal min(degree, K)."""
+    want = numpy_degrees(X, r, Q=Q, self_ids=self_ids)
+    got = o.degrees(X, r, Q=Q, self_ids=self_ids)
+    assert np.array_equal(got, want), "degrees: counts-only path differs"
+    for K in caps:
+        c = o.frnn(X, r, K, Q=Q, self_ids=self_ids)
+        assert np.array_equal(c.degree, want), f"degrees: CSR degree field differs (K={K})"
+        lens = np.minimum(want, K) if K > 0 else want
+        assert np.array_equal(np.diff(c.offsets), lens), f"degrees: row lengths differ (K={K})"
 
 
 def pin_fp64_band(o, X, r, Q=None):
@@ -406,9 +444,13 @@ def pin_boundary_ladder(o):
         got = sorted(zip(c.row(0)[0].tolist(), c.row(0)[1].view(U32).tolist()))
         exp = sorted((j, int(sb[j])) for j in range(len(P)) if sb[j] <= r2b)
         assert got == exp, f"boundary ladder r={r} D={D}"
+        # the counts-only path decides the same pairs
+        assert o.degrees(P, r, Q=P[:1]).tolist() == [len(exp)], f"boundary ladder degrees r={r} D={D}"
+        assert c.degree.tolist() == [len(exp)], f"boundary ladder degree field r={r} D={D}"
 
 
-ALL_FAST_PINS = ("golden", "boundary", "exact", "numpy", "fp64", "symmetry", "invariance", "range1d")
+ALL_FAST_PINS = ("golden", "boundary", "exact", "numpy", "degrees", "fp64", "symmetry", "invariance",
+                 "range1d")
 
 
 def run_fast_pins(o, X):
@@ -416,12 +458,16 @@ def run_fast_pins(o, X):
     first failure and returns its name, or None when every pin passed."""
     r = float(np.float32(0.1))
     Q = (X[:200] + np.float32(0.01)).astype(np.float32)
+    sub = np.arange(3, len(X), 5)     # a query subset whose self ids are not 0..M-1
     steps = {
         "golden": lambda: pin_golden_cases(o),
         "boundary": lambda: pin_boundary_ladder(o),
         "exact": lambda: pin_exact_small(o),
         "numpy": lambda: (pin_numpy_bitwise(o, X, r, 0), pin_numpy_bitwise(o, X, r, 4),
                           pin_numpy_bitwise(o, X, r, 0, Q=Q)),
+        "degrees": lambda: (pin_degrees(o, X, r),
+                            pin_degrees(o, X, r, Q=X[sub], self_ids=sub),
+                            pin_degrees(o, X, r, Q=Q)),
         "fp64": lambda: pin_fp64_band(o, X, r),
         "symmetry": lambda: pin_symmetry(o, X, r),
         "invariance": lambda: pin_invariances(o, X, r, 0),

@@ -26,6 +26,15 @@ MUTANTS = [
     ("queries used as references", "w->X + j * (int64_t)w->D", "w->Q + (j % w->M) * (int64_t)w->D"),
     ("absolute instead of square", "float u = t * t;", "float u = fabsf(t);"),
     ("squared radius in double", "if (s <= w->r2)", "if ((double)s <= (double)sqrtf(w->r2) * (double)sqrtf(w->r2))"),
+    # mistakes confined to the counts (degrees) path or to the degree field
+    ("counts path keeps self", "if (j == self) continue;", "if (w->want_rows && j == self) continue;"),
+    ("counts path strict boundary", "if (s <= w->r2) {", "if (w->want_rows ? s <= w->r2 : s < w->r2) {"),
+    ("degree recorded after the cap", "w->degree[i] = n;",
+     "w->degree[i] = (w->K > 0 && n > w->K) ? w->K : n;"),
+    ("counts path self by position", "int64_t self = w->self_ids ? w->self_ids[i] : -1;",
+     "int64_t self = w->self_ids ? (w->want_rows ? w->self_ids[i] : i) : -1;"),
+    ("counts path skips the last reference", "for (int64_t j = 0; j < w->N; ++j) {",
+     "for (int64_t j = 0; j < (w->want_rows ? w->N : w->N - 1); ++j) {"),
 ]
 
 

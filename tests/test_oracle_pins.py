@@ -64,6 +64,23 @@ def test_numpy_bitwise_d12(orc):
     pinlib.pin_numpy_bitwise(orc, x, inputs.C4_RADIUS, 64, Q=q)
 
 
+def test_degrees_uniform_cube(orc, c1):
+    """Counts only and the CSR's degree field against the NumPy route."""
+    pinlib.pin_degrees(orc, c1.points, c1.r, caps=(0, 4, 8))
+
+
+def test_degrees_tracks_subset_self_ids(orc):
+    w = inputs.c2()
+    X = w.points[:30000]
+    s = inputs.subset_rows(len(X), 0.02, 17)
+    pinlib.pin_degrees(orc, X, w.r, Q=X[s], self_ids=s, caps=(0, 4, 256))
+
+
+def test_degrees_clustered_d12_queries(orc):
+    x, q = inputs.clustered(30000, 400, 12, 0.03, seed=8)
+    pinlib.pin_degrees(orc, x, inputs.C4_RADIUS, Q=q, caps=(0, 4, 64))
+
+
 def test_fp64_band_c1(orc, c1):
     flagged = pinlib.pin_fp64_band(orc, c1.points, c1.r)
     assert len(flagged) <= 8
