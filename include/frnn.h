@@ -157,7 +157,7 @@ void frnn_csr_release(frnn_csr *csr);
 
 /* ------------------------------------------------------- host-array calls
  * Synchronous search on host arrays (the paper's public host interface,
- * Sec. 4.3): the points (and queries) are copied to the device through pinned
+ * Secs. 4.1 and 4.2): the points (and queries) are copied to the device through pinned
  * staging buffers, the host copy of one chunk overlapping the DMA of the
  * previous one; the batched device path runs on a library stream; the CSR
  * comes back compact, in pinned host memory owned by the library until
