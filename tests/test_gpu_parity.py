@@ -188,15 +188,26 @@ def test_radius_above_index(frnn):
 
 
 def test_tracking_event_300k(orc, frnn):
-    """The 300,000-point tracking event at full size: sampled rows against
-    the oracle plus properties that hold at any size."""
+    """The 300,000-point tracking event at full size, every row against the
+    oracle's complete CSR (offsets, indices and dist2 bits), through the
+    eager build + query calls and through the batched graph path the
+    benchmark times (run twice, so the second run replays its graphs), plus
+    properties that hold at any size."""
+    import torch
     w = inputs.c2()
-    say("tracks-300k: GPU")
+    say("tracks-300k: oracle, all 300,000 rows")
+    want = pinlib.as_tuple(orc.frnn(w.points, w.r, w.K))
+    say("tracks-300k: GPU, eager API")
     got = gpu_csr(w.points, w.r, w.K)
     check_csr_invariants(got, len(w.points), w.K)
-    rows = inputs.subset_rows(len(w.points), 0.005, 7)
-    say("tracks-300k: oracle rows")
-    check_rows(orc, got, w.points, w.r, w.K, rows, what="tracks-300k")
+    pinlib.assert_csr_equal(got, want, "tracks-300k eager API")
+    xd = dev(w.points)
+    for rep in range(2):
+        say(f"tracks-300k: GPU, graph path run {rep}")
+        c = frnn.query_batch([xd], w.r, w.K)[0]
+        pinlib.assert_csr_equal(c.numpy(), want, f"tracks-300k graph path run {rep}")
+        c.release()
+    torch.cuda.synchronize()
     # K=256 never binds here (max degree ~ 12): the relation is symmetric
     off, idx, d2 = got
     assert np.diff(off).max() < w.K
