@@ -9,8 +9,9 @@ Default run (about two minutes):
   * the CPU oracle timed on a bounded sample of the same event;
   * paper-shaped: the 271,663-point 12-D self-join (r=0.12, K=1000, self
     pairs excluded) standing in for the paper's measured event;
-  * batched: 64 uneven tracking events, one graph-replayed persistent batch
-    vs 64 plain per-event build+query calls (identical output checked);
+  * batched: 64 uneven tracking events, one graph-replayed batch (one
+    launch per pipeline step over all events) vs 64 plain per-event
+    build+query calls (identical output checked);
   * serving: Poisson arrivals of log-normal-size events through the
     continuous-batching server vs a FIFO of plain per-event calls.
 

@@ -83,8 +83,11 @@ typedef struct {
     int32_t cell_multiple;    /* m: cell width about r/m, reach +-m cells (1..3) */
     int32_t cells_per_item;   /* grid cells along the first grid axis per work item (1..8; default 2) */
     int32_t queries_per_item; /* queries evaluated per work item (1..64) */
-    int32_t persistent;       /* 1: persistent kernel draining a device work queue */
-    int32_t blocks_per_cu;    /* persistent grid size = 256 CUs x this (1..16) */
+    int32_t persistent;       /* count and fill passes as persistent kernels whose resident waves
+                                 drain a device work queue of windows (runs of cell blocks of one
+                                 event), costliest events first: 0 never, 1 always, 2 (default)
+                                 when the windows are at most twice the resident waves */
+    int32_t blocks_per_cu;    /* cap on resident blocks per CU of a persistent pass (1..16) */
     int32_t row_cap_lds;      /* rows longer than this sort in global memory (1..512) */
     int32_t stash_cap;        /* hits per query kept by the count pass (0, 8, 16, 32, 64, 128; default 64);
                                  the fill pass only re-evaluates rows longer than this */
@@ -137,9 +140,12 @@ typedef struct {
 } frnn_event;
 
 /* Many independent events, one pipeline: the events are binned, counted and
- * filled by single launches (a persistent kernel drains (event, cell block)
- * work items), the fixed pipeline is replayed as a HIP graph when the same
- * capacity recurs, and outs[e] is bit-identical to querying event e alone.
+ * filled by single launches over all events (work items are windows of
+ * sorted queries, i.e. runs of cell blocks of one event; with
+ * opts->persistent the resident waves drain them from a per-XCD queue,
+ * costliest events first), the fixed pipeline is replayed as a HIP graph
+ * when the same capacity recurs, and outs[e] is bit-identical to querying
+ * event e alone.
  * All events share D, r, K and flags.  Synchronises the stream once.
  * The outs[] share one allocation; release each of them.
  * Errors: INVALID_ARG, NONFINITE, OOM, HIP. */
@@ -148,7 +154,10 @@ frnn_status frnn_query_batch(const frnn_event *events, int32_t E, int32_t D,
                              const frnn_opts *opts, void *stream, frnn_csr *outs);
 
 /* Copy a CSR into caller buffers (device, or host when to_host != 0); any of
- * the three destinations may be NULL to skip it.  Synchronous when to_host. */
+ * the three destinations may be NULL to skip it.  Synchronous when to_host;
+ * a host copy also reports FRNN_ERR_INTERNAL when the output came from a run
+ * whose fill pass recounted a row longer than the stash differently from
+ * the count pass (an internal consistency check of the device code). */
 frnn_status frnn_csr_copy(const frnn_csr *csr, int64_t *offsets, int32_t *indices,
                           float *dist2, int32_t to_host, void *stream);
 

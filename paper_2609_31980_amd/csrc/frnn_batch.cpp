@@ -110,8 +110,10 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     lrows.reset(sizeof(uint32_t) * sh.q_cap, s);
     lat.reset(sizeof(int64_t) * 2 * sh.q_cap, s);
     stash.reset(sizeof(uint64_t) * sh.q_cap * std::max(1, sh.o.stash_cap), s);
-    flist.reset(sizeof(uint32_t) * std::max<int64_t>(1, sh.qch_cap * (kChunkRows / sh.o.queries_per_item)), s);
+    const int64_t fill_cap = std::max<int64_t>(1, (int64_t)sh.qch_cap * (kChunkRows / sh.o.queries_per_item));
+    flist.reset(sizeof(uint32_t) * fill_cap, s);
     part.reset(sizeof(uint64_t) * 2 * kScanBlocks, s);
+    lpt.reset(sizeof(uint32_t) * lpt_words(Ec), s);
 
     Bufs b{};
     b.bd = desc.as<BatchDesc>();
@@ -141,6 +143,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     b.long_at = lat.as<int64_t>();
     b.stash = stash.as<uint64_t>();
     b.fill_list = flist.as<uint32_t>();
+    b.lpt = lpt.as<uint32_t>();
     b.scan_part = part.as<uint64_t>();
     b.out = reinterpret_cast<OutDesc *>(desc.as<char>() + kOutOff);
     b.bases = reinterpret_cast<int64_t *>(hv.as<char>() + 2 * sizeof(Counters));
@@ -156,8 +159,9 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     kn_.window = sh.o.queries_per_item;
     kn_.cells_per_item = sh.o.cells_per_item;
     kn_.long_cap = sh.o.row_cap_lds;
-    kn_.persistent = sh.o.persistent;
     kn_.stash_cap = sh.o.stash_cap;
+    kn_.fill_cap = (uint32_t)fill_cap;
+    kn_.persistent = use_persistent(sh.o, Ec, sh.qch_cap, kn_, D);
     FRNN_HIP(hipEventCreateWithFlags(&counted_, hipEventDisableTiming));
     FRNN_HIP(hipEventCreateWithFlags(&done_, hipEventDisableTiming));
 }
@@ -165,7 +169,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
 void BatchContext::retarget(hipStream_t s) {
     DevBuf *all[] = {&desc, &hv, &grid, &cell_off, &ext,
                      &xs, &perm, &key, &rank, &skey, &cells, &qs, &qperm, &qkey, &qrank, &sqkey,
-                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &lat, &stash, &flist, &part, &lk_};
+                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &lat, &stash, &flist, &part, &lpt, &lk_};
     for (DevBuf *d : all) d->set_stream(s);
 }
 
@@ -261,7 +265,8 @@ void BatchContext::launch_a(hipStream_t s) {
         LAUNCH("scan_cells_q", s, launch_scan_cells(bq_, sh_.cells_cap, true, s));
         LAUNCH("scatter_q", s, launch_scatter(bq_, sh_.qch_cap, true, s));
     }
-    LAUNCH("count", s, launch_count(bq_, kn_, D, query_blocks(sh_.o, sh_.qch_cap), s));
+    if (kn_.persistent) LAUNCH("lpt", s, launch_lpt(bq_, kn_, s));
+    LAUNCH("count", s, launch_count(bq_, kn_, D, query_blocks(sh_.o, sh_.qch_cap, kn_.persistent), s));
     LAUNCH("scan_rows", s, launch_scan_rows(bq_, kn_, sh_.q_cap, s));
 }
 
@@ -432,9 +437,10 @@ BatchOutput alloc_output(const BatchContext &ctx, int64_t pairs, int64_t long_ke
     const int E = ctx.E();
     const size_t b_off = sizeof(int64_t) * (ctx.total_q() + E);
     const size_t b_idx = (sizeof(int32_t) * pairs + 255) / 256 * 256;
-    const size_t b_d2 = want_d2 ? sizeof(float) * pairs : 0;
+    const size_t b_d2 = want_d2 ? (sizeof(float) * pairs + 15) / 16 * 16 : 0;
     std::unique_ptr<OutputOwner> own(new OutputOwner());
-    own->buf.reset(b_off + b_idx + b_d2, s);
+    own->buf.reset(b_off + b_idx + b_d2 + 16, s);
+    own->status = reinterpret_cast<uint32_t *>(own->buf.as<char>() + b_off + b_idx + b_d2);
     if (!long_scratch) {
         bo.long_keys.reset(sizeof(uint64_t) * std::max<int64_t>(1, long_keys), s);
         long_scratch = bo.long_keys.as<uint64_t>();
@@ -442,7 +448,7 @@ BatchOutput alloc_output(const BatchContext &ctx, int64_t pairs, int64_t long_ke
     char *ob = own->buf.as<char>();
     bo.od = OutDesc{reinterpret_cast<int64_t *>(ob), reinterpret_cast<int32_t *>(ob + b_off),
                     want_d2 ? reinterpret_cast<float *>(ob + b_off + b_idx) : nullptr,
-                    long_scratch, pairs, long_keys};
+                    long_scratch, pairs, long_keys, own->status};
     bo.own = own.release();
     return bo;
 }
@@ -497,6 +503,7 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
             if (ctx->expect_long()) {
                 ctx->phase_b_long(s);
                 long_queued = true;
+                own->long_ran = true;
             }
         }
         BatchCounts c = ctx->wait_counts();
@@ -516,8 +523,10 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
                 own.reset(bo.own);
                 bo.own = nullptr;
                 ctx->phase_b(bo.od, long_rows, s);
+                own->long_ran = long_rows;
             } else if (long_rows && !long_queued) {
                 ctx->phase_b_long(s);
+                own->long_ran = true;
             }
             bo.own = own.release();
             hand_out(*ctx, c, bo, outs);

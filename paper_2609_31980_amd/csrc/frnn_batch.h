@@ -15,8 +15,10 @@
 // queued right behind A and the read-back, so the host checks the counts
 // while B runs; the fill kernels write nothing when the run does not fit,
 // and only then does the host allocate the exact size and replay B.
-// The count and fill kernels are persistent: a grid of resident workgroups
-// drains one device work queue of (event, cell block) items.
+// The count and fill kernels take windows of sorted queries (runs of cell
+// blocks of one event) as work items: one wave per window from the
+// hardware's dispatch, or, persistent (frnn_opts.persistent), a resident
+// grid dealing per-XCD queues built costliest event first (k_lpt).
 #pragma once
 
 #include <condition_variable>
@@ -111,7 +113,8 @@ private:
     Bufs bb_{}, bq_{};  // build run and query run
     size_t o_ev_ = 0, o_pc_ = 0, o_qc_ = 0;
     DevBuf desc, hv, grid, cell_off, ext, xs, perm, key, rank,
-        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, lat, stash, flist, part;
+        skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, lat, stash, flist, part,
+        lpt;
     Pinned back_;
     MappedHost stage_;            // descriptors, host side, read by the first kernel
     size_t stage_cap_ = 0;        // bytes, the capacity of the descriptor block

@@ -75,7 +75,7 @@ void frnn_opts_default(frnn_opts *o) {
     o->cell_multiple = 1;
     o->cells_per_item = 2;
     o->queries_per_item = 32;
-    o->persistent = 0;
+    o->persistent = 2;
     o->blocks_per_cu = 8;
     o->row_cap_lds = kRowLds;
     o->stash_cap = 64;
@@ -234,7 +234,11 @@ frnn_status frnn_csr_copy(const frnn_csr *c, int64_t *offsets, int32_t *indices,
             if (!c->dist2) return fail(FRNN_ERR_INVALID_ARG, "csr holds no dist2");
             FRNN_HIP(hipMemcpyAsync(dist2, c->dist2, sizeof(float) * c->nnz, k, s));
         }
-        if (to_host) FRNN_HIP(hipStreamSynchronize(s));
+        if (to_host) {
+            FRNN_HIP(hipStreamSynchronize(s));
+            // a row whose fill-pass recount differed from its count is reported here
+            if (auto *own = static_cast<OutputOwner *>(c->owner_)) return own->check(s);
+        }
         return FRNN_OK;
     });
 }

@@ -75,7 +75,8 @@ struct Counters {
     uint32_t status;       // kStatus* bits
     uint32_t n_fill;       // windows listed for the fill pass
     uint32_t plan_done;    // plan blocks finished (the last one scans the cell counts)
-    uint32_t pad[7];
+    uint32_t n_fill_light; // windows listed for the fill pass from the back of the list (lighter ones)
+    uint32_t pad[6];
     // persistent count-pass work queues, one per XCD, one 64-byte line each
     uint32_t heads[8][16];
 };
@@ -105,6 +106,8 @@ struct OutDesc {
     uint64_t *long_keys;   // [cap_long] scratch rows of the fill pass
     int64_t cap_pairs;
     int64_t cap_long;
+    uint32_t *status;      // written by the long-row pass: kStatusInternal when the fill's
+                           // recount of a row differed from the count pass
 };
 
 // Per-run scalars passed by value.
@@ -118,7 +121,23 @@ struct Knobs {
     int32_t long_cap;      // rows longer than this sort in global memory
     int32_t persistent;
     int32_t stash_cap;     // hits per query kept by the count pass (0 = none)
+    uint32_t fill_cap;     // entries of fill_list
 };
+
+// Layout of the persistent count pass's work order for E events (words):
+//   order[E]       events by decreasing estimated cost per window
+//   chunk0[E]      first query chunk of each event
+//   nwin[E]        windows of each event
+//   pre[8][E + 1]  per XCD: exclusive prefix of the event slices in that order
+constexpr int64_t lpt_words(int64_t E) { return 3 * E + 8 * (E + 1); }
+// most events the work order is built for (one block, in LDS); larger
+// batches take the non-persistent launch
+constexpr int kLptMaxEvents = 1024;
+
+// A listed window whose fill work (queries with rows longer than the stash
+// times the candidates of their group) reaches this many distance
+// evaluations goes to the front of the fill list.
+constexpr uint32_t kFillHeavy = 1u << 15;
 
 // Device buffers of a run.
 struct Bufs {
@@ -149,7 +168,9 @@ struct Bufs {
     uint32_t *long_rows;   // [total_q] length of each row listed for the row sort
     int64_t *long_at;      // [2*total_q] its scratch offset and output offset
     uint64_t *stash;       // [total_q][stash_cap] first hit keys per query (global row)
-    uint32_t *fill_list;   // windows holding rows longer than the stash
+    uint32_t *fill_list;   // windows holding rows longer than the stash: heavier ones from the
+                           // front, lighter ones from the back (fill_cap entries)
+    uint32_t *lpt;         // persistent count pass: work order (see k_lpt), lpt_words(E) words
     uint64_t *scan_part;   // scan block partials (2 x kScanBlocks)
     OutDesc *out;
 };

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "frnn_device.h"
@@ -489,6 +491,61 @@ __device__ void plan_offsets(Bufs &b, int E) {
     if (threadIdx.x == 255) {
         b.cell_off[E] = ssum[255];
         b.ctr->total_cells = (uint64_t)ssum[255];
+    }
+}
+
+// ------------------------------------------------------------------ lpt
+// Work order of the persistent count pass (one block).  The work items are
+// the windows of sorted queries (each a run of cell blocks of one event).
+// A window's cost is estimated from its event's grid: points per cell times
+// the cells a work group scans, (R + 2m)(2m + 1)^(G-1).  Events are ranked
+// by decreasing cost (ties by index: longest processing time first), and
+// each of the 8 XCD queues takes an eighth of every event's windows in that
+// order, so each XCD's L2 sees contiguous windows and every queue starts
+// with the costliest work.
+__global__ void __launch_bounds__(256) k_lpt(Bufs b, Knobs kn) {
+    __shared__ float s_cost[kLptMaxEvents];
+    __shared__ uint32_t s_nwin[kLptMaxEvents], s_order[kLptMaxEvents];
+    if (b.bd->E > kLptMaxEvents) return;  // the host never launches it then
+    const BatchDesc &bd = *b.bd;
+    const int E = bd.E, t = threadIdx.x;
+    const uint32_t wpc = kChunkRows / kn.window;
+    uint32_t *order = b.lpt, *chunk0 = b.lpt + E, *nwin = b.lpt + 2 * E, *pre = b.lpt + 3 * E;
+    for (int e = t; e < E; e += blockDim.x) {
+        const GridDesc g = b.grid[e];
+        const int64_t np = b.ev[e].n_pts, nq = b.ev[e].n_q;
+        float nb = 1.0f;
+        for (int a = 0; a < g.G; ++a) nb *= (a == 0 ? (float)(kn.cells_per_item + 2 * g.m) : (float)(2 * g.m + 1));
+        s_cost[e] = g.G > 0 ? (float)np / (float)max(1u, g.C) * nb : (float)np;
+        s_nwin[e] = (uint32_t)((nq + kChunkRows - 1) / kChunkRows) * wpc;
+    }
+    __syncthreads();
+    for (int e = t; e < E; e += blockDim.x) {
+        const float c = s_cost[e];
+        int rank = 0;
+        for (int e2 = 0; e2 < E; ++e2) rank += (s_cost[e2] > c || (s_cost[e2] == c && e2 < e)) ? 1 : 0;
+        s_order[rank] = (uint32_t)e;
+    }
+    __syncthreads();
+    for (int e = t; e < E; e += blockDim.x) {
+        order[e] = s_order[e];
+        nwin[e] = s_nwin[e];
+    }
+    if (t == 8) {  // chunks of an event are contiguous, events in input order
+        uint32_t c = 0;
+        for (int e = 0; e < E; ++e) {
+            chunk0[e] = c;
+            c += s_nwin[e] / wpc;
+        }
+    }
+    if (t < 8) {
+        uint32_t acc = 0;
+        for (int k = 0; k < E; ++k) {
+            pre[t * (E + 1) + k] = acc;
+            const uint64_t n = s_nwin[s_order[k]];
+            acc += (uint32_t)(n * (t + 1) / 8 - n * t / 8);
+        }
+        pre[t * (E + 1) + E] = acc;
     }
 }
 
@@ -989,6 +1046,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
     const uint32_t nwin = (uint32_t)bd.n_qchunks * wpc;
     uint64_t my_cand = 0;
     uint32_t my_groups = 0;
+    uint32_t win_fill = 0;  // count pass: the window's fill work (long queries x candidates)
     bool more = false;  // count pass: the window holds a row longer than the stash
 
     auto process_window = [&](uint32_t wid) {
@@ -1254,39 +1312,63 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                     }
                 } else {
                     if (mine) b.deg[q_off + wperm] = cntv;
-                    more = more || ballot(mine && cntv > SC) != 0;
+                    const uint32_t nlong = (uint32_t)__popcll(ballot(mine && cntv > SC));
+                    more = more || nlong != 0;
+                    win_fill += nlong * total;
                     my_cand += (uint64_t)total * (uint64_t)(ge - gb);
                 }
             }
             wave_lds_sync();
         }
         if (!FILL && more) {
-            if (lane == 0) b.fill_list[atomicAdd(&b.ctr->n_fill, 1u)] = wid;
+            // the costlier windows from the front of the list, so that the
+            // fill pass starts them first (longest processing time first)
+            if (lane == 0) {
+                if (win_fill >= kFillHeavy)
+                    b.fill_list[atomicAdd(&b.ctr->n_fill, 1u)] = wid;
+                else
+                    b.fill_list[kn.fill_cap - 1u - atomicAdd(&b.ctr->n_fill_light, 1u)] = wid;
+            }
             more = false;
         }
+        win_fill = 0;
     };
 
     if constexpr (FILL) {
-        // the listed windows, grid-strided
-        const uint32_t n = b.ctr->n_fill;
-        const uint32_t nw = gridDim.x * kWavesPerBlock;
-        for (uint32_t i = blockIdx.x * kWavesPerBlock + w; i < n; i += nw) process_window(b.fill_list[i]);
+        // the listed windows: the heavier ones (front of the list) first,
+        // then the lighter ones (back of the list)
+        const uint32_t nh = b.ctr->n_fill, n = nh + b.ctr->n_fill_light;
+        auto listed = [&](uint32_t i) { return b.fill_list[i < nh ? i : kn.fill_cap - 1u - (i - nh)]; };
+        if constexpr (PERS) {
+            // persistent: the resident waves take the list round robin
+            // (heaviest first), without atomics
+            const uint32_t nw = gridDim.x * kWavesPerBlock;
+            for (uint32_t i = uniform(blockIdx.x * kWavesPerBlock + (uint32_t)w); i < n; i += nw)
+                process_window(listed(i));
+        } else {
+            const uint32_t nw = gridDim.x * kWavesPerBlock;
+            for (uint32_t i = blockIdx.x * kWavesPerBlock + w; i < n; i += nw) process_window(listed(i));
+        }
     } else if constexpr (PERS) {
-        const int x0 = blockIdx.x & 7;
-        for (int qx = 0; qx < 8; ++qx) {
-            const int x = (x0 + qx) & 7;
-            const uint32_t lo = (uint32_t)((uint64_t)nwin * x / 8);
-            const uint32_t hi = (uint32_t)((uint64_t)nwin * (x + 1) / 8);
-            uint32_t *head = &b.ctr->heads[x][0];
-            for (;;) {
-                // a plain read first: a drained queue needs no atomic
-                if (lo + uniform(__atomic_load_n(head, __ATOMIC_RELAXED)) >= hi) break;
-                uint32_t v = 0;
-                if (lane == 0) v = atomicAdd(head, 1u);
-                v = uniform((uint32_t)__shfl((int)v, 0));
-                if (lo + v >= hi) break;
-                process_window(lo + v);
-            }
+        // persistent: the resident waves of each XCD take its queue (built
+        // by k_lpt: costliest events first) round robin.  The queue is dealt
+        // statically: a shared counter per queue costs a device-scope atomic
+        // per window, and those on one address were measured to serialise
+        // at a few hundred nanoseconds each, slower than the whole pass
+        const BatchDesc &bdr = *b.bd;
+        const uint32_t E = (uint32_t)bdr.E;
+        const uint32_t x = blockIdx.x & 7;
+        const uint32_t wx = uniform((blockIdx.x >> 3) * kWavesPerBlock + (uint32_t)w);
+        const uint32_t Wx = (gridDim.x >> 3) * kWavesPerBlock;  // grid is a multiple of 8 blocks
+        const uint32_t *order = b.lpt, *chunk0 = b.lpt + E, *nwe = b.lpt + 2 * E;
+        const uint32_t *pre = b.lpt + 3 * E + x * (E + 1);
+        const uint32_t nx = pre[E];
+        uint32_t k = 0, kend = pre[1];
+        for (uint32_t v = wx; v < nx; v += Wx) {
+            while (kend <= v) kend = pre[++k + 1];
+            const uint32_t e = order[k];
+            const uint32_t we = (uint32_t)((uint64_t)nwe[e] * x / 8) + (v - pre[k]);
+            process_window(chunk0[e] * wpc + we);
         }
     } else {
         const uint32_t nb = gridDim.x, per = nb / 8;  // grid is a multiple of 8 blocks
@@ -1567,6 +1649,9 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
 __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
     __shared__ __align__(16) uint64_t sbuf[kWavesPerBlock][kRowLds];
     if (!out_fits(b)) return;
+    // the fill pass, which ran before this launch on the same stream, flags
+    // a row whose recount differs; the output carries the flag to the host
+    if (blockIdx.x == 0 && threadIdx.x == 0 && b.out->status) *b.out->status = b.ctr->status & kStatusInternal;
     const uint32_t n_long = b.ctr->n_long;
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
@@ -1709,6 +1794,37 @@ hipError_t launch_scan_rows(const Bufs &b, const Knobs &kn, int64_t total_q, hip
     return launch_scan_mode<kScanRows>(b, kn, total_q + 1, s);
 }
 
+// Resident blocks per CU of a kernel at its launch configuration (cached:
+// the query does not enqueue work, and is asked once per kernel and size).
+static int resident_blocks(const void *fn, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, size_t>, int> *cache = new std::map<std::pair<const void *, size_t>, int>();
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache->find({fn, lds});
+    if (it != cache->end()) return it->second;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 64 * kWavesPerBlock, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        n = 1;
+    }
+    n = std::max(1, n);
+    (*cache)[{fn, lds}] = n;
+    return n;
+}
+
+static int device_cus() {
+    static int cus = [] {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            n = 256;
+        }
+        return std::max(8, n);
+    }();
+    return cus;
+}
+
 template <bool FILL>
 static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
     blocks = (blocks + 7) / 8 * 8;  // whole XCD rounds (see the window remap)
@@ -1718,38 +1834,52 @@ static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int bloc
     // dynamic LDS: the query rows of a window per wave (rows padded to a
     // multiple of 4 floats)
     auto lds = [&](int dt) { return (size_t)kWavesPerBlock * kn.window * ((dt + 3) & ~3) * sizeof(float); };
+    // a persistent grid is at most what stays resident (the count pass
+    // assigns its queue statically, so a block started late would finish
+    // late): blocks (a multiple of 256 CUs) capped at the kernel's occupancy
+    auto launch = [&](auto kern, int dt, bool pers) {
+        const size_t l = lds(dt);
+        dim3 g = grid;
+        if (pers) {
+            const int cus = device_cus();
+            const int res = resident_blocks((const void *)kern, l);
+            const int per_cu = std::min(std::max(1, FILL ? res : blocks / cus), res);
+            g = dim3((unsigned)(per_cu * cus / 8 * 8));
+        }
+        hipLaunchKernelGGL(kern, g, block, l, s, b, kn);
+    };
     auto go = [&](auto pers, auto excl) {
         constexpr bool P = decltype(pers)::value, X = decltype(excl)::value;
         if constexpr (FILL) {
             switch (D) {
-            case 3: hipLaunchKernelGGL((k_query<3, true, true, false, X>), grid, block, lds(3), s, b, kn); break;
-            case 8: hipLaunchKernelGGL((k_query<8, true, true, false, X>), grid, block, lds(8), s, b, kn); break;
+            case 3: launch(k_query<3, true, true, P, X>, 3, P); break;
+            case 8: launch(k_query<8, true, true, P, X>, 8, P); break;
             case 12:  // the launch bound of 5 waves per SIMD, only without self-exclusion
                 if constexpr (X)
-                    hipLaunchKernelGGL((k_query<12, true, true, false, X>), grid, block, lds(12), s, b, kn);
+                    launch(k_query<12, true, true, P, X>, 12, P);
                 else
-                    hipLaunchKernelGGL((k_query_o5<12, true, true, false, X>), grid, block, lds(12), s, b, kn);
+                    launch(k_query_o5<12, true, true, P, X>, 12, P);
                 break;
             default:
                 if (D <= 4)
-                    hipLaunchKernelGGL((k_query<4, false, true, false, X>), grid, block, lds(4), s, b, kn);
+                    launch(k_query<4, false, true, P, X>, 4, P);
                 else if (D <= 16)
-                    hipLaunchKernelGGL((k_query<16, false, true, false, X>), grid, block, lds(16), s, b, kn);
+                    launch(k_query<16, false, true, P, X>, 16, P);
                 else
-                    hipLaunchKernelGGL((k_query<32, false, true, false, X>), grid, block, lds(32), s, b, kn);
+                    launch(k_query<32, false, true, P, X>, 32, P);
             }
         } else {
             switch (D) {
-            case 3: hipLaunchKernelGGL((k_query<3, true, false, P, X>), grid, block, lds(3), s, b, kn); break;
-            case 8: hipLaunchKernelGGL((k_query_o5<8, true, false, P, X>), grid, block, lds(8), s, b, kn); break;
-            case 12: hipLaunchKernelGGL((k_query_o5<12, true, false, P, X>), grid, block, lds(12), s, b, kn); break;
+            case 3: launch(k_query<3, true, false, P, X>, 3, P); break;
+            case 8: launch(k_query_o5<8, true, false, P, X>, 8, P); break;
+            case 12: launch(k_query_o5<12, true, false, P, X>, 12, P); break;
             default:
                 if (D <= 4)
-                    hipLaunchKernelGGL((k_query<4, false, false, P, X>), grid, block, lds(4), s, b, kn);
+                    launch(k_query<4, false, false, P, X>, 4, P);
                 else if (D <= 16)
-                    hipLaunchKernelGGL((k_query<16, false, false, P, X>), grid, block, lds(16), s, b, kn);
+                    launch(k_query<16, false, false, P, X>, 16, P);
                 else
-                    hipLaunchKernelGGL((k_query<32, false, false, P, X>), grid, block, lds(32), s, b, kn);
+                    launch(k_query<32, false, false, P, X>, 32, P);
             }
         }
     };
@@ -1759,13 +1889,29 @@ static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int bloc
         else
             go(pers, std::false_type{});
     };
-    // the fill pass always strides over its window list
-    if (!FILL && kn.persistent)
+    if (kn.persistent)
         go_x(std::true_type{});
     else
         go_x(std::false_type{});
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
+}
+
+int count_resident_blocks(const Knobs &kn, int D) {
+    // the count kernel of this D at its launch configuration, persistent
+    // flavour (the same registers as the plain one within a few)
+    const size_t l = (size_t)kWavesPerBlock * kn.window * ((std::min(D, 32) + 3) & ~3) * sizeof(float);
+    const void *fn;
+    switch (D) {
+    case 3: fn = (const void *)k_query<3, true, false, true, false>; break;
+    case 8: fn = (const void *)k_query_o5<8, true, false, true, false>; break;
+    case 12: fn = (const void *)k_query_o5<12, true, false, true, false>; break;
+    default:
+        fn = D <= 4 ? (const void *)k_query<4, false, false, true, false>
+                    : D <= 16 ? (const void *)k_query<16, false, false, true, false>
+                              : (const void *)k_query<32, false, false, true, false>;
+    }
+    return resident_blocks(fn, l) * device_cus();
 }
 
 hipError_t launch_count(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s) {
@@ -1794,6 +1940,12 @@ hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipSt
 
 hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_long_sort, dim3(std::max(1, blocks)), dim3(256), 0, s, b, kn);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_lpt(const Bufs &b, const Knobs &kn, hipStream_t s) {
+    hipLaunchKernelGGL(k_lpt, dim3(1), dim3(256), 0, s, b, kn);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -31,6 +31,10 @@ hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipSt
 // the windows listed by the count pass; any grid size is correct
 hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
 hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStream_t s);
+// blocks of the persistent count kernel resident on the whole device
+int count_resident_blocks(const Knobs &kn, int D);
+// work order of the persistent count pass (needs the grids and b.lpt)
+hipError_t launch_lpt(const Bufs &b, const Knobs &kn, hipStream_t s);
 hipError_t launch_set_out(const Bufs &b, const OutDesc &v, hipStream_t s);
 
 }  // namespace frnn

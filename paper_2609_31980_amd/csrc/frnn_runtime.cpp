@@ -36,6 +36,15 @@ float r2_of(float r) {
     return rr;
 }
 
+frnn_status OutputOwner::check(hipStream_t s) {
+    if (!long_ran || !status) return FRNN_OK;
+    uint32_t v = 0;
+    FRNN_HIP(hipMemcpyAsync(&v, status, sizeof(v), hipMemcpyDeviceToHost, s));
+    FRNN_HIP(hipStreamSynchronize(s));
+    if (v & kStatusInternal) return fail(FRNN_ERR_INTERNAL, "the fill pass recounted a row differently");
+    return FRNN_OK;
+}
+
 // ------------------------------------------------------------------- pool
 Pool &Pool::get() {
     static Pool *p = new Pool();  // never destroyed: blocks live to exit
@@ -302,6 +311,7 @@ frnn_status Opts::validate(std::string *why) const {
     if (o.queries_per_item < 1 || o.queries_per_item > 64 || (o.queries_per_item & (o.queries_per_item - 1)))
         return bad("queries_per_item must be a power of two in 1..64");
     if (o.blocks_per_cu < 1 || o.blocks_per_cu > 16) return bad("blocks_per_cu out of 1..16");
+    if (o.persistent < 0 || o.persistent > 2) return bad("persistent must be 0, 1 or 2");
     if (o.row_cap_lds < 1 || o.row_cap_lds > kRowLds) return bad("row_cap_lds out of 1..512");
     if (o.stash_cap != 0 && o.stash_cap != 8 && o.stash_cap != 16 && o.stash_cap != 32 && o.stash_cap != 64 &&
         o.stash_cap != 128)
@@ -342,10 +352,23 @@ int fill_blocks(int64_t windows) {
 
 // Workgroups of the count kernel: the resident grid when persistent, else
 // one wave per window of sorted queries.
-int query_blocks(const frnn_opts &o, int64_t nqchunks) {
-    if (o.persistent) return 256 * o.blocks_per_cu;
+int query_blocks(const frnn_opts &o, int64_t nqchunks, bool persistent) {
+    if (persistent) return 256 * o.blocks_per_cu;
     const int64_t windows = nqchunks * (kChunkRows / o.queries_per_item);
     return (int)std::max<int64_t>(8, (windows + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+
+// Whether the count and fill passes run persistent.  Automatic: when the
+// windows are at most twice the waves that stay resident (a single event of
+// a few hundred thousand queries), where the dealt queue measured faster
+// than the hardware's dispatch of one block per four windows; with many
+// windows per wave (a large batch) the dealt queue's tail measured longer.
+bool use_persistent(const frnn_opts &o, int E, int64_t nqchunks, const Knobs &kn, int D) {
+    if (o.persistent == 0 || E > kLptMaxEvents) return false;
+    if (o.persistent == 1) return true;
+    const int64_t windows = nqchunks * (kChunkRows / o.queries_per_item);
+    const int64_t waves = (int64_t)std::min(count_resident_blocks(kn, D), 256 * o.blocks_per_cu) * kWavesPerBlock;
+    return windows <= 2 * waves;
 }
 
 frnn_status build_index(Index &ix, const float *const *points, const int64_t *n, int E, int D,
@@ -507,7 +530,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
         part(sizeof(uint64_t) * 2 * kScanBlocks, s),
         stash(sizeof(uint64_t) * tq1 * std::max(1, op.o.stash_cap), s),
         flist(sizeof(uint32_t) * std::max<int64_t>(1, (int64_t)nqc * (kChunkRows / op.o.queries_per_item)), s),
-        outd(sizeof(OutDesc), s);
+        outd(sizeof(OutDesc), s), lpt(sizeof(uint32_t) * lpt_words(E), s);
     DevBuf qs, qperm, qkey, qrank, sqkey, qcells;
     if (!selfq) {
         qs.reset(sizeof(float) * tq1 * Dp, s);
@@ -547,6 +570,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     b.long_at = lat.as<int64_t>();
     b.stash = stash.as<uint64_t>();
     b.fill_list = flist.as<uint32_t>();
+    b.lpt = lpt.as<uint32_t>();
     b.scan_part = part.as<uint64_t>();
     b.out = outd.as<OutDesc>();
 
@@ -558,9 +582,10 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     kn.window = op.o.queries_per_item;
     kn.cells_per_item = op.o.cells_per_item;
     kn.long_cap = op.o.row_cap_lds;
-    kn.persistent = op.o.persistent;
     kn.stash_cap = op.o.stash_cap;
-    const int qblocks = query_blocks(op.o, nqc);
+    kn.fill_cap = (uint32_t)std::max<int64_t>(1, (int64_t)nqc * (kChunkRows / op.o.queries_per_item));
+    kn.persistent = use_persistent(op.o, E, nqc, kn, D);
+    const int qblocks = query_blocks(op.o, nqc, kn.persistent);
 
     LAUNCH("init", s, launch_init(b, s));
     if (!selfq) {
@@ -569,6 +594,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
         LAUNCH("scan_cells_q", s, launch_scan_cells(b, ix.cells_cap, true, s));
         LAUNCH("scatter_q", s, launch_scatter(b, nqc, true, s));
     }
+    if (kn.persistent) LAUNCH("lpt", s, launch_lpt(b, kn, s));
     LAUNCH("count", s, launch_count(b, kn, D, qblocks, s));
     LAUNCH("scan_rows", s, launch_scan_rows(b, kn, totq, s));
 
@@ -596,20 +622,25 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     const size_t b_idx = (sizeof(int32_t) * nnz + 255) / 256 * 256;
     const size_t b_d2 = want_d2 ? sizeof(float) * nnz : 0;
     try {
-        own->buf.reset(b_off + b_idx + b_d2, s);
+        own->buf.reset(b_off + b_idx + (b_d2 + 15) / 16 * 16 + 16, s);
     } catch (...) {
         delete own;
         throw;
     }
     char *ob = own->buf.as<char>();
+    own->status = reinterpret_cast<uint32_t *>(ob + b_off + b_idx + b_d2);
     DevBuf lkeys(sizeof(uint64_t) * std::max<uint64_t>(1, c.long_total), s);
     OutDesc od{reinterpret_cast<int64_t *>(ob), reinterpret_cast<int32_t *>(ob + b_off),
                want_d2 ? reinterpret_cast<float *>(ob + b_off + b_idx) : nullptr, lkeys.as<uint64_t>(),
-               nnz, (int64_t)c.long_total};
+               nnz, (int64_t)c.long_total, own->status};
     LAUNCH("set_out", s, launch_set_out(b, od, s));
     LAUNCH("short_rows", s, launch_short_rows(b, kn, nqc, s));
-    if (c.n_fill) LAUNCH("fill", s, launch_fill(b, kn, D, fill_blocks(c.n_fill), s));
-    if (c.long_total) LAUNCH("long_sort", s, launch_long_sort(b, kn, 1536, s));
+    const uint32_t n_fill = c.n_fill + c.n_fill_light;
+    if (n_fill) LAUNCH("fill", s, launch_fill(b, kn, D, fill_blocks(n_fill), s));
+    if (c.long_total) {
+        LAUNCH("long_sort", s, launch_long_sort(b, kn, 1536, s));
+        own->long_ran = true;
+    }
 
     own->refs = E;
     for (int e = 0; e < E; ++e) {

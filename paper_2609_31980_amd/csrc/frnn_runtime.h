@@ -172,8 +172,13 @@ struct Index {
 };
 
 struct OutputOwner {
-    DevBuf buf;                     // offsets | indices | dist2
+    DevBuf buf;                     // offsets | indices | dist2 | status word
     std::atomic<int> refs{0};
+    uint32_t *status = nullptr;     // device word written by the long-row pass
+    bool long_ran = false;          // the long-row pass wrote into this output
+    // Reads the status word when the long-row pass ran (synchronises s):
+    // FRNN_ERR_INTERNAL when the fill's recount of a row differed.
+    frnn_status check(hipStream_t s);
     std::function<void()> on_release;  // e.g. return the bytes to a budget
     ~OutputOwner() {
         if (on_release) on_release();
@@ -206,7 +211,8 @@ void prof_set(bool on);
 int prof_read(frnn_kernel_time *out, int cap, bool reset);
 
 float r2_of(float r);
-int query_blocks(const frnn_opts &o, int64_t nqchunks);
+int query_blocks(const frnn_opts &o, int64_t nqchunks, bool persistent);
+bool use_persistent(const frnn_opts &o, int E, int64_t nqchunks, const Knobs &kn, int D);
 // grid of the fill pass over `windows` listed windows (it strides past 4096 blocks)
 int fill_blocks(int64_t windows);
 

@@ -157,6 +157,7 @@ void frnn_server_s::worker(int id) {
                 bo.own->on_release = [bud, outb]() { bud->release(outb); };
                 try {
                     ctx->phase_b(bo.od, c.ctr.long_total > 0, s);
+                    bo.own->long_ran = c.ctr.long_total > 0;
                 } catch (...) {
                     delete bo.own;  // returns the reservation
                     throw;
