@@ -224,6 +224,32 @@ frnn_status frnn_edges_copy(const frnn_edges *edges, int32_t *src, int32_t *dst,
 /* Return an edge list's buffers to the library's pool; the struct is zeroed. */
 void frnn_edges_release(frnn_edges *edges);
 
+/* ------------------------------------------------- no device allocation
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid allocation): the single-event self-query of
+ * frnn_query_batch (FRNN_SELF_QUERY required) with every work buffer taken
+ * from one device array of FRNN_NOALLOC_SCRATCH_BYTES that the library holds
+ * on each GPU it runs on until the process ends, and the output written into
+ * caller buffers.  The call makes no device (or pinned host) allocation.
+ *   points   device [N][D] float32, read during the call's stream work
+ *   offsets  device int64 [N+1] (caller-owned)
+ *   indices  device int32 [cap_pairs], dist2 device float32 [cap_pairs] (or
+ *            NULL without FRNN_WANT_DIST2); the CSR is that of
+ *            frnn_query_batch, bit for bit
+ *   *nnz     host: the number of pairs (also on FRNN_ERR_BUDGET)
+ * Synchronises the stream once (after counting); the outputs are complete
+ * when the stream's work is.  Errors: INVALID_ARG (also when the event's
+ * work buffers exceed the array: about 4*ceil(D/4)*4 + 8*stash_cap + 70 bytes
+ * per point), NONFINITE, BUDGET (cap_pairs below the pair count, or the
+ * rows longer than the stash exceed the rest of the array), HIP.  Calls on
+ * one GPU share its array: calls that overlap in time race and must be
+ * ordered by the caller. */
+#define FRNN_NOALLOC_SCRATCH_BYTES (256LL << 20)
+
+frnn_status frnn_query_noalloc(const float *points, int64_t N, int32_t D, float r, int32_t K,
+                               uint32_t flags, const frnn_opts *opts, int64_t *offsets, int32_t *indices,
+                               float *dist2, int64_t cap_pairs, int64_t *nnz, void *stream);
+
 /* ---------------------------------------------------------------- serving
  * A request loop on its own host thread and streams.  Submitted events are
  * admitted against an HBM budget, batched with whatever else is queued into

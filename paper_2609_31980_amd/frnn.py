@@ -133,6 +133,7 @@ def _load():
         "frnn_status_str": (ctypes.c_char_p, [i32]),
         "frnn_last_error": (ctypes.c_char_p, []),
         "frnn_test_fail_alloc_after": (None, [i64]),
+        "frnn_query_noalloc": (i32, [vp, i64, i32, f32, i32, u32, P(Opts), vp, vp, vp, i64, P(i64), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -426,6 +427,39 @@ def query_batch(points: list, r: float, K: int = 0, queries: list | None = None,
                                  _stream(stream), outs))
     keep = (points, queries)
     return [CSR(outs[e], keep=keep) for e in range(E)]
+
+
+def query_noalloc(points, r: float, K: int, offsets, indices, dist2=None, exclude_self: bool = False,
+                  opts: Opts | None = None, stream=None) -> int:
+    """Self-query of one event with no device allocation by the library
+    (frnn_query_noalloc): writes the CSR into the caller's tensors (offsets
+    int64 [N+1], indices int32 [cap], dist2 float32 [cap] or None) and
+    returns the pair count.  A FrnnError of status BUDGET carries the
+    needed capacity as `.nnz`."""
+    import torch
+    n = int(points.shape[0])
+    for t, dt, what in ((offsets, torch.int64, "offsets"), (indices, torch.int32, "indices"),
+                        (dist2, torch.float32, "dist2")):
+        if t is not None and (not t.is_cuda or t.dtype != dt or not t.is_contiguous()):
+            raise TypeError(f"{what} must be a contiguous CUDA {dt} tensor")
+    if offsets.numel() != n + 1:
+        raise ValueError("offsets must hold N + 1 entries")
+    cap = int(indices.numel())
+    if dist2 is not None and dist2.numel() < cap:
+        raise ValueError("dist2 must hold as many entries as indices")
+    flags = SELF_QUERY | (WANT_DIST2 if dist2 is not None else 0) | (EXCLUDE_SELF if exclude_self else 0)
+    nnz = ctypes.c_int64(0)
+    st = _lib.frnn_query_noalloc(_pts(points), n, int(points.shape[1]), float(np.float32(r)), int(K), flags,
+                                 ctypes.byref(opts) if opts is not None else None,
+                                 ctypes.c_void_p(offsets.data_ptr()),
+                                 ctypes.c_void_p(indices.data_ptr() if cap else 0),
+                                 ctypes.c_void_p(dist2.data_ptr() if dist2 is not None and cap else 0),
+                                 cap, ctypes.byref(nnz), _stream(stream))
+    if st != 0:
+        e = FrnnError(st, (_lib.frnn_last_error() or b"").decode())
+        e.nnz = int(nnz.value)
+        raise e
+    return int(nnz.value)
 
 
 # ------------------------------------------------------------- serving
