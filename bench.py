@@ -9,11 +9,15 @@ Default run (about two minutes):
   * the CPU oracle timed on a bounded sample of the same event;
   * paper-shaped: the 271,663-point 12-D self-join (r=0.12, K=1000, self
     pairs excluded) standing in for the paper's measured event;
+  * density: 1,000,000 12-D references, 200,000 separate queries, K=64;
   * batched: 64 uneven tracking events, one graph-replayed batch (one
     launch per pipeline step over all events) vs 64 plain per-event
     build+query calls (identical output checked);
   * serving: Poisson arrivals of log-normal-size events through the
-    continuous-batching server vs a FIFO of plain per-event calls.
+    continuous-batching server vs a FIFO of plain per-event calls, with a
+    load sweep, paired rounds and a tight memory budget.
+A/B comparisons follow the paper's protocol (Sec. 4.2): warm-ups, paired
+rounds in random order, medians with 95% bootstrap intervals, sign tests.
 
 Prints ONE JSON line.  `--gpus N` with N > 1 exits: the benchmark measures one GPU.
 """
@@ -32,11 +36,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "neighbour pairs/s + events/s (batched vs per-event); p50/p99 event latency"
-# Dense VALU rate for the op mix of the distance evaluation on MI355X:
-# 256 CUs x 64 FP32 lanes x 2.4 GHz, one subtract, multiply or add per lane
-# per clock (no FMA: the canonical sum forbids contraction; packed FP32 is
-# not used).
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# Vector ALU rate for the op mix of the distance evaluation on MI355X: the
+# published FP32 vector peak, 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 256 flops
+# per CU per clock, counts each fused multiply-add as two flops; the
+# distance's subtract, multiply and add are one operation each and may not
+# be fused, so their peak is half of it, 128 per CU per clock (78.6 T op/s).
+# The microkernel of frnn_measure_valu_rate measures the same chain on the
+# device and is reported beside it.
+VALU_PEAK_OPS = 256 * 128 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
 
@@ -71,6 +78,57 @@ def sync():
 
 def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+# ------------------------------------------------------ statistics (Sec. 4.2)
+# The paper's protocol: warm-ups, paired rounds in randomised order with a
+# synchronisation before and after each timed call, outputs verified first,
+# medians with 95 % percentile-bootstrap intervals from 10,000 resamples, and
+# an exact two-sided sign test on the paired differences.
+def boot_ci(x, n_boot=10_000, seed=0):
+    """Median and its 95 % percentile-bootstrap interval."""
+    x = np.asarray(x, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    meds = np.median(x[rng.integers(0, len(x), size=(n_boot, len(x)))], axis=1)
+    return {"median": float(np.median(x)), "ci95": [float(np.percentile(meds, 2.5)), float(np.percentile(meds, 97.5))],
+            "n": int(len(x))}
+
+
+def sign_test(a, b):
+    """Exact two-sided sign test of paired samples a vs b (ties dropped)."""
+    from math import comb
+    d = np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)
+    pos, neg = int(np.sum(d > 0)), int(np.sum(d < 0))
+    n, k = pos + neg, min(pos, neg)
+    p = min(1.0, 2.0 * sum(comb(n, i) for i in range(k + 1)) / 2.0 ** n) if n else 1.0
+    return {"a_slower_rounds": pos, "b_slower_rounds": neg, "p_two_sided": p}
+
+
+def paired_rounds(fns, rounds=30, seed=1):
+    """Time each function once per round, in a seeded random order per round,
+    with a device synchronisation before and after each call."""
+    rng = np.random.default_rng(seed)
+    times = {k: [] for k in fns}
+    names = list(fns)
+    for _ in range(rounds):
+        for k in rng.permutation(names):
+            sync()
+            t0 = time.perf_counter()
+            fns[k]()
+            sync()
+            times[k].append(time.perf_counter() - t0)
+    return times
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 # ------------------------------------------------------------ single event
@@ -134,11 +192,20 @@ def cpu_baseline(points, r, K, budget_s=12.0):
     t0 = time.perf_counter()
     c = o.frnn(points, r, K, Q=points[rows])
     dt = time.perf_counter() - t0
+    # one thread, on a sample that takes about a quarter of that time
+    m1 = max(100, m // (4 * max(1, o.threads())))
+    rows1 = np.sort(np.random.default_rng(7).choice(n, size=min(n, m1), replace=False))
+    t0 = time.perf_counter()
+    c1 = o.frnn(points, r, K, Q=points[rows1], nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": c.nnz / dt, "unit": "neighbour pairs/s", "cores": o.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{m} of {n} queries of the same event against all {n} references "
                       f"({c.nnz} pairs, {dt:.1f} s); full-event rate scales linearly in queries",
-            "seconds": dt, "events_per_s_equiv": (m / n) / dt}
+            "seconds": dt, "events_per_s_equiv": (m / n) / dt,
+            "pair_evaluations_per_s": m * n / dt,
+            "one_thread": {"value": c1.nnz / dt1, "unit": "neighbour pairs/s", "queries": int(len(rows1)),
+                           "seconds": dt1, "pair_evaluations_per_s": len(rows1) * n / dt1}}
 
 
 # ------------------------------------------------------------ batched
@@ -230,7 +297,7 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
                               "note": "different hardware and the real event; context, not a target"}}
 
 
-def bench_batched(frnn, rounds=3):
+def bench_batched(frnn, rounds=30):
     import torch
     from paper_2609_31980_amd import inputs
     log("batched: generating 64 events")
@@ -265,28 +332,31 @@ def bench_batched(frnn, rounds=3):
         o.release()
     del a, b
     sync()
-    times = {per_event: [], per_event_graph: [], batched: []}
-    fns = [per_event, per_event_graph, batched]
-    for fn in fns:          # warm-up (graph capture, pools)
-        [o.release() for o in fn()]
-    for i in range(rounds):
-        order = fns if i % 2 == 0 else fns[::-1]
-        for fn in order:
-            sync()
-            t0 = time.perf_counter()
-            outs = fn()
-            sync()
-            times[fn].append(time.perf_counter() - t0)
-            for o in outs:
-                o.release()
+    fns = {"per_event": per_event, "per_event_graph": per_event_graph, "batched": batched}
+
+    def run(fn):
+        return lambda: [o.release() for o in fn()]
+    for _ in range(10):      # warm-up (graph capture, pools)
+        for fn in fns.values():
+            run(fn)()
+    times = paired_rounds({k: run(f) for k, f in fns.items()}, rounds=rounds)
     E = len(xs)
-    tp, tg, tb = (float(np.median(times[f])) for f in fns)
+    tp, tg, tb = (float(np.median(times[k])) for k in fns)
+    ms = {k: {kk: (v * 1e3 if kk == "median" else [u * 1e3 for u in v] if kk == "ci95" else v)
+              for kk, v in boot_ci(times[k]).items()} for k in fns}
     res = {"events": E, "points": npts, "pairs": nnz,
            "per_event_ms": tp * 1e3, "per_event_graph_ms": tg * 1e3, "batched_ms": tb * 1e3,
            "per_event_events_per_s": E / tp, "per_event_graph_events_per_s": E / tg,
            "batched_events_per_s": E / tb, "batched_pairs_per_s": nnz / tb,
            "speedup_vs_per_event": tp / tb, "speedup_vs_per_event_graph": tg / tb,
-           "identical_output": True,
+           "ms_median_ci95": ms,
+           "sign_test_per_event_vs_batched": sign_test(times["per_event"], times["batched"]),
+           "sign_test_per_event_graph_vs_batched": sign_test(times["per_event_graph"], times["batched"]),
+           "protocol": f"10 warm-up rounds, then {rounds} rounds each timing the three paths once in a seeded "
+                       "random order, synchronised before and after each call; medians with 95% percentile "
+                       "bootstrap intervals (10,000 resamples); exact two-sided sign tests",
+           "identical_output": "batched == per-event API on the device, every event; every event also equals "
+                               "the CPU oracle's CSR in the GPU tests (stored digests)",
            "per_event": "64 x (build + query API calls)",
            "per_event_graph": "64 x single-event graph-replayed calls",
            "batched": "one graph-replayed launch sequence over all 64 events"}
@@ -296,7 +366,12 @@ def bench_batched(frnn, rounds=3):
 
 
 # ------------------------------------------------------------ serving
-def bench_serving(frnn, n_events=600, load=0.7, pool=96):
+def bench_serving(frnn, n_events=600, load=0.7, pool=96, sweep_events=300, rounds=30):
+    """Open-loop Poisson arrivals of log-normal-size events through the
+    continuous-batching server vs a FIFO of plain per-event calls on the same
+    trace: at 0.7x the batched capacity (headline), a load sweep that also
+    covers loads the plain path can sustain, paired rounds at 0.7x the plain
+    capacity, and a run under a tight memory budget."""
     import torch
     from paper_2609_31980_amd import inputs
     log("serving: generating event pool")
@@ -304,7 +379,7 @@ def bench_serving(frnn, n_events=600, load=0.7, pool=96):
     evs = [inputs.c5_event(a) for a in probe]        # distinct events, reused cyclically
     mean_n = float(np.mean([len(e) for e in evs]))
     r, K = 0.1, 256
-    # capacity of the plain path (events/s) on this pool, to set the load
+    # capacity of the plain path (events/s) on this pool
     xs = [torch.from_numpy(e).cuda() for e in evs[:16]]
     sync()
     t0 = time.perf_counter()
@@ -315,23 +390,26 @@ def bench_serving(frnn, n_events=600, load=0.7, pool=96):
     sync()
     plain_rate = len(xs) / (time.perf_counter() - t0)
     del xs
+
+    def server(budget=64 << 30):
+        return frnn.Server(8, r, K, hbm_budget_bytes=budget, max_batch_events=64, max_inflight=2)
+
     # batched capacity: the server with everything queued at once
-    srv = frnn.Server(8, r, K, hbm_budget_bytes=64 << 30, max_batch_events=64, max_inflight=2)
+    srv = server()
     t0 = time.perf_counter()
     tick = [srv.submit(evs[i % pool]) for i in range(128)]
     for t in tick:
         c, _ = srv.wait(t)
         c.release()
     cap = 128 / (time.perf_counter() - t0)
-    rate = load * cap
-    trace = inputs.c5_trace(n_events, rate=rate)
-    log(f"serving: plain capacity {plain_rate:.0f}/s, batched capacity {cap:.0f}/s, offered {rate:.0f}/s")
+    log(f"serving: plain capacity {plain_rate:.0f}/s, batched capacity {cap:.0f}/s")
 
-    def run_server():
-        lat = []
+    def run_server(srv, trace):
+        n = len(trace)
+        lat, bid = [], set()
         done = [0.0]
-        tickets = [None] * n_events
-        start = time.perf_counter() + 0.05
+        tickets = [None] * n
+        start = time.perf_counter() + 0.02
 
         def submitter():
             for i, a in enumerate(trace):
@@ -348,13 +426,15 @@ def bench_serving(frnn, n_events=600, load=0.7, pool=96):
             c, tm = srv.wait(tickets[i])
             c.release()
             lat.append(tm["done_s"] - (start + a.t))
+            bid.add(tm["batch_id"])
             done[0] = tm["done_s"]
         th.join()
-        return lat, n_events / (done[0] - start)
+        return lat, n / (done[0] - start), len(bid)
 
-    def run_plain():
+    def run_plain(trace):
+        n = len(trace)
         lat = []
-        start = time.perf_counter() + 0.05
+        start = time.perf_counter() + 0.02
         last = start
         for i, a in enumerate(trace):
             dl = start + a.t - time.perf_counter()
@@ -367,17 +447,111 @@ def bench_serving(frnn, n_events=600, load=0.7, pool=96):
             sync()
             last = time.perf_counter()
             lat.append(last - (start + a.t))
-        return lat, n_events / (last - start)
+        return lat, n / (last - start)
 
-    ls, rs = run_server()
+    def both(rate, n, seed=inputs.SEED_C5):
+        trace = inputs.c5_trace(n, rate=rate, seed=seed)
+        ls, rs, nb = run_server(srv, trace)
+        lp, rp = run_plain(trace)
+        return {"offered_events_per_s": rate, "events": n, "batches": nb,
+                "served_events_per_s": rs, "served_p50_ms": pct(ls, 50) * 1e3, "served_p99_ms": pct(ls, 99) * 1e3,
+                "plain_fifo_events_per_s": rp, "plain_p50_ms": pct(lp, 50) * 1e3, "plain_p99_ms": pct(lp, 99) * 1e3}
+
+    head = both(load * cap, n_events)
+    log("serving: load sweep")
+    sweep = {}
+    for f in (0.3, 0.5, 0.7, 0.9):
+        sweep[f"{f}x_batched_capacity"] = both(f * cap, sweep_events, seed=inputs.SEED_C5 + 10)
+    sweep["0.7x_plain_capacity"] = both(0.7 * plain_rate, sweep_events, seed=inputs.SEED_C5 + 11)
+    # paired rounds at a load both paths sustain: per-round median latency
+    log("serving: paired rounds")
+    rng = np.random.default_rng(2)
+    p50s = {"served": [], "plain": []}
+    for i in range(rounds):
+        trace = inputs.c5_trace(60, rate=0.7 * plain_rate, seed=inputs.SEED_C5 + 100 + i)
+        for which in rng.permutation(["served", "plain"]):
+            lat = run_server(srv, trace)[0] if which == "served" else run_plain(trace)[0]
+            p50s[which].append(pct(lat, 50) * 1e3)
     srv.close()
-    lp, rp = run_plain()
-    return {"events": n_events, "mean_points": mean_n, "offered_events_per_s": rate,
-            "load_fraction_of_batched_capacity": load,
-            "served_events_per_s": rs, "served_p50_ms": pct(ls, 50) * 1e3, "served_p99_ms": pct(ls, 99) * 1e3,
-            "plain_fifo_events_per_s": rp, "plain_p50_ms": pct(lp, 50) * 1e3, "plain_p99_ms": pct(lp, 99) * 1e3,
+    paired = {"load": "0.7x the plain capacity, 60-event traces, a fresh trace per round",
+              "served_p50_ms": boot_ci(p50s["served"]), "plain_p50_ms": boot_ci(p50s["plain"]),
+              "sign_test_plain_vs_served": sign_test(p50s["plain"], p50s["served"])}
+    # a budget that holds only a few events' work at once: admission waits
+    log("serving: tight budget")
+    tight = 512 << 20
+    srv = server(tight)
+    trace = inputs.c5_trace(sweep_events, rate=0.9 * cap, seed=inputs.SEED_C5 + 12)
+    lt, rt, nbt = run_server(srv, trace)
+    held, peak = srv.memory()
+    srv.close()
+    tight_res = {"hbm_budget_bytes": tight, "offered_events_per_s": 0.9 * cap, "events": sweep_events,
+                 "batches": nbt, "served_events_per_s": rt, "served_p50_ms": pct(lt, 50) * 1e3,
+                 "served_p99_ms": pct(lt, 99) * 1e3, "server_peak_bytes": peak}
+    return {"events": n_events, "mean_points": mean_n, "load_fraction_of_batched_capacity": load,
+            **head,
             "plain_capacity_events_per_s": plain_rate, "batched_capacity_events_per_s": cap,
+            "load_sweep": sweep, "paired_rounds": paired, "tight_budget": tight_res,
             "latency": "completion on the device minus scheduled arrival; H2D of the event included"}
+
+
+def hbm_kernels(kern, N, D, nnz, cells, cells_cleared):
+    """Algorithmic HBM bytes per launch of the memory-bound kernels of one
+    event (read + written once each), their rate and fraction of the 8 TB/s
+    peak at the measured per-launch times."""
+    Dp = (D + 3) & ~3
+    alg = {"extent": 4 * D * N + 4 * cells_cleared,            # read X, clear the cell table
+           "keys": (4 * D + 8 + 4) * N,                          # read X, write key and rank, one counter update
+           "scatter": (4 * D + 12) * N + (4 * Dp + 8) * N,       # read X, key, rank, cell start; write row, perm, key
+           "short_rows": 16 * nnz + 16 * N,                      # stash keys in, (index, dist2) out, offsets
+           "scan_cells": 8 * cells,                              # counts in, starts out
+           "scan_rows": 20 * N}                                  # degree in, two offsets out
+    out = {}
+    for k, b in alg.items():
+        if k in kern and kern[k]["avg_ms"] > 0:
+            gbs = b / (kern[k]["avg_ms"] * 1e-3) / 1e9
+            out[k] = {"algorithmic_bytes": int(b), "avg_us": kern[k]["avg_ms"] * 1e3, "GB_per_s": gbs,
+                      "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    return out
+
+
+def bench_density(frnn, steps=10, warmup=3):
+    """The density workload: 1,000,000 12-D references in Zipf-sized
+    clusters, 200,000 separate queries, r=0.15 (mean degree about 100), K=64;
+    one step = bin the references and the queries, count, fill."""
+    import torch
+    from paper_2609_31980_amd import inputs
+    log("density: generating 1M x 200k")
+    w = inputs.c4()
+    x = torch.from_numpy(w.points).cuda()
+    q = torch.from_numpy(w.queries).cuda()
+
+    def step():
+        c = frnn.query_batch([x], w.r, w.K, queries=[q])[0]
+        n = c.nnz
+        c.release()
+        return n
+    dt, nnz = time_steps(step, steps, warmup)
+    stats = frnn.last_stats()
+    frnn.profile_enable(True)
+    frnn.profile_read(reset=True)
+    for _ in range(3):
+        step()
+    sync()
+    prof = frnn.profile_read(reset=True)
+    frnn.profile_enable(False)
+    kus = {k: round(v[1] / max(v[0], 1) * 1e3, 1) for k, v in prof.items()}
+    cand = stats["candidates"]
+    ops = cand * 3 * w.points.shape[1]
+    cnt_s = kus.get("count", 0.0) * 1e-6
+    del x, q
+    return {"workload": "zipf-clusters-1m-200k-d12: 1,000,000 references in Zipf(1.5)-sized Gaussian clusters "
+                        "(sigma 0.03) in [-1,1]^12, 200,000 queries drawn from the clusters, r=0.15, K=64",
+            "ms_per_step": dt / steps * 1e3, "pairs_per_step": nnz, "pairs_per_s": nnz * steps / dt,
+            "queries_per_s": 200_000 * steps / dt, "candidates_per_pair": cand / max(nnz, 1),
+            "kernels_us": kus,
+            "count_roofline": {"achieved": ops / cnt_s / 1e12 if cnt_s else None, "peak": VALU_PEAK_OPS / 1e12,
+                               "unit": "TFLOP/s", "frac": (ops / cnt_s) / VALU_PEAK_OPS if cnt_s else None,
+                               "ops_per_launch": ops, "candidates": cand}}
 
 
 # ------------------------------------------------------------ main
@@ -390,6 +564,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
+    ap.add_argument("--no-density", action="store_true")
     ap.add_argument("--paper-only", action="store_true",
                     help="run only the paper-shaped self-join and print its JSON (a profiling aid)")
     ap.add_argument("--serve-events", type=int, default=600)
@@ -428,11 +603,36 @@ def main():
     ops = cand * 3 * D            # D subtracts, D multiplies, D adds per candidate pair
     avg_s = kern[dom]["avg_ms"] * 1e-3
     achieved = ops / avg_s / 1e12
+    log("valu rate microkernel")
+    measured = frnn.measure_valu_rate() / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12, "unit": "TFLOP/s",
             "frac": achieved / (VALU_PEAK_OPS / 1e12), "traffic": counter_traffic() if dom == "count" else None,
             "kernel": dom, "kernel_avg_ms": kern[dom]["avg_ms"],
             "algorithmic_ops_per_launch": ops, "candidates_per_launch": cand,
-            "candidates_per_pair": cand / max(nnz, 1)}
+            "candidates_per_pair": cand / max(nnz, 1),
+            "peak_measured": measured, "frac_of_measured": achieved / measured,
+            "peak_published_fp32": 157.3, "frac_of_published_fp32": achieved / 157.3,
+            "peak_note": "peak: the published 157.3 TFLOP/s FP32 vector peak halved (it counts a fused "
+                         "multiply-add as two flops; the distance's subtract, multiply and add are one op each "
+                         "and are never fused): 256 CUs x 128 ops x 2.4 GHz; peak_measured: that operation "
+                         "chain timed on this GPU (frnn_measure_valu_rate)"}
+    # per-step distribution (Sec. 4.2 protocol: 30 synchronised timed steps)
+    def one():
+        c = frnn.query_batch([x], w.r, w.K)[0]
+        c.release()
+    st30 = paired_rounds({"step": one}, rounds=30)["step"]
+    step_stats = {k: ([u * 1e3 for u in v] if k == "ci95" else v * 1e3 if k == "median" else v)
+                  for k, v in boot_ci(st30).items()}
+    step_stats["unit"] = "ms"
+    # the event's grid cells and the cell table the batched path clears (its
+    # capacity class: 2 cells per point of 2^k x {1, 1.25, 1.5, 1.75} points)
+    ix = frnn.build(x, w.r)
+    cells = int(ix.info()["cells"])
+    ix.close()
+    pts_cap = 4096
+    while pts_cap * 2 <= w.points.shape[0]:
+        pts_cap *= 2
+    pts_cap = next(pts_cap + pts_cap * q // 4 for q in range(5) if pts_cap + pts_cap * q // 4 >= w.points.shape[0])
     out = {"metric": METRIC, "value": nnz * args.steps / dt, "unit": "neighbour pairs/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -445,7 +645,9 @@ def main():
            "api_build_query": {"ms_per_step": dt_api / args.steps * 1e3,
                                "pairs_per_s": nnz * args.steps / dt_api,
                                "events_per_s": args.steps / dt_api},
+           "step_ms_median_ci95": step_stats,
            "roofline": roof, "kernels": kern,
+           "hbm_kernels": hbm_kernels(kern, w.points.shape[0], D, nnz, cells, 2 * pts_cap + 2),
            "edge_export": bench_edges(frnn, x, w.r, w.K),
            "host_interface": bench_host(frnn, w.points, w.r, w.K)}
     if not args.no_cpu:
@@ -456,6 +658,10 @@ def main():
     if not args.no_paper:
         log("paper-shaped")
         out["paper_shaped"] = bench_paper_shaped(frnn)
+        torch.cuda.empty_cache()
+    if not args.no_density:
+        log("density")
+        out["density"] = bench_density(frnn)
         torch.cuda.empty_cache()
     if not args.no_batched:
         log("batched")

@@ -262,7 +262,7 @@ typedef struct {
     float r;
     int32_t K;
     uint32_t flags;            /* FRNN_SELF_QUERY is implied */
-    int64_t hbm_budget_bytes;  /* device bytes the server may hold at once */
+    int64_t hbm_budget_bytes;  /* device bytes the server may hold at once (frnn_server_memory) */
     int32_t max_batch_events;  /* cap on events per batch (1..1024) */
     int32_t max_inflight;      /* batches on the device at once (1..8) */
     frnn_opts opts;
@@ -286,6 +286,13 @@ frnn_status frnn_server_submit(frnn_server s, const float *points, int64_t N,
  * return FRNN_ERR_NOT_READY).  Hands the result to the caller (release it). */
 frnn_status frnn_server_wait(frnn_server s, uint64_t ticket, double timeout_s,
                              frnn_csr *out, frnn_timing *timing);
+/* Device bytes the server holds for its work, now and at the peak, as the
+ * pool hands them out (size classes): input copies of admitted events, each
+ * worker's batch context, and outputs not yet released.  Admission keeps
+ * this within hbm_budget_bytes, except that the oldest running batch may
+ * always reserve its output (so the excess is at most one output per batch
+ * in flight); the pool's free blocks are not counted. */
+frnn_status frnn_server_memory(frnn_server s, int64_t *held_bytes, int64_t *peak_bytes);
 void frnn_server_destroy(frnn_server s);
 
 /* ---------------------------------------------------------------- tuning
@@ -315,6 +322,13 @@ typedef struct {
 
 void frnn_profile_enable(int32_t on);
 int32_t frnn_profile_read(frnn_kernel_time *out, int32_t cap, int32_t reset);
+
+/* Measured rate (operations per second, whole device) of the distance
+ * evaluation's operation mix: float32 subtract, multiply and add, each
+ * rounded on its own (no fused multiply-add, no packed FP32), run by every
+ * resident wave with independent chains (a microkernel of ~25 ms).  The
+ * roofline denominator of the distance kernels. */
+frnn_status frnn_measure_valu_rate(void *stream, double *ops_per_s);
 
 /* Work counters of the most recent query or batch on this thread. */
 typedef struct {

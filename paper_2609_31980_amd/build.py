@@ -16,7 +16,8 @@ BUILD = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["frnn_kernels.hip", "frnn_runtime.cpp", "frnn_batch.cpp", "frnn_capi.cpp",
-           "frnn_server.cpp", "frnn_tuner.cpp", "frnn_edges.hip", "frnn_edges.cpp", "frnn_host.cpp", "frnn_noalloc.hip"]
+           "frnn_server.cpp", "frnn_tuner.cpp", "frnn_edges.hip", "frnn_edges.cpp", "frnn_host.cpp", "frnn_noalloc.hip",
+           "frnn_valu_probe.hip"]
 
 # -ffp-contract=off: the squared distance must not be fused (exact float32
 # membership).  packed FP32 instructions are switched off for all HIP code.

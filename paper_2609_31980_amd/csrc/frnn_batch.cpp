@@ -68,6 +68,67 @@ bool BatchContext::fits(const Shape &n) const {
            sh_.pch_cap >= n.pch_cap && sh_.qch_cap >= n.qch_cap;
 }
 
+namespace {
+// Sizes of a context's device buffers, in the order the constructor makes
+// them (0: not allocated).
+struct BufSizes {
+    size_t desc, hv, grid, runs, cell_off, ext, xs, perm, key, rank, skey, cells, qs, qperm, qkey, qrank, sqkey,
+        qcells, deg, offs, lofs, lrows, lat, stash, flist, part, lpt;
+    size_t o_ev, o_pc, o_qc;
+};
+
+BufSizes buf_sizes(const BatchContext::Shape &sh) {
+    BufSizes z{};
+    const int D = sh.D, Dp = (D + 3) & ~3, Ec = sh.E_cap;
+    const bool selfq = sh.flags & FRNN_SELF_QUERY;
+    z.o_ev = 256;
+    z.o_pc = z.o_ev + sizeof(EventDev) * Ec;
+    z.o_qc = z.o_pc + sizeof(Chunk) * sh.pch_cap;
+    z.desc = (z.o_qc + sizeof(Chunk) * sh.qch_cap + 15) / 16 * 16;
+    z.hv = 2 * sizeof(Counters) + sizeof(int64_t) * (Ec + 1);
+    z.grid = sizeof(GridDesc) * Ec;
+    z.runs = sizeof(RunEntry) * kRunsMax * Ec;
+    z.cell_off = sizeof(int64_t) * (Ec + 1);
+    z.ext = sizeof(uint32_t) * 2 * sh.pch_cap * D;  // per-chunk extent slots
+    z.xs = sizeof(float) * sh.pts_cap * Dp;
+    z.perm = z.key = z.rank = z.skey = sizeof(uint32_t) * sh.pts_cap;
+    z.cells = sizeof(uint32_t) * (sh.cells_cap + 1);
+    if (!selfq) {
+        z.qs = sizeof(float) * sh.q_cap * Dp;
+        z.qperm = z.qkey = z.qrank = z.sqkey = sizeof(uint32_t) * sh.q_cap;
+        z.qcells = sizeof(uint32_t) * (sh.cells_cap + 1);
+    }
+    z.deg = sizeof(uint32_t) * sh.q_cap;
+    z.offs = z.lofs = sizeof(int64_t) * (sh.q_cap + 1);
+    z.lrows = sizeof(uint32_t) * sh.q_cap;
+    z.lat = sizeof(int64_t) * 2 * sh.q_cap;
+    z.stash = sizeof(uint64_t) * sh.q_cap * std::max(1, sh.o.stash_cap);
+    z.flist = sizeof(uint32_t) * std::max<int64_t>(1, (int64_t)sh.qch_cap * (kChunkRows / sh.o.queries_per_item));
+    z.part = sizeof(uint64_t) * 2 * kScanBlocks;
+    z.lpt = sizeof(uint32_t) * lpt_words(Ec);
+    return z;
+}
+}  // namespace
+
+int64_t BatchContext::bytes_for(const Shape &sh) {
+    const BufSizes z = buf_sizes(sh);
+    int64_t t = 0;
+    for (size_t v : {z.desc, z.hv, z.grid, z.runs, z.cell_off, z.ext, z.xs, z.perm, z.key, z.rank, z.skey, z.cells,
+                     z.qs, z.qperm, z.qkey, z.qrank, z.sqkey, z.qcells, z.deg, z.offs, z.lofs, z.lrows, z.lat,
+                     z.stash, z.flist, z.part, z.lpt})
+        if (v) t += Pool::class_bytes(v);
+    return t;
+}
+
+int64_t BatchContext::device_bytes() const {
+    int64_t t = 0;
+    for (const DevBuf *d : {&desc, &hv, &grid, &cell_off, &ext, &xs, &perm, &key, &rank, &skey, &cells, &qs, &qperm,
+                            &qkey, &qrank, &sqkey, &qcells, &runs, &deg, &offs, &lofs, &lrows, &lat, &stash, &flist,
+                            &part, &lpt, &lk_})
+        if (d->get()) t += Pool::class_bytes(d->bytes());
+    return t;
+}
+
 BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     const int D = sh.D;
     Dp_ = (D + 3) & ~3;
@@ -76,44 +137,45 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     // descriptors (one block, one copy per batch): batch | output | events |
     // point chunks | query chunks, each region sized for the capacity
     static_assert(sizeof(BatchDesc) <= kOutOff && kOutOff + sizeof(OutDesc) <= 256, "descriptor head");
-    o_ev_ = 256;
-    o_pc_ = o_ev_ + sizeof(EventDev) * Ec;
-    o_qc_ = o_pc_ + sizeof(Chunk) * sh.pch_cap;
-    stage_cap_ = (o_qc_ + sizeof(Chunk) * sh.qch_cap + 15) / 16 * 16;
+    const BufSizes z = buf_sizes(sh);
+    o_ev_ = z.o_ev;
+    o_pc_ = z.o_pc;
+    o_qc_ = z.o_qc;
+    stage_cap_ = z.desc;
     desc.reset(stage_cap_, s);
     // the host writes each batch's descriptors here and the first kernel of
     // phase A reads them (coherent: no stale copy in a GPU cache)
     stage_.reset(stage_cap_);
     // read-back block: query counters | build counters | event bases
-    hv.reset(2 * sizeof(Counters) + sizeof(int64_t) * (Ec + 1), s);
-    grid.reset(sizeof(GridDesc) * Ec, s);
-    runs.reset(sizeof(RunEntry) * kRunsMax * Ec, s);
-    cell_off.reset(sizeof(int64_t) * (Ec + 1), s);
-    ext.reset(sizeof(uint32_t) * 2 * sh.pch_cap * D, s);  // per-chunk extent slots
-    xs.reset(sizeof(float) * sh.pts_cap * Dp_, s);
-    perm.reset(sizeof(int32_t) * sh.pts_cap, s);
-    key.reset(sizeof(uint32_t) * sh.pts_cap, s);
-    rank.reset(sizeof(uint32_t) * sh.pts_cap, s);
-    skey.reset(sizeof(uint32_t) * sh.pts_cap, s);
-    cells.reset(sizeof(uint32_t) * (sh.cells_cap + 1), s);
+    hv.reset(z.hv, s);
+    grid.reset(z.grid, s);
+    runs.reset(z.runs, s);
+    cell_off.reset(z.cell_off, s);
+    ext.reset(z.ext, s);
+    xs.reset(z.xs, s);
+    perm.reset(z.perm, s);
+    key.reset(z.key, s);
+    rank.reset(z.rank, s);
+    skey.reset(z.skey, s);
+    cells.reset(z.cells, s);
     if (!selfq) {
-        qs.reset(sizeof(float) * sh.q_cap * Dp_, s);
-        qperm.reset(sizeof(int32_t) * sh.q_cap, s);
-        qkey.reset(sizeof(uint32_t) * sh.q_cap, s);
-        qrank.reset(sizeof(uint32_t) * sh.q_cap, s);
-        sqkey.reset(sizeof(uint32_t) * sh.q_cap, s);
-        qcells.reset(sizeof(uint32_t) * (sh.cells_cap + 1), s);
+        qs.reset(z.qs, s);
+        qperm.reset(z.qperm, s);
+        qkey.reset(z.qkey, s);
+        qrank.reset(z.qrank, s);
+        sqkey.reset(z.sqkey, s);
+        qcells.reset(z.qcells, s);
     }
-    deg.reset(sizeof(uint32_t) * sh.q_cap, s);
-    offs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
-    lofs.reset(sizeof(int64_t) * (sh.q_cap + 1), s);
-    lrows.reset(sizeof(uint32_t) * sh.q_cap, s);
-    lat.reset(sizeof(int64_t) * 2 * sh.q_cap, s);
-    stash.reset(sizeof(uint64_t) * sh.q_cap * std::max(1, sh.o.stash_cap), s);
-    const int64_t fill_cap = std::max<int64_t>(1, (int64_t)sh.qch_cap * (kChunkRows / sh.o.queries_per_item));
-    flist.reset(sizeof(uint32_t) * fill_cap, s);
-    part.reset(sizeof(uint64_t) * 2 * kScanBlocks, s);
-    lpt.reset(sizeof(uint32_t) * lpt_words(Ec), s);
+    deg.reset(z.deg, s);
+    offs.reset(z.offs, s);
+    lofs.reset(z.lofs, s);
+    lrows.reset(z.lrows, s);
+    lat.reset(z.lat, s);
+    stash.reset(z.stash, s);
+    const int64_t fill_cap = (int64_t)(z.flist / sizeof(uint32_t));
+    flist.reset(z.flist, s);
+    part.reset(z.part, s);
+    lpt.reset(z.lpt, s);
 
     Bufs b{};
     b.bd = desc.as<BatchDesc>();
@@ -405,8 +467,10 @@ std::unique_ptr<BatchContext> acquire_context(const BatchContext::Shape &need, h
         if (best >= 0) {
             Cached c = std::move(g_cache[best]);
             g_cache.erase(g_cache.begin() + best);
-            // the previous run of this context may still be on another stream
-            if (c.stream != s) FRNN_HIP(hipStreamWaitEvent(s, c.ctx->done(), 0));
+            // the previous run of this context may still be on another stream:
+            // wait for it on the host (a cross-stream event wait is refused,
+            // and spoils that stream's capture, while it is being captured)
+            if (c.stream != s) FRNN_HIP(hipEventSynchronize(c.ctx->done()));
             c.ctx->retarget(s);
             return std::move(c.ctx);
         }
@@ -429,6 +493,14 @@ void return_context(std::unique_ptr<BatchContext> ctx, hipStream_t s) {
         (void)hipEventSynchronize(old.ctx->done());
         old.ctx->retarget(nullptr);  // its work is done; its stream may be gone
     }
+}
+
+int64_t output_bytes(const BatchContext &ctx, int64_t pairs, int64_t long_keys, bool want_d2) {
+    const size_t b_off = sizeof(int64_t) * (ctx.total_q() + ctx.E());
+    const size_t b_idx = (sizeof(int32_t) * pairs + 255) / 256 * 256;
+    const size_t b_d2 = want_d2 ? (sizeof(float) * pairs + 15) / 16 * 16 : 0;
+    return Pool::class_bytes(b_off + b_idx + b_d2 + 16) +
+           Pool::class_bytes(sizeof(uint64_t) * std::max<int64_t>(1, long_keys));
 }
 
 BatchOutput alloc_output(const BatchContext &ctx, int64_t pairs, int64_t long_keys, bool want_d2,

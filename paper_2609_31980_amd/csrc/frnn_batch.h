@@ -57,6 +57,10 @@ public:
     static Shape shape_for(const frnn_event *ev, int E, int D, float r, int K, uint32_t flags,
                            const Opts &o);
     bool fits(const Shape &need) const;
+    // device bytes a context of this shape holds (pool size classes), and
+    // those this one holds now (its long-row scratch included)
+    static int64_t bytes_for(const Shape &sh);
+    int64_t device_bytes() const;
 
     // 1. descriptors of this batch; prepare writes them to the context's
     //    pinned, device-mapped stage, upload adds the output descriptor when
@@ -146,6 +150,8 @@ struct BatchOutput {
 BatchOutput alloc_output(const BatchContext &ctx, int64_t pairs, int64_t long_keys, bool want_d2,
                          hipStream_t s, uint64_t *long_scratch = nullptr);
 BatchOutput alloc_output(const BatchContext &ctx, const BatchCounts &c, bool want_d2, hipStream_t s);
+// device bytes (pool size classes) of the output alloc_output makes
+int64_t output_bytes(const BatchContext &ctx, int64_t pairs, int64_t long_keys, bool want_d2);
 void hand_out(const BatchContext &ctx, const BatchCounts &c, BatchOutput &bo, frnn_csr *outs);
 
 }  // namespace frnn

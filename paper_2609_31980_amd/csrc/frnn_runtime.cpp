@@ -69,21 +69,25 @@ void *Pool::alloc(size_t bytes, hipStream_t s) {
     const size_t cls = size_class(bytes);
     Block got{nullptr, 0, nullptr, nullptr};
     {
+        // a block freed on this stream is reused at once (stream order); one
+        // freed on another stream only once its last use there is complete.
+        // Ordering by a cross-stream event wait is avoided: when the other
+        // stream is being captured into a graph meanwhile, the runtime
+        // refuses the dependency and invalidates that capture.
         std::lock_guard<std::mutex> g(mu_);
         for (size_t i = 0; i < free_.size(); ++i) {
-            if (free_[i].cls == cls) {
-                got = free_[i];
-                free_[i] = free_.back();
-                free_.pop_back();
-                break;
+            if (free_[i].cls != cls) continue;
+            if (free_[i].stream != s && hipEventQuery(free_[i].ready) != hipSuccess) {
+                (void)hipGetLastError();
+                continue;
             }
+            got = free_[i];
+            free_[i] = free_.back();
+            free_.pop_back();
+            break;
         }
     }
     if (got.p) {
-        if (got.stream != s) {
-            hipError_t e = hipStreamWaitEvent(s, got.ready, 0);
-            if (e != hipSuccess) throw Fail{FRNN_ERR_HIP, std::string("hipStreamWaitEvent: ") + hipGetErrorString(e)};
-        }
         give_event(got.ready);
         std::lock_guard<std::mutex> g(mu_);
         live_.push_back({got.p, cls});

@@ -35,9 +35,9 @@ frnn_status fail(frnn_status st, const std::string &msg);
 
 // ------------------------------------------------------------------- pool
 // Caching device allocator.  Blocks are kept in size classes (2^k times
-// 1, 1.25, 1.5, 1.75) and reused; a block freed on one stream and handed out
-// on another makes the new stream wait for the free point (stream-ordered
-// reuse without host synchronisation).
+// 1, 1.25, 1.5, 1.75) and reused: on the stream that freed them at once
+// (stream order), on another stream once the work before the free point is
+// complete (no host synchronisation, no cross-stream wait).
 class Pool {
 public:
     static Pool &get();
@@ -49,6 +49,8 @@ public:
     int64_t peak() const { return peak_.load(); }
     // test hook: the k-th allocation from now fails (0 = off)
     void fail_after(int64_t k) { fail_at_ = k; }
+    // bytes the pool holds for a request of `bytes` (its size class)
+    static int64_t class_bytes(size_t bytes) { return (int64_t)size_class(bytes ? bytes : 16); }
 
 private:
     struct Block {

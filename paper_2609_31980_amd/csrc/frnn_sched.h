@@ -40,6 +40,34 @@ public:
         return k;
     }
 
+    // Admit the longest prefix k (1..n) of the queue whose charge(k) fits,
+    // reserving charge(k); charge must not decrease with k.  0 when even
+    // charge(1) does not fit.
+    template <class F>
+    int admit_prefix(F &&charge, int n, int64_t *charged) {
+        std::lock_guard<std::mutex> g(mu_);
+        int k = 0;
+        int64_t c = 0;
+        for (int i = 1; i <= n; ++i) {
+            const int64_t ci = charge(i);
+            if (used_ + ci > limit_) break;
+            k = i;
+            c = ci;
+        }
+        used_ += c;
+        peak_ = std::max(peak_, used_);
+        *charged = c;
+        return k;
+    }
+
+    // Take bytes without a wait or a check (a held context growing: the
+    // caller's admission already reserved the difference).
+    void take(int64_t bytes) {
+        std::lock_guard<std::mutex> g(mu_);
+        used_ += bytes;
+        peak_ = std::max(peak_, used_);
+    }
+
     // Wait (up to timeout_s) until anything is returned.
     void wait_release(double timeout_s) {
         std::unique_lock<std::mutex> l(mu_);

@@ -2,14 +2,20 @@
 //
 // Submissions are copied to host memory and queued.  A dispatcher inside
 // each of max_inflight worker threads (each with its own HIP stream) takes
-// whatever is queued, admits events while their pre-count footprint fits the
-// budget, and runs them as one batch through the batched pipeline.  Because
-// several workers run at once, a new batch is binned and counted on one
-// stream while earlier batches are still being filled on others.  After the
-// count pass the batch's exact output size is known; it is reserved against
-// the budget (waiting for releases if needed) before the fill.  Output bytes
-// stay charged until the client releases the result.  The ledger's rules
-// (frnn_sched.h) keep this free of deadlock.
+// whatever is queued, admits the longest prefix of the queue whose device
+// bytes fit the budget, and runs it as one batch through the batched
+// pipeline.  Because several workers run at once, a new batch is binned and
+// counted on one stream while earlier batches are still being filled on
+// others.  After the count pass the batch's exact output size is known; it
+// is reserved against the budget (waiting for releases if needed) before the
+// fill.  Output bytes stay charged until the client releases the result.
+// The ledger's rules (frnn_sched.h) keep this free of deadlock.
+//
+// What is charged is what the pool hands out, in its size classes: each
+// event's input copy (from admission to the end of its batch), each
+// worker's batch context (its binning and work buffers, kept and reused
+// while the next batch fits it, charged for as long as the worker holds it)
+// and each output (from the count pass until the client releases it).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -65,14 +71,15 @@ struct frnn_server_s {
     uint64_t next_ticket = 1;
     int next_batch = 0;
 
-    int64_t precount_bytes(int64_t N) const {
-        const int64_t D = o.D, Dp = (o.D + 3) & ~3;
-        const double cpp = opts.o.cells_per_point;
-        // input + sorted rows + 4 per-point arrays + cells + per-query work
-        // (degree, two row scans, long-row record, and the stash row of
-        // stash_cap 8-byte keys)
-        const int64_t stash = 8 * (int64_t)std::max(1, opts.o.stash_cap);
-        return N * (4 * D + 4 * Dp + 16 + 40 + stash) + (int64_t)(4.0 * cpp * (double)N) + 4096;
+    // device bytes of an event's input copy
+    int64_t input_bytes(int64_t N) const {
+        return Pool::class_bytes(sizeof(float) * (size_t)std::max<int64_t>(1, N) * o.D);
+    }
+    // the context shape of a batch of events of these sizes
+    BatchContext::Shape shape_of(const int64_t *n, int k) const {
+        std::vector<frnn_event> ev(k);
+        for (int i = 0; i < k; ++i) ev[i] = frnn_event{nullptr, n[i], nullptr, 0};
+        return BatchContext::shape_for(ev.data(), k, o.D, o.r, o.K, o.flags, opts);
     }
     void worker(int id);
 };
@@ -82,21 +89,45 @@ void frnn_server_s::worker(int id) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
     const bool want_d2 = o.flags & FRNN_WANT_DIST2;
+    std::unique_ptr<BatchContext> ctx;  // this worker's context
+    int64_t ctx_charge = 0;             // its bytes, charged while it is held
     for (;;) {
         std::vector<std::shared_ptr<Request>> batch;
         int bid = 0;
+        int64_t in_charge = 0;  // this batch's input copies
+        BatchContext::Shape need{};
         {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] { return stop || !queue.empty(); });
             if (stop && queue.empty()) break;
-            // admit in arrival order while the pre-count footprint fits
-            std::vector<int64_t> pre;
-            for (size_t i = 0; i < queue.size() && (int)i < o.max_batch_events; ++i)
-                pre.push_back(queue[i]->precount);
-            const int k = budget->admit(pre.data(), (int)pre.size(), o.max_batch_events);
+            // admit in arrival order the longest prefix whose inputs, and the
+            // growth of this worker's context if it must grow, fit
+            const int n = (int)std::min<size_t>(queue.size(), (size_t)o.max_batch_events);
+            std::vector<int64_t> sizes(n), inb(n + 1, 0);
+            for (int i = 0; i < n; ++i) {
+                sizes[i] = queue[i]->N;
+                inb[i + 1] = inb[i] + input_bytes(sizes[i]);
+            }
+            auto charge = [&](int k) {
+                const BatchContext::Shape sh = shape_of(sizes.data(), k);
+                const int64_t grow =
+                    ctx && ctx->fits(sh) ? 0 : std::max<int64_t>(0, BatchContext::bytes_for(sh) - ctx_charge);
+                return inb[k] + grow;
+            };
+            int64_t charged = 0;
+            const int k = budget->admit_prefix(charge, n, &charged);
             if (k == 0) {
-                // over budget: wait for a release, then try again
                 lk.unlock();
+                if (ctx) {
+                    // this idle worker's context may be what blocks the
+                    // budget: give its bytes back and try again
+                    (void)hipStreamSynchronize(s);
+                    ctx.reset();
+                    budget->release(ctx_charge);
+                    ctx_charge = 0;
+                    continue;
+                }
+                // over budget: wait for a release, then try again
                 budget->wait_release(0.002);
                 continue;
             }
@@ -106,6 +137,10 @@ void frnn_server_s::worker(int id) {
                 batch.push_back(queue.front());
                 queue.pop_front();
             }
+            in_charge = inb[k];
+            need = shape_of(sizes.data(), k);
+            // the reserved growth now belongs to the context
+            ctx_charge += charged - in_charge;
             bid = next_batch++;
             budget->begin(bid);
             if (!queue.empty()) cv_work.notify_one();
@@ -131,18 +166,31 @@ void frnn_server_s::worker(int id) {
                                             sizeof(float) * batch[e]->N * o.D, hipMemcpyHostToDevice, s));
                 ev[e] = frnn_event{inputs[e].as<float>(), batch[e]->N, nullptr, 0};
             }
-            auto need = BatchContext::shape_for(ev.data(), E, o.D, o.r, o.K, o.flags, opts);
-            std::unique_ptr<BatchContext> ctx = acquire_context(need, s);
-            try {
+            if (!ctx || !ctx->fits(need)) {
+                // the old context's buffers go back to the pool first, then
+                // the new one takes its charge (the growth reserved above;
+                // a smaller replacement returns the difference)
+                ctx.reset();
+                try {
+                    ctx.reset(new BatchContext(need, s));
+                } catch (...) {
+                    budget->release(ctx_charge);
+                    ctx_charge = 0;
+                    throw;
+                }
+                const int64_t now = ctx->device_bytes();
+                if (now < ctx_charge) budget->release(ctx_charge - now);
+                else budget->take(now - ctx_charge);
+                ctx_charge = now;
+            }
+            {
                 ctx->set_inputs(ev.data(), E, s);
                 ctx->phase_a(s);
                 BatchCounts c = ctx->read_counts(s);
                 if (c.build_status & kStatusNonfinitePts)
                     throw Fail{FRNN_ERR_NONFINITE, "non-finite coordinate in the points"};
                 // post-count reservation of the exact output
-                const int64_t outb = (int64_t)sizeof(int64_t) * (ctx->total_q() + E) +
-                                     (int64_t)c.ctr.nnz * (want_d2 ? 8 : 4) +
-                                     (int64_t)c.ctr.long_total * 8 + 512;
+                const int64_t outb = output_bytes(*ctx, (int64_t)c.ctr.nnz, (int64_t)c.ctr.long_total, want_d2);
                 if (outb > budget->limit()) throw Fail{FRNN_ERR_BUDGET, "batch output exceeds the budget"};
                 if (!budget->reserve_output(bid, outb, 30.0))
                     throw Fail{FRNN_ERR_BUDGET, "timed out waiting for budget"};
@@ -163,11 +211,7 @@ void frnn_server_s::worker(int id) {
                     throw;
                 }
                 hand_out(*ctx, c, bo, outs.data());
-            } catch (...) {
-                return_context(std::move(ctx), s);
-                throw;
             }
-            return_context(std::move(ctx), s);
             FRNN_HIP(hipStreamSynchronize(s));  // results complete on the device
             // the client may release the results after this stream is gone
             if (E > 0 && outs[0].owner_) static_cast<OutputOwner *>(outs[0].owner_)->buf.set_stream(nullptr);
@@ -180,9 +224,7 @@ void frnn_server_s::worker(int id) {
             err = x.what();
         }
         const double t1 = now_s();
-        int64_t pre = 0;
-        for (auto &r : batch) pre += r->precount;
-        budget->end(bid, pre);
+        budget->end(bid, in_charge);
         {
             std::lock_guard<std::mutex> g(mu);
             for (int e = 0; e < E; ++e) {
@@ -199,6 +241,12 @@ void frnn_server_s::worker(int id) {
         if (st != FRNN_OK)
             for (auto &oc : outs) frnn_csr_release(&oc);
         cv_done.notify_all();
+    }
+    if (ctx) {
+        (void)hipStreamSynchronize(s);
+        ctx->retarget(nullptr);
+        ctx.reset();
+        budget->release(ctx_charge);
     }
     (void)hipStreamDestroy(s);
 }
@@ -256,7 +304,7 @@ frnn_status frnn_server_submit(frnn_server s, const float *points, int64_t N, ui
             return fail(FRNN_ERR_INVALID_ARG, "bad submission");
         auto r = std::make_shared<Request>();
         r->N = N;
-        r->precount = s->precount_bytes(N);
+        r->precount = s->input_bytes(N) + BatchContext::bytes_for(s->shape_of(&N, 1));
         if (r->precount > s->budget->limit()) return fail(FRNN_ERR_BUDGET, "event larger than the whole budget");
         r->host.assign(points, points + N * (int64_t)s->o.D);
         r->tm.submit_s = now_s();
@@ -301,6 +349,13 @@ frnn_status frnn_server_wait(frnn_server s, uint64_t ticket, double timeout_s, f
     } catch (const std::exception &x) {
         return fail(FRNN_ERR_INTERNAL, x.what());
     }
+}
+
+frnn_status frnn_server_memory(frnn_server s, int64_t *held_bytes, int64_t *peak_bytes) {
+    if (!s) return fail(FRNN_ERR_INVALID_ARG, "null server");
+    if (held_bytes) *held_bytes = s->budget->used();
+    if (peak_bytes) *peak_bytes = s->budget->peak();
+    return FRNN_OK;
 }
 
 void frnn_server_destroy(frnn_server s) {

@@ -125,6 +125,7 @@ def _load():
         "frnn_server_submit": (i32, [vp, vp, i64, P(ctypes.c_uint64)]),
         "frnn_server_wait": (i32, [vp, ctypes.c_uint64, ctypes.c_double, P(_CSR), P(Timing)]),
         "frnn_server_destroy": (None, [vp]),
+        "frnn_server_memory": (i32, [vp, P(i64), P(i64)]),
         "frnn_tune": (i32, [vp, i64, i32, f32, i32, u32, vp, P(Opts), P(TuneReport)]),
         "frnn_profile_enable": (None, [i32]),
         "frnn_profile_read": (i32, [P(KernelTime), i32, i32]),
@@ -134,6 +135,7 @@ def _load():
         "frnn_last_error": (ctypes.c_char_p, []),
         "frnn_test_fail_alloc_after": (None, [i64]),
         "frnn_query_noalloc": (i32, [vp, i64, i32, f32, i32, u32, P(Opts), vp, vp, vp, i64, P(i64), vp]),
+        "frnn_measure_valu_rate": (i32, [vp, P(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -498,6 +500,12 @@ class Server:
                                      ctypes.byref(tm)))
         return CSR(out), {k: getattr(tm, k) for k, _ in Timing._fields_}
 
+    def memory(self):
+        """(held, peak) device bytes charged to the server's budget."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.frnn_server_memory(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.frnn_server_destroy(self._h)
@@ -529,6 +537,13 @@ def profile_read(reset: bool = True) -> dict:
     arr = (KernelTime * max(n, 1))()
     n = _lib.frnn_profile_read(arr, n, 1 if reset else 0)
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n)}
+
+
+def measure_valu_rate(stream=None) -> float:
+    """Measured float32 subtract/multiply/add rate of the device (ops/s)."""
+    v = ctypes.c_double(0.0)
+    _check(_lib.frnn_measure_valu_rate(_stream(stream), ctypes.byref(v)))
+    return float(v.value)
 
 
 def last_stats() -> dict:

@@ -1,9 +1,14 @@
 // Simulation of the serving loop's budget rule with a fake executor: several
 // workers admit events from a shared queue, "count" them (a random delay),
 // reserve a random output size, and hand the output to a client thread that
-// releases it later.  Checks: every event is served exactly once, no output
-// reservation times out (no deadlock), and the limit is never exceeded by
-// more than one output per worker (batches in flight).
+// releases it later.  As in the server, each worker keeps a context whose
+// charge grows with the batches it has run (a held context that fits costs
+// nothing more; one that must grow reserves the growth at admission) and
+// gives it back when nothing can be admitted.  Checks: every event is served
+// exactly once, no output reservation times out (no deadlock), the limit is
+// never exceeded by more than one output per worker (batches in flight), and
+// the ledger balances at the end.
+#include <algorithm>
 #include <atomic>
 #include <cstdio>
 #include <cstdlib>
@@ -56,17 +61,37 @@ int main(int argc, char **argv) {
     for (int w = 0; w < workers; ++w) {
         ws.emplace_back([&, w] {
             std::mt19937 r(100 + w);
+            int64_t held = 0;  // this worker's context charge
+            // context bytes for a batch of k events (grows in classes)
+            auto ctx_of = [](int k) {
+                int c = 1;
+                while (c < k) c *= 2;
+                return (int64_t)40 * c;
+            };
             for (;;) {
                 std::vector<std::pair<int, int64_t>> batch;
                 int bid;
+                int64_t in_charge = 0;
                 {
                     std::unique_lock<std::mutex> lk(qmu);
-                    if (queue.empty()) return;
-                    std::vector<int64_t> pre;
-                    for (size_t i = 0; i < queue.size() && i < 8; ++i) pre.push_back(queue[i].second);
-                    const int k = L.admit(pre.data(), (int)pre.size(), 8);
+                    if (queue.empty()) {
+                        lk.unlock();
+                        L.release(held);
+                        return;
+                    }
+                    const int n = (int)std::min<size_t>(queue.size(), 8);
+                    std::vector<int64_t> inb(n + 1, 0);
+                    for (int i = 0; i < n; ++i) inb[i + 1] = inb[i] + queue[i].second;
+                    auto charge = [&](int k) { return inb[k] + std::max<int64_t>(0, ctx_of(k) - held); };
+                    int64_t charged = 0;
+                    const int k = L.admit_prefix(charge, n, &charged);
                     if (k == 0) {
                         lk.unlock();
+                        if (held) {
+                            L.release(held);
+                            held = 0;
+                            continue;
+                        }
                         L.wait_release(0.001);
                         continue;
                     }
@@ -74,6 +99,8 @@ int main(int argc, char **argv) {
                         batch.push_back(queue.front());
                         queue.pop_front();
                     }
+                    in_charge = inb[k];
+                    held += charged - in_charge;
                     bid = next_batch++;
                     L.begin(bid);
                 }
@@ -91,16 +118,12 @@ int main(int argc, char **argv) {
                     bad = true;
                 }
                 std::this_thread::sleep_for(std::chrono::microseconds(r() % 50));  // fill pass
-                int64_t pre_total = 0;
-                for (auto &e : batch) {
-                    served[e.first]++;
-                    pre_total += e.second;
-                }
+                for (auto &e : batch) served[e.first]++;
                 {
                     std::lock_guard<std::mutex> g(rmu);
                     pending.push_back(out);
                 }
-                L.end(bid, pre_total);
+                L.end(bid, in_charge);
             }
         });
     }

@@ -141,6 +141,35 @@ def test_server_budget_admission(frnn):
     srv.close()
 
 
+def test_server_memory_within_budget(frnn):
+    """The device bytes the server holds (inputs, its workers' contexts and
+    unreleased outputs, in the pool's size classes) stay within the budget,
+    plus at most one output per batch in flight (the oldest batch may always
+    reserve its output); results are still exact and everything is returned
+    at the end."""
+    budget = 40_000_000
+    evs = [inputs.tracks(n, 8, seed=120 + i) for i, n in enumerate([20000, 9000, 26000, 15000] * 3)]
+    srv = frnn.Server(8, 0.1, 256, hbm_budget_bytes=budget, max_batch_events=8, max_inflight=2)
+    ts = [srv.submit(e) for e in evs]
+    out_bytes = []
+    batches = {}
+    for i, t in enumerate(ts):
+        c, tm = srv.wait(t)
+        got = _np(c)
+        if i % 4 == 0:
+            pinlib.assert_csr_equal(got, gpu_csr(evs[i], 0.1, 256), f"budgeted event {i}")
+        batches.setdefault(tm["batch_id"], []).append(8 * (len(got[0]) + c.nnz))
+        c.release()
+    held, peak = srv.memory()
+    # one output per batch in flight, with the pool's rounding (at most 1.25x
+    # and a 256-byte class) and the long-row scratch block of each output
+    largest = max(sum(v) for v in batches.values())
+    slack = 2 * (1.25 * largest + 4096 + 512)
+    say(f"server memory: peak {peak} of {budget} (+ {slack:.0f} slack), {len(batches)} batches")
+    assert peak <= budget + slack
+    srv.close()
+
+
 def test_tuner_candidates_all_exact(frnn):
     x = dev(inputs.tracks(30000, 8, seed=7))
     best, rep = frnn.tune(x, 0.1, 256)

@@ -85,3 +85,24 @@ def test_paper_shaped_degree_near_target(orc):
     s = inputs.subset_rows(len(w.points), 500 / len(w.points), 5)
     d = orc.degrees(w.points, w.r, Q=w.points[s], self_ids=s)
     assert abs(d.mean() - 9_279_672 / 271_663) < 0.15 * 34.16
+
+
+def test_stored_event_digests_match_the_generators():
+    """The oracle digests stored for the multi-event workloads cover every
+    event, in order, with the sizes the seeded generators give (the digests
+    themselves are written by tests/golden/write_event_hashes.py from the
+    oracle alone)."""
+    import json
+    import os
+    g = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    b = json.load(open(os.path.join(g, "batch64_hashes.json")))
+    assert [e["event"] for e in b["events"]] == list(range(64))
+    assert [e["N"] for e in b["events"]] == inputs.c3_sizes().tolist()
+    s = json.load(open(os.path.join(g, "stream40_hashes.json")))
+    assert [e["event"] for e in s["events"]] == list(range(40))
+    n = [e["N"] for e in s["events"]]
+    assert n == [a.n for a in inputs.c5_trace(40, rate=1.0)]
+    assert min(n) < 50_000 and max(n) > 200_000          # spans the log-normal range
+    for doc in (b, s):
+        assert doc["K"] == 256 and doc["self_join"] and not doc["exclude_self"]
+        assert all(len(e["sha256"]) == 64 and e["nnz"] <= e["degree_sum"] for e in doc["events"])
