@@ -297,7 +297,7 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
                               "note": "different hardware and the real event; context, not a target"}}
 
 
-def bench_batched(frnn, rounds=30):
+def bench_batched(frnn, rounds=30, tuned=None):
     import torch
     from paper_2609_31980_amd import inputs
     log("batched: generating 64 events")
@@ -320,6 +320,9 @@ def bench_batched(frnn, rounds=30):
     def batched():
         return frnn.query_batch(xs, r, K)
 
+    def batched_tuned():
+        return frnn.query_batch(xs, r, K, opts=tuned)
+
     # parity: batched == per-event, event by event, before any timing
     a, b = per_event(), batched()
     for e in range(len(xs)):
@@ -333,6 +336,15 @@ def bench_batched(frnn, rounds=30):
     del a, b
     sync()
     fns = {"per_event": per_event, "per_event_graph": per_event_graph, "batched": batched}
+    if tuned is not None:
+        c = batched_tuned()
+        for e in range(len(xs)):   # tuned == default batched output, event by event
+            ob, ib, db = c[e].torch()
+            oa, ia, da = frnn.query_batch([xs[e]], r, K)[0].torch()
+            assert torch.equal(oa, ob) and torch.equal(ia, ib) and torch.equal(da.view(torch.int32), db.view(torch.int32))
+        for o in c:
+            o.release()
+        fns["batched_tuned"] = batched_tuned
 
     def run(fn):
         return lambda: [o.release() for o in fn()]
@@ -341,7 +353,7 @@ def bench_batched(frnn, rounds=30):
             run(fn)()
     times = paired_rounds({k: run(f) for k, f in fns.items()}, rounds=rounds)
     E = len(xs)
-    tp, tg, tb = (float(np.median(times[k])) for k in fns)
+    tp, tg, tb = (float(np.median(times[k])) for k in ("per_event", "per_event_graph", "batched"))
     ms = {k: {kk: (v * 1e3 if kk == "median" else [u * 1e3 for u in v] if kk == "ci95" else v)
               for kk, v in boot_ci(times[k]).items()} for k in fns}
     res = {"events": E, "points": npts, "pairs": nnz,
@@ -352,6 +364,11 @@ def bench_batched(frnn, rounds=30):
            "ms_median_ci95": ms,
            "sign_test_per_event_vs_batched": sign_test(times["per_event"], times["batched"]),
            "sign_test_per_event_graph_vs_batched": sign_test(times["per_event_graph"], times["batched"]),
+           **({"batched_tuned_ms": float(np.median(times["batched_tuned"])) * 1e3,
+               "batched_tuned_events_per_s": E / float(np.median(times["batched_tuned"])),
+               "tuned_options": tuned.as_dict(),
+               "sign_test_batched_vs_tuned": sign_test(times["batched"], times["batched_tuned"])}
+              if tuned is not None else {}),
            "protocol": f"10 warm-up rounds, then {rounds} rounds each timing the three paths once in a seeded "
                        "random order, synchronised before and after each call; medians with 95% percentile "
                        "bootstrap intervals (10,000 resamples); exact two-sided sign tests",
@@ -514,6 +531,35 @@ def hbm_kernels(kern, N, D, nnz, cells, cells_cleared):
     return out
 
 
+def bench_tuning(frnn):
+    """The autotuner (frnn_tune) on one event of each tracking-shaped
+    workload: the 300,000-point event, the median-size event of the batch of
+    64, and a median-size served event; chosen options, the default's and the
+    best time (batched single-event path, best of three), the density class."""
+    import torch
+    from paper_2609_31980_amd import inputs
+    evs = {"tracks-300k-d8": inputs.c2().points,
+           "batch64-median-event": None, "serving-median-event": None}
+    sizes = inputs.c3_sizes()
+    k = int(np.argsort(sizes)[len(sizes) // 2])
+    # event k of the batch, generated alone (its own spawned seed, as c3_events does)
+    evs["batch64-median-event"] = inputs.tracks(
+        int(sizes[k]), 8, seed=np.random.SeedSequence(inputs.SEED_C3).spawn(1 + len(sizes))[1 + k])
+    tr = inputs.c5_trace(96, rate=1.0)
+    med = sorted(tr, key=lambda a: a.n)[48]
+    evs["serving-median-event"] = inputs.c5_event(med)
+    out = {}
+    for name, pts in evs.items():
+        x = torch.from_numpy(pts).cuda()
+        best, rep = frnn.tune(x, 0.1, 256)
+        out[name] = {"N": int(len(pts)), "chosen": best.as_dict(), "default_ms": rep["default_ms"],
+                     "best_ms": rep["best_ms"], "gain": rep["default_ms"] / max(rep["best_ms"], 1e-9),
+                     "tried": rep["candidates_tried"], "rejected": rep["candidates_rejected"],
+                     "density_class": rep["density_class"], "from_cache": bool(rep["from_cache"])}
+        del x
+    return out
+
+
 def bench_density(frnn, steps=10, warmup=3):
     """The density workload: 1,000,000 12-D references in Zipf-sized
     clusters, 200,000 separate queries, r=0.15 (mean degree about 100), K=64;
@@ -565,8 +611,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--no-density", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--paper-only", action="store_true",
                     help="run only the paper-shaped self-join and print its JSON (a profiling aid)")
+    ap.add_argument("--only", choices=["density", "batched", "serving"], default=None,
+                    help="run only this section and print its JSON (a profiling aid)")
     ap.add_argument("--serve-events", type=int, default=600)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also write and then read this many MiB with plain kernels (to scale HBM counters)")
@@ -581,6 +630,12 @@ def main():
 
     if args.paper_only:
         print(json.dumps({"paper_shaped": bench_paper_shaped(frnn, args.steps, args.warmup)}), flush=True)
+        return
+    if args.only:
+        fn = {"density": lambda: bench_density(frnn, args.steps, args.warmup),
+              "batched": lambda: bench_batched(frnn, rounds=args.steps),
+              "serving": lambda: bench_serving(frnn, args.serve_events, sweep_events=100, rounds=3)}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
         return
     if args.calib_copy_mib:
         # a plain write kernel and a plain read kernel of known size, to
@@ -663,9 +718,15 @@ def main():
         log("density")
         out["density"] = bench_density(frnn)
         torch.cuda.empty_cache()
+    tuned = None
+    if not args.no_tune:
+        log("tuning")
+        out["tuning"] = bench_tuning(frnn)
+        tuned = frnn.default_opts(**out["tuning"]["batch64-median-event"]["chosen"])
+        torch.cuda.empty_cache()
     if not args.no_batched:
         log("batched")
-        out["batched"] = bench_batched(frnn)
+        out["batched"] = bench_batched(frnn, tuned=tuned)
     if not args.no_serving:
         log("serving")
         out["serving"] = bench_serving(frnn, args.serve_events)

@@ -296,15 +296,22 @@ frnn_status frnn_server_memory(frnn_server s, int64_t *held_bytes, int64_t *peak
 void frnn_server_destroy(frnn_server s);
 
 /* ---------------------------------------------------------------- tuning
- * Times candidate frnn_opts on the given input (a self-query with K) and
- * returns the fastest whose output is bit-identical to the default's.  The
- * result is cached per (device, D, density class, K) in the JSON file named
- * by FRNN_TUNE_CACHE, if set.  Errors as frnn_query. */
+ * Times candidate frnn_opts on the given input (a batched self-query with K,
+ * the graph-replayed path) by coordinate descent over the grid axes, cells
+ * per point, cells and queries per work item, stash size and persistent
+ * launch, and returns the fastest whose output is bit-identical to the
+ * default's.  The result is cached per (device, D, K, density class) in the
+ * JSON file named by FRNN_TUNE_CACHE, if set; the density class is the pair
+ * of half-octaves of the mean candidates and mean neighbours per query of
+ * the default run, so inputs of one class share a setting whatever their
+ * size.  Errors as frnn_query_batch. */
 typedef struct {
     int32_t candidates_tried;
     int32_t candidates_rejected; /* output differed from the default's */
     double best_ms;
     double default_ms;
+    int32_t from_cache;          /* 1: the class was found in the cache (nothing timed beyond the default) */
+    char density_class[96];      /* the cache key */
 } frnn_tune_report;
 
 frnn_status frnn_tune(const float *points, int64_t N, int32_t D, float r, int32_t K,

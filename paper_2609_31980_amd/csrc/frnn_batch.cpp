@@ -235,6 +235,13 @@ void BatchContext::retarget(hipStream_t s) {
     for (DevBuf *d : all) d->set_stream(s);
 }
 
+void BatchContext::retire() {
+    DevBuf *all[] = {&desc, &hv, &grid, &cell_off, &ext,
+                     &xs, &perm, &key, &rank, &skey, &cells, &qs, &qperm, &qkey, &qrank, &sqkey,
+                     &qcells, &runs, &deg, &offs, &lofs, &lrows, &lat, &stash, &flist, &part, &lpt, &lk_};
+    for (DevBuf *d : all) d->mark_complete();
+}
+
 uint64_t *BatchContext::long_scratch(int64_t n, hipStream_t s) {
     const size_t need = sizeof(uint64_t) * (size_t)std::max<int64_t>(1, n);
     if (lk_.bytes() < need) lk_.reset(need, s);
@@ -341,12 +348,15 @@ void BatchContext::launch_b_long(hipStream_t s) {
     LAUNCH("long_sort", s, launch_long_sort(bq_, kn_, 1536, s));
 }
 
-static bool capture(hipStream_t s, hipGraph_t *g, hipGraphExec_t *ge, void (*fn)(void *, hipStream_t),
-                    void *arg) {
-    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+// Builds the graph of fn's launches node by node (no stream capture) and
+// instantiates it; false on any failure (the caller then launches eagerly).
+static bool record(hipStream_t s, hipGraph_t *g, hipGraphExec_t *ge, void (*fn)(void *, hipStream_t), void *arg) {
+    GraphRecorder rec;
+    if (hipGraphCreate(&rec.graph, 0) != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
+    set_recorder(&rec);
     set_capturing(true);
     bool ok = true;
     try {
@@ -355,28 +365,22 @@ static bool capture(hipStream_t s, hipGraph_t *g, hipGraphExec_t *ge, void (*fn)
         ok = false;
     }
     set_capturing(false);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &graph);
-    if (!ok || e != hipSuccess || !graph) {
+    set_recorder(nullptr);
+    if (!ok || rec.err != hipSuccess || hipGraphInstantiate(ge, rec.graph, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGetLastError();
-        if (graph) (void)hipGraphDestroy(graph);
-        return false;
-    }
-    if (hipGraphInstantiate(ge, graph, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipGraphDestroy(graph);
+        (void)hipGraphDestroy(rec.graph);
         *ge = nullptr;
         return false;
     }
-    *g = graph;
+    *g = rec.graph;
     return true;
 }
 
-// Replays graph *ge, capturing it from fn first; false when graphs are off
-// or capture fails (the caller then launches eagerly).
+// Replays graph *ge, recording it from fn first; false when graphs are off
+// or recording fails (the caller then launches eagerly).
 bool BatchContext::replay(hipGraphExec_t *ge, hipGraph_t *g, void (*fn)(void *, hipStream_t), hipStream_t s) {
     if (!graphs_enabled || prof_enabled()) return false;
-    if (!*ge && !capture(s, g, ge, fn, this)) {
+    if (!*ge && !record(s, g, ge, fn, this)) {
         graphs_enabled = false;
         return false;
     }
@@ -468,8 +472,8 @@ std::unique_ptr<BatchContext> acquire_context(const BatchContext::Shape &need, h
             Cached c = std::move(g_cache[best]);
             g_cache.erase(g_cache.begin() + best);
             // the previous run of this context may still be on another stream:
-            // wait for it on the host (a cross-stream event wait is refused,
-            // and spoils that stream's capture, while it is being captured)
+            // wait for it on the host (no cross-stream dependency is left
+            // behind in either stream)
             if (c.stream != s) FRNN_HIP(hipEventSynchronize(c.ctx->done()));
             c.ctx->retarget(s);
             return std::move(c.ctx);
@@ -482,7 +486,7 @@ void return_context(std::unique_ptr<BatchContext> ctx, hipStream_t s) {
     if (hipEventRecord(ctx->done(), s) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipStreamSynchronize(s);
-        ctx->retarget(nullptr);
+        ctx->retire();
         return;  // drop the context
     }
     std::lock_guard<std::mutex> g(g_cache_mu);
@@ -491,7 +495,7 @@ void return_context(std::unique_ptr<BatchContext> ctx, hipStream_t s) {
         Cached old = std::move(g_cache.front());
         g_cache.erase(g_cache.begin());
         (void)hipEventSynchronize(old.ctx->done());
-        old.ctx->retarget(nullptr);  // its work is done; its stream may be gone
+        old.ctx->retire();  // its work is done; its stream may be gone
     }
 }
 

@@ -3,8 +3,8 @@
 // A BatchContext owns device buffers sized for a capacity class (events,
 // points, queries, cells, chunks; rounded up so that similar batches share a
 // class).  Its launch sequence has fixed grid sizes and reads every actual
-// size from device memory, so it is captured once as HIP graphs and
-// replayed for any batch of its class:
+// size from device memory, so it is recorded once as HIP graphs (built node
+// by node, no stream capture) and replayed for any batch of its class:
 //   graph A: bin the points of every event, count every query's neighbours,
 //            scan the capped counts        (then one 8-byte-per-event read-back)
 //   graph B: short rows and per-event offsets; then, only when some row is
@@ -91,6 +91,9 @@ public:
     // Make every buffer's stream-ordered release follow stream s (the
     // stream of the current user, or null once the device work is done).
     void retarget(hipStream_t s);
+    // every buffer's use is complete (its stream synchronised): their
+    // release then records nothing on any stream
+    void retire();
 
     // recorded on the stream of the last run when the context is returned
     hipEvent_t done() const { return done_; }

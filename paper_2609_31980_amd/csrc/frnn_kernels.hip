@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "frnn_device.h"
@@ -1728,12 +1729,50 @@ __global__ void k_set_out(Bufs b, OutDesc v) { *b.out = v; }
         if (e_ != hipSuccess) return e_;   \
     } while (0)
 
+static thread_local GraphRecorder *t_rec = nullptr;
+
+void set_recorder(GraphRecorder *r) { t_rec = r; }
+
+// One kernel launch on stream s, or, while this thread records, one kernel
+// node after the recorder's last (the argument values are copied into the
+// node; the stream is not used).
+template <class... P, class... A>
+static void emit(void (*kern)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t s, A... args) {
+    GraphRecorder *r = t_rec;
+    if (!r) {
+        hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
+        return;
+    }
+    if (r->err != hipSuccess) return;
+    std::tuple<std::decay_t<P>...> vals(args...);  // converted to the parameter types
+    void *params[sizeof...(P) + 1] = {};
+    std::apply([&](auto &...v) {
+        int i = 0;
+        ((params[i++] = (void *)&v), ...);
+    }, vals);
+    hipKernelNodeParams kp{};
+    kp.func = (void *)kern;
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = (unsigned)lds;
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    const hipError_t e = hipGraphAddKernelNode(&node, r->graph, r->last ? &r->last : nullptr, r->last ? 1 : 0, &kp);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        r->err = e;
+        return;
+    }
+    r->last = node;
+}
+
 hipError_t launch_init(const Bufs &b, hipStream_t s, Counters *also, const void *src, void *dst, int64_t bytes) {
     static_assert(sizeof(Counters) / 4 <= 256, "one block clears the counters");
     const int64_t n16 = src ? (bytes + 15) / 16 : 0;
     const int64_t per = 256 * kFetchUnroll;
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, (n16 + per - 1) / per));
-    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, b, also, reinterpret_cast<const uint4 *>(src),
+    emit(k_init, dim3(blocks), dim3(256), 0, s, b, also, reinterpret_cast<const uint4 *>(src),
                        reinterpret_cast<uint4 *>(dst), n16);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
@@ -1744,27 +1783,27 @@ hipError_t launch_extent(const Bufs &b, int nchunks, int E_cap, bool queries, in
     static_assert(kExtentRows == 4 * kChunkRows, "unit bound");
     const int units = (nchunks + 3) / 4 + E_cap;
     const int blocks = std::max(1, std::max(units, (int)std::min<int64_t>((zero_n + 4095) / 4096, 4096)));
-    hipLaunchKernelGGL(k_extent, dim3(blocks), dim3(256), 0, s, b, (int32_t)queries, zero_n);
+    emit(k_extent, dim3(blocks), dim3(256), 0, s, b, (int32_t)queries, zero_n);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
 
 hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_plan, dim3(std::max(1, E_cap)), dim3(256), 0, s, b);
+    emit(k_plan, dim3(std::max(1, E_cap)), dim3(256), 0, s, b);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
 
 hipError_t launch_keys(const Bufs &b, int nchunks, bool queries, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_keys, dim3(std::min(nchunks, 8192)), dim3(256), 0, s, b, (int32_t)queries);
+    emit(k_keys, dim3(std::min(nchunks, 8192)), dim3(256), 0, s, b, (int32_t)queries);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
 
 hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3(std::min(nchunks, 8192)), dim3(256), 0, s, b, (int32_t)queries);
+    emit(k_scatter, dim3(std::min(nchunks, 8192)), dim3(256), 0, s, b, (int32_t)queries);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1777,9 +1816,9 @@ static int scan_blocks(int64_t n_cap) {
 template <int MODE>
 static hipError_t launch_scan_mode(const Bufs &b, const Knobs &kn, int64_t n_cap, hipStream_t s) {
     const int nb = scan_blocks(n_cap);
-    hipLaunchKernelGGL(k_scan_reduce<MODE>, dim3(nb), dim3(kScanThreads), 0, s, b, kn);
+    emit(k_scan_reduce<MODE>, dim3(nb), dim3(kScanThreads), 0, s, b, kn);
     FRNN_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_scan_apply<MODE>, dim3(nb), dim3(kScanThreads), 0, s, b, kn);
+    emit(k_scan_apply<MODE>, dim3(nb), dim3(kScanThreads), 0, s, b, kn);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1846,7 +1885,7 @@ static hipError_t launch_query_t(const Bufs &b, const Knobs &kn, int D, int bloc
             const int per_cu = std::min(std::max(1, FILL ? res : blocks / cus), res);
             g = dim3((unsigned)(per_cu * cus / 8 * 8));
         }
-        hipLaunchKernelGGL(kern, g, block, l, s, b, kn);
+        emit(kern, g, block, l, s, b, kn);
     };
     auto go = [&](auto pers, auto excl) {
         constexpr bool P = decltype(pers)::value, X = decltype(excl)::value;
@@ -1926,12 +1965,12 @@ hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipSt
     static_assert(kChunkRows == 256, "one block per chunk");
     dim3 grid(std::max(1, nqchunks)), block(kChunkRows);
     switch (kn.stash_cap) {
-    case 0: hipLaunchKernelGGL(k_short_rows<0>, grid, block, 0, s, b, kn); break;
-    case 8: hipLaunchKernelGGL(k_short_rows<8>, grid, block, 0, s, b, kn); break;
-    case 16: hipLaunchKernelGGL(k_short_rows<16>, grid, block, 0, s, b, kn); break;
-    case 32: hipLaunchKernelGGL(k_short_rows<32>, grid, block, 0, s, b, kn); break;
-    case 64: hipLaunchKernelGGL(k_short_rows<64>, grid, block, 0, s, b, kn); break;
-    case 128: hipLaunchKernelGGL(k_short_rows<128>, grid, block, 0, s, b, kn); break;
+    case 0: emit(k_short_rows<0>, grid, block, 0, s, b, kn); break;
+    case 8: emit(k_short_rows<8>, grid, block, 0, s, b, kn); break;
+    case 16: emit(k_short_rows<16>, grid, block, 0, s, b, kn); break;
+    case 32: emit(k_short_rows<32>, grid, block, 0, s, b, kn); break;
+    case 64: emit(k_short_rows<64>, grid, block, 0, s, b, kn); break;
+    case 128: emit(k_short_rows<128>, grid, block, 0, s, b, kn); break;
     default: return hipErrorInvalidValue;
     }
     FRNN_CHECK_LAUNCH();
@@ -1939,19 +1978,19 @@ hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipSt
 }
 
 hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_long_sort, dim3(std::max(1, blocks)), dim3(256), 0, s, b, kn);
+    emit(k_long_sort, dim3(std::max(1, blocks)), dim3(256), 0, s, b, kn);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
 
 hipError_t launch_lpt(const Bufs &b, const Knobs &kn, hipStream_t s) {
-    hipLaunchKernelGGL(k_lpt, dim3(1), dim3(256), 0, s, b, kn);
+    emit(k_lpt, dim3(1), dim3(256), 0, s, b, kn);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
 
 hipError_t launch_set_out(const Bufs &b, const OutDesc &v, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_out, dim3(1), dim3(1), 0, s, b, v);
+    emit(k_set_out, dim3(1), dim3(1), 0, s, b, v);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }

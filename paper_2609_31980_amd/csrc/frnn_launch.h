@@ -9,6 +9,19 @@
 
 namespace frnn {
 
+// Graph recording.  While a thread has a recorder set, the launchers below
+// append kernel nodes to its graph instead of launching, each node depending
+// on the one before (the order of launches on one stream).  Building the
+// graph this way involves no stream capture, so nothing another thread does
+// meanwhile (allocations, synchronisations, work on other streams or the
+// null stream) can spoil it.
+struct GraphRecorder {
+    hipGraph_t graph = nullptr;
+    hipGraphNode_t last = nullptr;
+    hipError_t err = hipSuccess;  // first failure to add a node
+};
+void set_recorder(GraphRecorder *r);  // this thread's; null: launch again
+
 // zeroes b.ctr (and `also`, when given); with src, also copies `bytes` of
 // descriptors from device-mapped host memory src to device memory dst (both
 // 16-byte aligned, bytes rounded up to 16)

@@ -63,21 +63,17 @@ size_t Pool::size_class(size_t bytes) {
     return 2 * p;
 }
 
-void *Pool::alloc(size_t bytes, hipStream_t s) {
-    if (fail_at_.load() > 0 && --fail_at_ == 0)
-        throw Fail{FRNN_ERR_OOM, "device allocation failed (test hook)"};
-    const size_t cls = size_class(bytes);
+// A free block of class cls that stream s may use now: one freed on s is
+// reused at once (stream order); one freed on another stream only once its
+// last use there is complete (no cross-stream wait: that would tie this
+// stream's later work to the other stream's).
+void *Pool::take_free(size_t cls, hipStream_t s) {
     Block got{nullptr, 0, nullptr, nullptr};
     {
-        // a block freed on this stream is reused at once (stream order); one
-        // freed on another stream only once its last use there is complete.
-        // Ordering by a cross-stream event wait is avoided: when the other
-        // stream is being captured into a graph meanwhile, the runtime
-        // refuses the dependency and invalidates that capture.
         std::lock_guard<std::mutex> g(mu_);
         for (size_t i = 0; i < free_.size(); ++i) {
             if (free_[i].cls != cls) continue;
-            if (free_[i].stream != s && hipEventQuery(free_[i].ready) != hipSuccess) {
+            if (free_[i].ready && free_[i].stream != s && hipEventQuery(free_[i].ready) != hipSuccess) {
                 (void)hipGetLastError();
                 continue;
             }
@@ -87,12 +83,16 @@ void *Pool::alloc(size_t bytes, hipStream_t s) {
             break;
         }
     }
-    if (got.p) {
-        give_event(got.ready);
-        std::lock_guard<std::mutex> g(mu_);
-        live_.push_back({got.p, cls});
-    } else {
-        void *p = nullptr;
+    if (got.ready) give_event(got.ready);
+    return got.p;
+}
+
+void *Pool::alloc(size_t bytes, hipStream_t s) {
+    if (fail_at_.load() > 0 && --fail_at_ == 0)
+        throw Fail{FRNN_ERR_OOM, "device allocation failed (test hook)"};
+    const size_t cls = size_class(bytes);
+    void *p = take_free(cls, s);
+    if (!p) {
         hipError_t e = hipMalloc(&p, cls);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -103,8 +103,9 @@ void *Pool::alloc(size_t bytes, hipStream_t s) {
                 throw Fail{FRNN_ERR_OOM, "hipMalloc of " + std::to_string(cls) + " bytes failed"};
             }
         }
-        got.p = p;
         held_ += (int64_t)cls;
+    }
+    {
         std::lock_guard<std::mutex> g(mu_);
         live_.push_back({p, cls});
     }
@@ -112,36 +113,49 @@ void *Pool::alloc(size_t bytes, hipStream_t s) {
     int64_t pk = peak_.load();
     while (now > pk && !peak_.compare_exchange_weak(pk, now)) {
     }
-    return got.p;
+    return p;
+}
+
+size_t Pool::unlive(void *p) {
+    std::lock_guard<std::mutex> g(mu_);
+    for (size_t i = 0; i < live_.size(); ++i) {
+        if (live_[i].first == p) {
+            const size_t cls = live_[i].second;
+            live_[i] = live_.back();
+            live_.pop_back();
+            return cls;
+        }
+    }
+    return 0;
 }
 
 void Pool::free(void *p, hipStream_t s) {
     if (!p) return;
-    size_t cls = 0;
-    {
-        std::lock_guard<std::mutex> g(mu_);
-        for (size_t i = 0; i < live_.size(); ++i) {
-            if (live_[i].first == p) {
-                cls = live_[i].second;
-                live_[i] = live_.back();
-                live_.pop_back();
-                break;
-            }
-        }
-    }
+    const size_t cls = unlive(p);
     if (!cls) return;
     hipEvent_t ev = take_event();
-    if (!ev || hipEventRecord(ev, s) != hipSuccess) {
-        // cannot order the reuse: wait here instead
+    if (ev && hipEventRecord(ev, s) != hipSuccess) {
         (void)hipGetLastError();
+        give_event(ev);
+        ev = nullptr;
+    }
+    if (!ev) {
+        // the reuse cannot be ordered by an event: wait here instead
         (void)hipStreamSynchronize(s);
-        if (ev) (void)hipEventDestroy(ev);
-        (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        (void)hipEventRecord(ev, nullptr);
+        (void)hipGetLastError();
     }
     in_use_ -= (int64_t)cls;
     std::lock_guard<std::mutex> g(mu_);
     free_.push_back({p, cls, ev, s});
+}
+
+void Pool::free_complete(void *p) {
+    if (!p) return;
+    const size_t cls = unlive(p);
+    if (!cls) return;
+    in_use_ -= (int64_t)cls;
+    std::lock_guard<std::mutex> g(mu_);
+    free_.push_back({p, cls, nullptr, nullptr});
 }
 
 hipEvent_t Pool::take_event() {
@@ -175,8 +189,10 @@ void Pool::trim() {
         blocks.swap(free_);
     }
     for (auto &b : blocks) {
-        (void)hipEventSynchronize(b.ready);
-        (void)hipEventDestroy(b.ready);
+        if (b.ready) {
+            (void)hipEventSynchronize(b.ready);
+            (void)hipEventDestroy(b.ready);
+        }
         (void)hipFree(b.p);
         held_ -= (int64_t)b.cls;
     }

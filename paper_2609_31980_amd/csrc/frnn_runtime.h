@@ -43,6 +43,8 @@ public:
     static Pool &get();
     void *alloc(size_t bytes, hipStream_t s);
     void free(void *p, hipStream_t s);
+    // return a block whose every use is already complete (no stream order)
+    void free_complete(void *p);
     void trim();
     int64_t held() const { return held_.load(); }
     int64_t in_use() const { return in_use_.load(); }
@@ -56,10 +58,12 @@ private:
     struct Block {
         void *p;
         size_t cls;
-        hipEvent_t ready;   // recorded at free
+        hipEvent_t ready;   // recorded at free; null: every use is complete
         hipStream_t stream; // stream of the free
     };
     static size_t size_class(size_t bytes);
+    void *take_free(size_t cls, hipStream_t s);
+    size_t unlive(void *p);
     // free blocks' events are recycled (creating one costs a runtime call)
     hipEvent_t take_event();
     void give_event(hipEvent_t e);
@@ -86,6 +90,7 @@ public:
             p_ = o.p_;
             bytes_ = o.bytes_;
             s_ = o.s_;
+            done_ = o.done_;
             o.p_ = nullptr;
             o.bytes_ = 0;
         }
@@ -94,15 +99,26 @@ public:
     void reset(size_t bytes, hipStream_t s) {
         release();
         s_ = s;
+        done_ = false;
         bytes_ = bytes;
         p_ = Pool::get().alloc(bytes ? bytes : 16, s);
     }
     void release() {
-        if (p_) Pool::get().free(p_, s_);
+        if (p_) {
+            if (done_) Pool::get().free_complete(p_);
+            else Pool::get().free(p_, s_);
+        }
         p_ = nullptr;
         bytes_ = 0;
     }
-    void set_stream(hipStream_t s) { s_ = s; }
+    void set_stream(hipStream_t s) {
+        s_ = s;
+        done_ = false;
+    }
+    // Every use of the block is complete (the caller has synchronised its
+    // stream): its release then records nothing on any stream, so it may
+    // come from any thread after that stream is gone.
+    void mark_complete() { done_ = true; }
     template <class T>
     T *as() const { return reinterpret_cast<T *>(p_); }
     void *get() const { return p_; }
@@ -112,6 +128,7 @@ private:
     void *p_ = nullptr;
     size_t bytes_ = 0;
     hipStream_t s_ = nullptr;
+    bool done_ = false;
 };
 
 // Pinned host staging buffer (grows, never shrinks).
@@ -218,7 +235,7 @@ bool use_persistent(const frnn_opts &o, int E, int64_t nqchunks, const Knobs &kn
 // grid of the fill pass over `windows` listed windows (it strides past 4096 blocks)
 int fill_blocks(int64_t windows);
 
-// Graph capture in progress on this thread (per-launch timing is skipped).
+// Graph recording in progress on this thread (per-launch timing is skipped).
 void set_capturing(bool on);
 bool capturing();
 

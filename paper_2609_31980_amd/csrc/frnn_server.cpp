@@ -122,6 +122,7 @@ void frnn_server_s::worker(int id) {
                     // this idle worker's context may be what blocks the
                     // budget: give its bytes back and try again
                     (void)hipStreamSynchronize(s);
+                    ctx->retire();
                     ctx.reset();
                     budget->release(ctx_charge);
                     ctx_charge = 0;
@@ -214,8 +215,8 @@ void frnn_server_s::worker(int id) {
             }
             FRNN_HIP(hipStreamSynchronize(s));  // results complete on the device
             // the client may release the results after this stream is gone
-            if (E > 0 && outs[0].owner_) static_cast<OutputOwner *>(outs[0].owner_)->buf.set_stream(nullptr);
-            for (auto &in : inputs) in.set_stream(nullptr);
+            if (E > 0 && outs[0].owner_) static_cast<OutputOwner *>(outs[0].owner_)->buf.mark_complete();
+            for (auto &in : inputs) in.mark_complete();
         } catch (const Fail &f) {
             st = f.st;
             err = f.msg;
@@ -244,7 +245,7 @@ void frnn_server_s::worker(int id) {
     }
     if (ctx) {
         (void)hipStreamSynchronize(s);
-        ctx->retarget(nullptr);
+        ctx->retire();
         ctx.reset();
         budget->release(ctx_charge);
     }

@@ -2,11 +2,14 @@
 //
 // Coordinate descent from the defaults: each parameter in turn takes each of
 // its candidate values with the others held, and the fastest setting is
-// kept.  A candidate is timed as one full build + self-query (the user's
-// wall time, which includes the count read-back) over a few repetitions, and
-// its CSR must be bit-identical to the default setting's; a mismatch is
-// counted as rejected and never chosen.  Winners are cached in a JSON file
-// (FRNN_TUNE_CACHE) under a key of device, D, log2 N, r and K.
+// kept.  A candidate is timed as one batched self-query of the event (the
+// graph-replayed path, the user's wall time including the count read-back)
+// over a few repetitions, and its CSR must be bit-identical to the default
+// setting's; a mismatch is counted as rejected and never chosen.  Winners
+// are cached in a JSON file (FRNN_TUNE_CACHE) under a key of device, D, K
+// and the input's density class: half-octaves of the mean candidates and of
+// the mean neighbours per query, measured by the default run (inputs of one
+// class share their cost structure whatever their size).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,19 +41,14 @@ struct HostCSR {
     }
 };
 
-// One timed build + query; returns milliseconds (and the CSR when asked).
+// One timed batched self-query; returns milliseconds (and the CSR when asked).
 double run_once(const float *pts, int64_t N, int D, float r, int K, uint32_t flags,
                 const frnn_opts &o, hipStream_t s, HostCSR *keep) {
     auto t0 = std::chrono::steady_clock::now();
-    frnn_index ix = nullptr;
-    frnn_status st = frnn_build(pts, N, D, r, &o, s, &ix);
-    if (st) throw Fail{st, frnn_last_error()};
+    const frnn_event ev{pts, N, nullptr, 0};
     frnn_csr c{};
-    st = frnn_query(ix, nullptr, N, r, K, flags, s, &c);
-    if (st) {
-        frnn_index_destroy(ix);
-        throw Fail{st, frnn_last_error()};
-    }
+    frnn_status st = frnn_query_batch(&ev, 1, D, r, K, flags, &o, s, &c);
+    if (st) throw Fail{st, frnn_last_error()};
     FRNN_HIP(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
     if (keep) {
@@ -61,7 +59,6 @@ double run_once(const float *pts, int64_t N, int D, float r, int K, uint32_t fla
                            (c.dist2 && c.nnz) ? keep->d2.data() : nullptr, 1, s);
     }
     frnn_csr_release(&c);
-    frnn_index_destroy(ix);
     if (st) throw Fail{st, frnn_last_error()};
     return std::chrono::duration<double, std::milli>(t1 - t0).count();
 }
@@ -81,10 +78,13 @@ std::string device_name() {
     return p.gcnArchName;
 }
 
-std::string cache_key(int D, int64_t N, float r, int K) {
+// Density class of an input: half-octaves of the mean candidates and of the
+// mean (capped) neighbours per query of the default run.
+std::string cache_key(int D, int K, double cand_per_query, double pairs_per_query) {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s|D%d|N2^%d|r%.6g|K%d", device_name().c_str(), D,
-                  (int)std::lround(std::log2((double)std::max<int64_t>(N, 1))), (double)r, K);
+    std::snprintf(buf, sizeof buf, "%s|D%d|K%d|cand2^%.1f|nbr2^%.1f", device_name().c_str(), D, K,
+                  std::round(2.0 * std::log2(1.0 + cand_per_query)) / 2.0,
+                  std::round(2.0 * std::log2(1.0 + pairs_per_query)) / 2.0);
     return buf;
 }
 
@@ -173,20 +173,28 @@ extern "C" frnn_status frnn_tune(const float *points, int64_t N, int32_t D, floa
         hipStream_t s = (hipStream_t)stream;
         flags = (flags | FRNN_SELF_QUERY) & ~(uint32_t)FRNN_EXCLUDE_SELF;
         const char *cpath = std::getenv("FRNN_TUNE_CACHE");
-        const std::string key = cache_key(D, N, r, K);
+        frnn_opts cur;
+        frnn_opts_default(&cur);
+        HostCSR ref;
+        const double t_def = time_opts(points, N, D, r, K, flags, cur, s, &ref);
+        const frnn_stats st0 = last_stats();
+        const std::string key =
+            cache_key(D, K, (double)st0.candidates / (double)N, (double)st0.pairs / (double)N);
+        if (report) std::snprintf(report->density_class, sizeof report->density_class, "%s", key.c_str());
         if (cpath) {
             std::lock_guard<std::mutex> g(g_cache_mu);
             auto m = read_cache(cpath);
             auto it = m.find(key);
             if (it != m.end()) {
                 *best = it->second;
+                if (report) {
+                    report->candidates_tried = 1;
+                    report->default_ms = report->best_ms = t_def;
+                    report->from_cache = 1;
+                }
                 return FRNN_OK;
             }
         }
-        frnn_opts cur;
-        frnn_opts_default(&cur);
-        HostCSR ref;
-        const double t_def = time_opts(points, N, D, r, K, flags, cur, s, &ref);
         double t_best = t_def;
         int tried = 1, rejected = 0;
         // candidate values per parameter, tried in this order
@@ -195,7 +203,7 @@ extern "C" frnn_status frnn_tune(const float *points, int64_t N, int32_t D, floa
         const int cpis[] = {1, 2, 4};
         const int qpis[] = {8, 16, 32, 64};
         const int stashes[] = {0, 8, 16, 32, 64, 128};
-        const int pers[] = {0, 1};
+        const int pers[] = {0, 1, 2};
         const int bpcs[] = {4, 8, 16};
         auto consider = [&](frnn_opts cand) {
             if (std::memcmp(&cand, &cur, sizeof cand) == 0) return;

@@ -96,7 +96,8 @@ class Timing(ctypes.Structure):
 
 class TuneReport(ctypes.Structure):
     _fields_ = [("candidates_tried", ctypes.c_int32), ("candidates_rejected", ctypes.c_int32),
-                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("from_cache", ctypes.c_int32), ("density_class", ctypes.c_char * 96)]
 
 
 # ------------------------------------------------------------- loading
@@ -525,7 +526,9 @@ def tune(points, r: float, K: int = 0, stream=None):
     _check(_lib.frnn_tune(_pts(points), int(points.shape[0]), int(points.shape[1]),
                           float(np.float32(r)), int(K), WANT_DIST2 | SELF_QUERY,
                           _stream(stream), ctypes.byref(best), ctypes.byref(rep)))
-    return best, {k: getattr(rep, k) for k, _ in TuneReport._fields_}
+    out = {k: getattr(rep, k) for k, _ in TuneReport._fields_}
+    out["density_class"] = out["density_class"].decode()
+    return best, out
 
 
 def profile_enable(on: bool = True):

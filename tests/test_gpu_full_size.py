@@ -101,3 +101,29 @@ def test_stream40_served_events_bit_exact(orc, frnn):
         assert len(batches) > 1
     finally:
         srv.close()
+
+
+def test_stream40_served_under_tight_budget_bit_exact(orc, frnn):
+    """The same stream under a 512 MiB budget with two workers: admission
+    waits, idle workers drop their contexts and new ones are captured into
+    graphs while the other worker runs and the client copies and releases
+    results; every served CSR still equals the oracle's."""
+    want = load("stream40_hashes.json", 40)
+    tr = inputs.c5_trace(40, rate=1.0)
+    say("stream of 40, tight budget: generating")
+    evs = [inputs.c5_event(a) for a in tr]
+    budget = 512 << 20
+    srv = frnn.Server(8, R, K, hbm_budget_bytes=budget, max_batch_events=64, max_inflight=2)
+    try:
+        tickets = [srv.submit(x) for x in evs]
+        batches = set()
+        for i, t in enumerate(tickets):
+            c, tm = srv.wait(t)
+            batches.add(tm["batch_id"])
+            check_event(orc, evs[i], c.numpy(), want[i], f"tight-budget event {i} (batch {tm['batch_id']})")
+            c.release()
+        held, peak = srv.memory()
+        say(f"stream of 40, tight budget: {len(batches)} batches, peak {peak >> 20} MiB")
+        assert len(batches) > 2
+    finally:
+        srv.close()
