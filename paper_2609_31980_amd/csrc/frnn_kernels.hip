@@ -57,6 +57,10 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
 }
 
 // Orders LDS writes of a wave before its later LDS reads by other lanes.
+// s_waitcnt immediate that waits for every vector memory access (vmcnt 0)
+// and for nothing else (expcnt 7, lgkmcnt 15)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1061,7 +1065,14 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         const int e = ch.ev;
         const GridDesc &g = b.grid[e];
         const int G = g.G, m = g.m, runs = g.runs;
-        const int n0 = G > 0 ? g.n[0] : 1;
+        // the per-axis cell counts, read once per window into scalar
+        // registers (all loads together): read through the reference inside
+        // the group loop, the compiler reloads them after every store, one
+        // dependent round trip per axis and probe
+        int gn[kGMax];
+#pragma unroll
+        for (int a = 0; a < kGMax; ++a) gn[a] = (int)uniform((uint32_t)g.n[a]);
+        const int n0 = G > 0 ? gn[0] : 1;
         const int R = kn.cells_per_item;
         const int64_t coff = b.cell_off[e];
         const int64_t q_off = b.ev[e].q_off;
@@ -1070,6 +1081,11 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         const bool inw = lane < nwq;
         const uint32_t wkey = inw ? sqkey[p0 + lane] : 0u;
         const int32_t wperm = inw ? qperm[p0 + lane] : 0;
+        // one run-table entry per lane, loaded once per window (tables with
+        // more than 64 runs, and rows of more than 8 floats, are read per
+        // group instead: there it was measured faster)
+        RunEntry wre{};
+        if (DT <= 8 && lane < runs) wre = rtab[lane];
         const uint32_t wdeg = (FILL && inw) ? b.deg[q_off + wperm] : 0u;
         const int64_t wrow = (FILL && inw) ? b.lofs[q_off + wperm] : 0;  // scratch row (fill pass)
         const int64_t woffs = (FILL && inw) ? b.offs[q_off + wperm] : 0;  // output row (fill pass)
@@ -1094,8 +1110,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
             for (int a = 0; a < kGMax; ++a) {
                 int ca = 0;
                 if (a < G) {
-                    ca = (int)(rem % (uint32_t)g.n[a]);
-                    rem /= (uint32_t)g.n[a];
+                    ca = (int)(rem % (uint32_t)gn[a]);
+                    rem /= (uint32_t)gn[a];
                 }
                 if (a == 0)
                     cw0 = ca;
@@ -1118,16 +1134,18 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         }
         wave_lds_sync();
 
+        // every load of the window's setup is complete here: the group loop
+        // then waits only for its own loads (the compiler cannot count loads
+        // issued before a loop, and would wait for all of them at the first
+        // use of one)
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         // neighbour runs of the group whose first query is window lane gb:
-        // lane s < runs probes run s (start, length)
-        // one run-table entry per lane, loaded once per window (tables with
-        // more than 64 runs, and rows of more than 8 floats, are read per
-        // group instead: there it was measured faster)
-        RunEntry wre{};
-        if (DT <= 8 && lane < runs) wre = rtab[lane];
-        auto probe = [&](int gb, int s, uint32_t &start, uint32_t &len) {
+        // lane s < runs probes run s
+        // (start, end) of the run in the sorted points; the subtraction is
+        // left to commit, so a probe made ahead is not waited for until then
+        auto probe = [&](int gb, int s, uint32_t &start, uint32_t &end) {
             start = 0;
-            len = 0;
+            end = 0;
             if (s >= runs) return;
             const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)wkey, gb);
             int cc[kGMax];
@@ -1149,17 +1167,18 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
             for (int a = 1; a < kGMax; ++a) {
                 if (a < G) {
                     const int ca = cc[a] + re.o[a];
-                    ok = ok && ca >= 0 && ca < g.n[a];
+                    ok = ok & (ca >= 0) & (ca < gn[a]);  // no short circuit: no branch per axis
                 }
             }
             if (ok) {
                 const int64_t k0 = coff + (int64_t)kbase + re.koff;
                 start = cells[k0 + lo0];
-                len = cells[k0 + hi0 + 1] - start;
+                end = cells[k0 + hi0 + 1];
             }
         };
         // compacts probed runs into the LDS table; returns the candidates so far
-        auto commit = [&](uint32_t start, uint32_t len, uint32_t &total, int &nruns) {
+        auto commit = [&](uint32_t start, uint32_t end, uint32_t &total, int &nruns) {
+            const uint32_t len = end - start;
             const uint64_t nz = ballot(len > 0);
             const uint32_t inc = wave_incl_scan(len);
             if (len > 0) {
@@ -1172,8 +1191,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         };
 
         const bool one_batch = runs <= 64;
-        uint32_t nst = 0, nln = 0;
-        if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nln);
+        uint32_t nst = 0, nen = 0;
+        if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nen);
         while (todo) {
             const int gb = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
@@ -1183,12 +1202,12 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
             uint32_t total = 0;
             int nruns = 0;
             if (one_batch) {
-                commit(nst, nln, total, nruns);
+                commit(nst, nen, total, nruns);
             } else {
                 for (int s0 = 0; s0 < runs; s0 += 64) {
-                    uint32_t st0, ln0;
-                    probe(gb, s0 + lane, st0, ln0);
-                    commit(st0, ln0, total, nruns);
+                    uint32_t st0, en0;
+                    probe(gb, s0 + lane, st0, en0);
+                    commit(st0, en0, total, nruns);
                 }
             }
             if (lane == 0) L.run_pref[nruns] = total;
@@ -1230,7 +1249,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 };
                 if (total > 0) fetch(0);
                 // fetch the next group's runs while this one is evaluated
-                if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nln);
+                if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nen);
                 // one query of the group against one chunk; self-exclusion is
                 // decided once per launch (two copies of the loop)
                 auto eval_chunk = [&](auto excl, uint32_t pos, uint32_t j, const CandRow<DT> &x, float thr) {
