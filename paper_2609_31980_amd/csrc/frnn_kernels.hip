@@ -1176,13 +1176,14 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 end = cells[k0 + hi0 + 1];
             }
         };
-        // compacts probed runs into the LDS table; returns the candidates so far
-        auto commit = [&](uint32_t start, uint32_t end, uint32_t &total, int &nruns) {
+        // compacts probed runs into the LDS table from entry tb; returns the
+        // candidates so far
+        auto commit = [&](int tb, uint32_t start, uint32_t end, uint32_t &total, int &nruns) {
             const uint32_t len = end - start;
             const uint64_t nz = ballot(len > 0);
             const uint32_t inc = wave_incl_scan(len);
             if (len > 0) {
-                const int at = nruns + (int)lanes_below(nz);
+                const int at = tb + nruns + (int)lanes_below(nz);
                 L.run_base[at] = start;
                 L.run_pref[at] = total + inc - len;
             }
@@ -1190,9 +1191,26 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
             nruns += __popcll(nz);
         };
 
+        // With at most 64 runs the run table has two halves: the next
+        // group's runs are probed and committed into one while the current
+        // group's, in the other, are read.
         const bool one_batch = runs <= 64;
-        uint32_t nst = 0, nen = 0;
-        if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nen);
+        constexpr int kHalf = kRunsMax / 2;
+        int t_next = 0;  // half holding the next group's runs
+        uint32_t tot_next = 0;
+        int nr_next = 0;
+        auto commit_next = [&](int tb, uint32_t st0, uint32_t en0) {
+            t_next = tb;
+            tot_next = 0;
+            nr_next = 0;
+            commit(tb, st0, en0, tot_next, nr_next);
+            if (lane == 0) L.run_pref[tb + nr_next] = tot_next;
+        };
+        if (one_batch && todo) {
+            uint32_t st0, en0;
+            probe(__ffsll((unsigned long long)todo) - 1, lane, st0, en0);
+            commit_next(0, st0, en0);
+        }
         while (todo) {
             const int gb = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
@@ -1200,17 +1218,19 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
             const int ge = later ? __ffsll((unsigned long long)later) - 1 : nwq;
             ++my_groups;
             uint32_t total = 0;
-            int nruns = 0;
+            int nruns = 0, tb0 = 0;
             if (one_batch) {
-                commit(nst, nen, total, nruns);
+                total = tot_next;
+                nruns = nr_next;
+                tb0 = t_next;
             } else {
                 for (int s0 = 0; s0 < runs; s0 += 64) {
                     uint32_t st0, en0;
                     probe(gb, s0 + lane, st0, en0);
-                    commit(st0, en0, total, nruns);
+                    commit(0, st0, en0, total, nruns);
                 }
+                if (lane == 0) L.run_pref[nruns] = total;
             }
-            if (lane == 0) L.run_pref[nruns] = total;
             wave_lds_sync();
             {
                 // candidates in chunks of 64 (one per lane), every query of the
@@ -1229,7 +1249,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                 // starts are distinct), counted with one 64-bit word of run
                 // starts per chunk
                 const bool few = nruns <= 64;
-                const uint32_t rp = (few && lane < nruns) ? L.run_pref[lane] : 0xffffffffu;
+                const uint32_t rp = (few && lane < nruns) ? L.run_pref[tb0 + lane] : 0xffffffffu;
                 auto fetch = [&](uint32_t v0) {
                     const uint32_t v = v0 + lane;
                     if (few) {
@@ -1240,23 +1260,39 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                         if (lane == 0) L.starts = 0;
                         const uint32_t before = (uint32_t)__popcll(ballot(rp < v0));
                         const uint32_t kr = before + lanes_below(sm) + (uint32_t)((sm >> lane) & 1ull) - 1u;
-                        pn = v < total ? L.run_base[kr] + (v - L.run_pref[kr]) : 0u;
+                        pn = v < total ? L.run_base[tb0 + kr] + (v - L.run_pref[tb0 + kr]) : 0u;
                     } else {
-                        pn = v < total ? locate(L, nruns, v) : 0u;
+                        pn = v < total ? locate(L, nruns, v) : 0u;  // (one table: tb0 == 0)
                     }
-                    load_row<DT, EXACT_D>(xn, b.xs + (int64_t)pn * Dp, D);
+                    // the index before the row: waiting for the row (always
+                    // used) then covers the index (used only by hits)
                     jn = (uint32_t)b.perm[pn];
+                    load_row<DT, EXACT_D>(xn, b.xs + (int64_t)pn * Dp, D);
                 };
-                if (total > 0) fetch(0);
-                // fetch the next group's runs while this one is evaluated
-                if (one_batch && todo) probe(__ffsll((unsigned long long)todo) - 1, lane, nst, nen);
+                // the next group's probe is issued first and this group's first
+                // chunk second, so their round trips overlap, and committing
+                // the probe (a wait for its loads) leaves the chunk's loads in
+                // flight (loads complete in issue order)
+                // (the first chunk is fetched even when the group has no
+                // candidate, lanes past the end reading row 0, so that the
+                // loads in flight at the commit are the same on every path)
+                const bool ahead = one_batch && todo;
+                uint32_t pst = 0, pen = 0;
+                if (ahead) probe(__ffsll((unsigned long long)todo) - 1, lane, pst, pen);
+                fetch(0);
+                if (ahead) commit_next(tb0 ^ kHalf, pst, pen);
                 // one query of the group against one chunk; self-exclusion is
                 // decided once per launch (two copies of the loop)
                 auto eval_chunk = [&](auto excl, uint32_t pos, uint32_t j, const CandRow<DT> &x, float thr) {
                     // the group's query range through scalar registers: the
                     // loop index is then scalar
                     const int tb = (int)uniform((uint32_t)gb), te = (int)uniform((uint32_t)ge);
-                    for (int t = tb; t < te; ++t) {
+                    // a group holds at least one query (tb < te): the first
+                    // pass always reads the chunk, so the compiler knows its
+                    // loads are complete afterwards and does not wait for the
+                    // stores made meanwhile before the next chunk's loads
+                    int t = tb;
+                    do {
                         if constexpr (FILL)
                             if ((uint32_t)__builtin_amdgcn_readlane((int)wdeg, t) <= SC) continue;
                         QueryRow<DT> qr;
@@ -1299,21 +1335,29 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                             else
                                 cntv = lane == t ? c + (uint32_t)__popcll(hm) : cntv;
                         }
-                    }
+                    } while (++t < te);
                 };
-                for (uint32_t v0 = 0; v0 < total; v0 += 64) {
+                if constexpr (DT >= kPrefetchBelow) {
                     // rows of 8 floats or more: no next-chunk prefetch (one
                     // candidate row live instead of two; measured faster at
                     // D = 8 and D = 12, where the extra resident waves hide
-                    // the load instead)
-                    if constexpr (DT >= kPrefetchBelow)
-                        if (v0 > 0) fetch(v0);
-                    const uint32_t pos = pn, j = jn;
-                    const CandRow<DT> x = xn;
-                    const float thr = v0 + lane < total ? r2 : -1.0f;
-                    if constexpr (DT < kPrefetchBelow)
+                    // the load instead).  The first chunk (fetched above; a
+                    // group without candidates evaluates it with every lane
+                    // past the end) is evaluated before the loop, so every
+                    // path into the loop has its loads complete
+                    eval_chunk(std::integral_constant<bool, EXCL>{}, pn, jn, xn, lane < total ? r2 : -1.0f);
+                    for (uint32_t v0 = 64; v0 < total; v0 += 64) {
+                        fetch(v0);
+                        eval_chunk(std::integral_constant<bool, EXCL>{}, pn, jn, xn, v0 + lane < total ? r2 : -1.0f);
+                    }
+                } else {
+                    for (uint32_t v0 = 0; v0 < total; v0 += 64) {
+                        const uint32_t pos = pn, j = jn;
+                        const CandRow<DT> x = xn;
+                        const float thr = v0 + lane < total ? r2 : -1.0f;
                         if (v0 + 64 < total) fetch(v0 + 64);
-                    eval_chunk(std::integral_constant<bool, EXCL>{}, pos, j, x, thr);
+                        eval_chunk(std::integral_constant<bool, EXCL>{}, pos, j, x, thr);
+                    }
                 }
                 const bool mine = lane >= gb && lane < ge;
                 if constexpr (FILL) {
