@@ -324,7 +324,8 @@ void BatchContext::launch_a(hipStream_t s) {
     // build and query counters in one launch
     LAUNCH("init", s, launch_init(bb_, s, bq_.ctr, stage_.dev(), desc.get(), (int64_t)stage_cap_));
     LAUNCH("extent", s, launch_extent(bb_, sh_.pch_cap, sh_.E_cap, false, sh_.cells_cap + 1, s));
-    LAUNCH("plan", s, launch_plan(bb_, sh_.E_cap, s));
+    // the persistent count pass's work order is built by the plan's last block
+    LAUNCH("plan", s, launch_plan(bb_, sh_.E_cap, s, kn_.persistent ? &kn_ : nullptr));
     LAUNCH("keys", s, launch_keys(bb_, sh_.pch_cap, false, s));
     LAUNCH("scan_cells", s, launch_scan_cells(bb_, sh_.cells_cap, false, s));
     LAUNCH("scatter", s, launch_scatter(bb_, sh_.pch_cap, false, s));
@@ -334,7 +335,6 @@ void BatchContext::launch_a(hipStream_t s) {
         LAUNCH("scan_cells_q", s, launch_scan_cells(bq_, sh_.cells_cap, true, s));
         LAUNCH("scatter_q", s, launch_scatter(bq_, sh_.qch_cap, true, s));
     }
-    if (kn_.persistent) LAUNCH("lpt", s, launch_lpt(bq_, kn_, s));
     LAUNCH("count", s, launch_count(bq_, kn_, D, query_blocks(sh_.o, sh_.qch_cap, kn_.persistent), s));
     LAUNCH("scan_rows", s, launch_scan_rows(bq_, kn_, sh_.q_cap, s));
 }

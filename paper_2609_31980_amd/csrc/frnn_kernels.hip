@@ -284,7 +284,11 @@ __device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane, uint32
 // slot layout [unit][min, max][D]),
 // then its first wave plans the grid.  The last block to finish (a ticket
 // counter) scans the events' cell counts into the cell offsets.
-__global__ void __launch_bounds__(256) k_plan(Bufs b) {
+__device__ void lpt_order(Bufs &b, const Knobs &kn);
+
+// with_lpt: the block that plans last also orders the persistent count
+// pass's work (see lpt_order), which needs every event's grid
+__global__ void __launch_bounds__(256) k_plan(Bufs b, Knobs kn, int32_t with_lpt) {
     __shared__ uint32_t s_last;
     __shared__ uint32_t rmin[256];
     __shared__ long long s_c0[256];
@@ -340,6 +344,10 @@ __global__ void __launch_bounds__(256) k_plan(Bufs b) {
     if (gridDim.x == 1) {  // every event in this block: no ticket needed
         __syncthreads();
         plan_offsets(b, bd.E);
+        if (with_lpt) {
+            __syncthreads();
+            lpt_order(b, kn);
+        }
         return;
     }
     __threadfence();
@@ -349,6 +357,10 @@ __global__ void __launch_bounds__(256) k_plan(Bufs b) {
     if (!s_last) return;
     __threadfence();
     plan_offsets(b, bd.E);
+    if (with_lpt) {
+        __syncthreads();
+        lpt_order(b, kn);
+    }
 }
 
 __device__ void plan_event(Bufs &b, const BatchDesc &bd, int e, int lane, uint32_t emin, uint32_t emax) {
@@ -508,10 +520,10 @@ __device__ void plan_offsets(Bufs &b, int E) {
 // each of the 8 XCD queues takes an eighth of every event's windows in that
 // order, so each XCD's L2 sees contiguous windows and every queue starts
 // with the costliest work.
-__global__ void __launch_bounds__(256) k_lpt(Bufs b, Knobs kn) {
+__device__ void lpt_order(Bufs &b, const Knobs &kn) {
     __shared__ float s_cost[kLptMaxEvents];
     __shared__ uint32_t s_nwin[kLptMaxEvents], s_order[kLptMaxEvents];
-    if (b.bd->E > kLptMaxEvents) return;  // the host never launches it then
+    if (b.bd->E > kLptMaxEvents) return;  // the host never asks for it then
     const BatchDesc &bd = *b.bd;
     const int E = bd.E, t = threadIdx.x;
     const uint32_t wpc = kChunkRows / kn.window;
@@ -553,6 +565,8 @@ __global__ void __launch_bounds__(256) k_lpt(Bufs b, Knobs kn) {
         pre[t * (E + 1) + E] = acc;
     }
 }
+
+__global__ void __launch_bounds__(256) k_lpt(Bufs b, Knobs kn) { lpt_order(b, kn); }
 
 // ------------------------------------------------------------------ keys
 __device__ __forceinline__ uint32_t cell_key(const GridDesc &g, const float *row) {
@@ -1851,8 +1865,8 @@ hipError_t launch_extent(const Bufs &b, int nchunks, int E_cap, bool queries, in
     return hipSuccess;
 }
 
-hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s) {
-    emit(k_plan, dim3(std::max(1, E_cap)), dim3(256), 0, s, b);
+hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s, const Knobs *lpt) {
+    emit(k_plan, dim3(std::max(1, E_cap)), dim3(256), 0, s, b, lpt ? *lpt : Knobs{}, (int32_t)(lpt != nullptr));
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }

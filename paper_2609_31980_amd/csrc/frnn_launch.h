@@ -30,7 +30,9 @@ hipError_t launch_init(const Bufs &b, hipStream_t s, Counters *also = nullptr, c
 // one block per chunk (per-chunk extent slots for the points); also clears
 // zero_n cells of the (point or query) cell histogram
 hipError_t launch_extent(const Bufs &b, int nchunks, int E_cap, bool queries, int64_t zero_n, hipStream_t s);
-hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s);
+// with lpt (a persistent count pass's knobs), the plan's last block also
+// builds that pass's work order, as launch_lpt does
+hipError_t launch_plan(const Bufs &b, int E_cap, hipStream_t s, const Knobs *lpt = nullptr);
 hipError_t launch_keys(const Bufs &b, int nchunks, bool queries, hipStream_t s);
 hipError_t launch_scan_cells(const Bufs &b, int64_t cells_cap, bool queries, hipStream_t s);
 hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t s);
