@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 
 #include "frnn_launch.h"
@@ -85,7 +86,7 @@ BufSizes buf_sizes(const BatchContext::Shape &sh) {
     z.o_pc = z.o_ev + sizeof(EventDev) * Ec;
     z.o_qc = z.o_pc + sizeof(Chunk) * sh.pch_cap;
     z.desc = (z.o_qc + sizeof(Chunk) * sh.qch_cap + 15) / 16 * 16;
-    z.hv = 2 * sizeof(Counters) + sizeof(int64_t) * (Ec + 1);
+    z.hv = (2 * sizeof(Counters) + sizeof(int64_t) * (Ec + 1) + 15) / 16 * 16;
     z.grid = sizeof(GridDesc) * Ec;
     z.runs = sizeof(RunEntry) * kRunsMax * Ec;
     z.cell_off = sizeof(int64_t) * (Ec + 1);
@@ -148,6 +149,10 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     stage_.reset(stage_cap_);
     // read-back block: query counters | build counters | event bases
     hv.reset(z.hv, s);
+    // its host-mapped copy, written by the last kernel of phase A (coherent:
+    // the host reads it after the stream's mark, no copy command needed)
+    back_.reset(z.hv);
+    hv16_ = z.hv / 16;
     grid.reset(z.grid, s);
     runs.reset(z.runs, s);
     cell_off.reset(z.cell_off, s);
@@ -249,9 +254,9 @@ uint64_t *BatchContext::long_scratch(int64_t n, hipStream_t s) {
 }
 
 BatchContext::~BatchContext() {
-    for (hipGraphExec_t ge : {ga_, gbs_, gbl_})
+    for (hipGraphExec_t ge : {ga_, gbs_, gbl_, gab_, gabl_})
         if (ge) (void)hipGraphExecDestroy(ge);
-    for (hipGraph_t g : {gra_, grbs_, grbl_})
+    for (hipGraph_t g : {gra_, grbs_, grbl_, grab_, grabl_})
         if (g) (void)hipGraphDestroy(g);
     if (counted_) (void)hipEventDestroy(counted_);
     if (done_) (void)hipEventDestroy(done_);
@@ -293,6 +298,7 @@ void BatchContext::prepare(const frnn_event *ev, int E) {
         tq > sh_.q_cap || E > sh_.E_cap)
         throw Fail{FRNN_ERR_INTERNAL, "batch does not fit its context"};
     BatchDesc bd{};
+    bd.run_id = ++run_seq_;
     bd.E = E;
     bd.D = sh_.D;
     bd.Dp = Dp_;
@@ -337,6 +343,22 @@ void BatchContext::launch_a(hipStream_t s) {
     }
     LAUNCH("count", s, launch_count(bq_, kn_, D, query_blocks(sh_.o, sh_.qch_cap, kn_.persistent), s));
     LAUNCH("scan_rows", s, launch_scan_rows(bq_, kn_, sh_.q_cap, s));
+    LAUNCH("publish", s, launch_copy16(hv.get(), back_.dev(), (int64_t)hv16_, s));
+}
+
+// (the counts are marked between the two parts, so the host reads them
+// while the fill runs)
+void BatchContext::launch_ab(hipStream_t s) {
+    launch_a(s);
+    FRNN_HIP(mark_event(counted_, s));
+    launch_b_short(s);
+}
+
+void BatchContext::launch_abl(hipStream_t s) {
+    launch_a(s);
+    FRNN_HIP(mark_event(counted_, s));
+    launch_b_short(s);
+    launch_b_long(s);
 }
 
 void BatchContext::launch_b_short(hipStream_t s) {
@@ -399,15 +421,36 @@ BatchCounts BatchContext::read_counts(hipStream_t s) {
     return wait_counts();
 }
 
+void BatchContext::phase_ab(bool with_long, hipStream_t s) {
+    last_s_ = s;
+    if (with_long) {
+        if (!replay(&gabl_, &grabl_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_abl(st); }, s))
+            launch_abl(s);
+    } else {
+        if (!replay(&gab_, &grab_, [](void *p, hipStream_t st) { ((BatchContext *)p)->launch_ab(st); }, s))
+            launch_ab(s);
+    }
+}
+
 void BatchContext::fetch_counts(hipStream_t s) {
-    const size_t hvb = 2 * sizeof(Counters) + sizeof(int64_t) * (E_ + 1);
-    FRNN_HIP(hipMemcpyAsync(back_.ensure(hvb), hv.get(), hvb, hipMemcpyDeviceToHost, s));
+    last_s_ = s;
     FRNN_HIP(hipEventRecord(counted_, s));
 }
 
 BatchCounts BatchContext::wait_counts() {
     FRNN_HIP(hipEventSynchronize(counted_));
-    const char *p = back_.as<char>();
+    const char *p = back_.host();
+    // the block must carry this run's number; otherwise (a mark that did
+    // not wait for this run) wait for the stream and read it again
+    auto id_of = [&]() {
+        uint32_t id;
+        std::memcpy(&id, p + offsetof(Counters, run_id), sizeof(id));
+        return id;
+    };
+    if (id_of() != run_seq_) {
+        FRNN_HIP(hipStreamSynchronize(last_s_));
+        if (id_of() != run_seq_) throw Fail{FRNN_ERR_INTERNAL, "read-back block of another run"};
+    }
     BatchCounts c;
     std::memcpy(&c.ctr, p, sizeof(Counters));
     Counters cb;
@@ -568,19 +611,18 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
         // the output owner is freed here unless handed out
         std::unique_ptr<OutputOwner> own(bo.own);
         bo.own = nullptr;
-        ctx->phase_a(s);
-        ctx->fetch_counts(s);
-        // the fill runs while the host reads the counts; its long-row part
-        // only when the previous run had long rows (else after the counts,
-        // if needed: the two parts write different rows)
+        // with a guessed output the fill is in the same graph as the count
+        // (its long-row part only when the previous run had long rows; else
+        // after the counts, if needed: the two parts write different rows);
+        // a fill whose output turns out too small writes nothing
         bool long_queued = false;
         if (spec) {
-            ctx->phase_b_short(s);
-            if (ctx->expect_long()) {
-                ctx->phase_b_long(s);
-                long_queued = true;
-                own->long_ran = true;
-            }
+            long_queued = ctx->expect_long();
+            ctx->phase_ab(long_queued, s);  // marks the counts itself
+            if (long_queued) own->long_ran = true;
+        } else {
+            ctx->phase_a(s);
+            ctx->fetch_counts(s);
         }
         BatchCounts c = ctx->wait_counts();
         if (c.build_status & kStatusNonfinitePts) {

@@ -68,10 +68,15 @@ public:
     void set_inputs(const frnn_event *ev, int E, hipStream_t s);
     void prepare(const frnn_event *ev, int E);
     void upload(hipStream_t s, const OutDesc *od);
-    // 2. bin + count + scan (graph A)
+    // 2. bin + count + scan, and the counters and event bases written to
+    //    the host-mapped read-back block (graph A)
     void phase_a(hipStream_t s);
-    // 3. wait for phase A and read the counters (fetch_counts queues the
-    //    read-back, wait_counts waits for it)
+    // 2+4. graph A followed by the short rows (and the long rows) in one
+    //    graph, for a run whose output was allocated from a guess; the
+    //    counts are marked between the parts (no fetch_counts needed)
+    void phase_ab(bool with_long, hipStream_t s);
+    // 3. wait for phase A and read the counters (fetch_counts marks the
+    //    stream after the read-back, wait_counts waits for the mark)
     BatchCounts read_counts(hipStream_t s);
     void fetch_counts(hipStream_t s);
     BatchCounts wait_counts();
@@ -110,6 +115,8 @@ private:
     void launch_a(hipStream_t s);
     void launch_b_short(hipStream_t s);
     void launch_b_long(hipStream_t s);
+    void launch_ab(hipStream_t s);
+    void launch_abl(hipStream_t s);
     bool replay(hipGraphExec_t *ge, hipGraph_t *g, void (*fn)(void *, hipStream_t), hipStream_t s);
     Shape sh_;
     int Dp_ = 0;
@@ -122,15 +129,18 @@ private:
     DevBuf desc, hv, grid, cell_off, ext, xs, perm, key, rank,
         skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, lat, stash, flist, part,
         lpt;
-    Pinned back_;
+    MappedHost back_;  // read-back block, written by the last kernel of graph A
+    size_t hv16_ = 0;  // its size in 16-byte words
     MappedHost stage_;            // descriptors, host side, read by the first kernel
     size_t stage_cap_ = 0;        // bytes, the capacity of the descriptor block
     int64_t seen_pairs_ = -1, seen_long_ = 0;  // the previous run's output
-    hipEvent_t counted_ = nullptr;  // recorded after the read-back
+    hipEvent_t counted_ = nullptr;  // recorded after graph A (or A and B)
+    uint32_t run_seq_ = 0;          // number of the latest run (BatchDesc::run_id)
+    hipStream_t last_s_ = nullptr;  // stream of the latest run
     hipEvent_t done_ = nullptr;
     DevBuf lk_;
-    hipGraphExec_t ga_ = nullptr, gbs_ = nullptr, gbl_ = nullptr;
-    hipGraph_t gra_ = nullptr, grbs_ = nullptr, grbl_ = nullptr;
+    hipGraphExec_t ga_ = nullptr, gbs_ = nullptr, gbl_ = nullptr, gab_ = nullptr, gabl_ = nullptr;
+    hipGraph_t gra_ = nullptr, grbs_ = nullptr, grbl_ = nullptr, grab_ = nullptr, grabl_ = nullptr;
 };
 
 // Check a context of a fitting class out of the shared cache (or make one);

@@ -60,7 +60,7 @@ struct BatchDesc {
     int32_t grid_axes_max, cell_multiple;
     float cells_per_point;
     float r_build;
-    int32_t pad0;
+    uint32_t run_id;       // the host's number of this run (echoed in the counters)
     int64_t total_pts, total_q;
 };
 
@@ -76,9 +76,8 @@ struct Counters {
     uint32_t n_fill;       // windows listed for the fill pass
     uint32_t plan_done;    // plan blocks finished (the last one scans the cell counts)
     uint32_t n_fill_light; // windows listed for the fill pass from the back of the list (lighter ones)
-    uint32_t pad[6];
-    // persistent count-pass work queues, one per XCD, one 64-byte line each
-    uint32_t heads[8][16];
+    uint32_t run_id;       // BatchDesc::run_id of the run that wrote them (batched path)
+    uint32_t pad[5];
 };
 
 // One neighbour key run of a work group: offsets o[a] (a = 1..G-1) of the

@@ -102,9 +102,19 @@ __device__ __forceinline__ bool finite32(float f) {
 constexpr int kFetchUnroll = 1;
 
 __global__ void __launch_bounds__(256) k_init(Bufs b, Counters *ctr2, const uint4 *src, uint4 *dst, int64_t n16) {
-    if (blockIdx.x == 0 && threadIdx.x < sizeof(Counters) / 4) {
-        reinterpret_cast<uint32_t *>(b.ctr)[threadIdx.x] = 0u;
-        if (ctr2) reinterpret_cast<uint32_t *>(ctr2)[threadIdx.x] = 0u;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < sizeof(Counters) / 4) {
+            reinterpret_cast<uint32_t *>(b.ctr)[threadIdx.x] = 0u;
+            if (ctr2) reinterpret_cast<uint32_t *>(ctr2)[threadIdx.x] = 0u;
+        }
+        // the run's number, from the descriptors at the head of the stage
+        // (the host checks it in the read-back)
+        __syncthreads();
+        if (src && threadIdx.x == 0) {
+            const uint32_t id = reinterpret_cast<const BatchDesc *>(src)->run_id;
+            b.ctr->run_id = id;
+            if (ctr2) ctr2->run_id = id;
+        }
     }
     if (!src) return;
     const int64_t per = (int64_t)blockDim.x * kFetchUnroll;
@@ -1795,6 +1805,12 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
     }
 }
 
+// Copies n16 16-byte words (one block; the read-back of the counters and
+// event bases into device-mapped host memory, inside the recorded graph).
+__global__ void __launch_bounds__(256) k_copy16(const uint4 *src, uint4 *dst, int64_t n16) {
+    for (int64_t i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+}
+
 // Writes the output descriptor from kernel arguments (so the values are
 // captured at launch time, unlike a copy from host memory).
 __global__ void k_set_out(Bufs b, OutDesc v) { *b.out = v; }
@@ -1809,6 +1825,23 @@ __global__ void k_set_out(Bufs b, OutDesc v) { *b.out = v; }
 static thread_local GraphRecorder *t_rec = nullptr;
 
 void set_recorder(GraphRecorder *r) { t_rec = r; }
+
+// Records event ev on stream s, or, while this thread records a graph, an
+// event-record node after the recorder's last node.
+hipError_t mark_event(hipEvent_t ev, hipStream_t s) {
+    GraphRecorder *r = t_rec;
+    if (!r) return hipEventRecord(ev, s);
+    if (r->err != hipSuccess) return r->err;
+    hipGraphNode_t node = nullptr;
+    const hipError_t e = hipGraphAddEventRecordNode(&node, r->graph, r->last ? &r->last : nullptr, r->last ? 1 : 0, ev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        r->err = e;
+        return e;
+    }
+    r->last = node;
+    return hipSuccess;
+}
 
 // One kernel launch on stream s, or, while this thread records, one kernel
 // node after the recorder's last (the argument values are copied into the
@@ -2062,6 +2095,13 @@ hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStrea
 
 hipError_t launch_lpt(const Bufs &b, const Knobs &kn, hipStream_t s) {
     emit(k_lpt, dim3(1), dim3(256), 0, s, b, kn);
+    FRNN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s) {
+    emit(k_copy16, dim3(1), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src), reinterpret_cast<uint4 *>(dst),
+         n16);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }
