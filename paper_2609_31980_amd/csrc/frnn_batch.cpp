@@ -7,6 +7,9 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <atomic>
+#include <thread>
+#include <chrono>
 
 #include "frnn_launch.h"
 
@@ -151,7 +154,7 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     hv.reset(z.hv, s);
     // its host-mapped copy, written by the last kernel of phase A (coherent:
     // the host reads it after the stream's mark, no copy command needed)
-    back_.reset(z.hv);
+    back_.reset(z.hv + 16);  // and the flag word after it
     hv16_ = z.hv / 16;
     grid.reset(z.grid, s);
     runs.reset(z.runs, s);
@@ -229,7 +232,6 @@ BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
     kn_.stash_cap = sh.o.stash_cap;
     kn_.fill_cap = (uint32_t)fill_cap;
     kn_.persistent = use_persistent(sh.o, Ec, sh.qch_cap, kn_, D);
-    FRNN_HIP(hipEventCreateWithFlags(&counted_, hipEventDisableTiming));
     FRNN_HIP(hipEventCreateWithFlags(&done_, hipEventDisableTiming));
 }
 
@@ -258,7 +260,6 @@ BatchContext::~BatchContext() {
         if (ge) (void)hipGraphExecDestroy(ge);
     for (hipGraph_t g : {gra_, grbs_, grbl_, grab_, grabl_})
         if (g) (void)hipGraphDestroy(g);
-    if (counted_) (void)hipEventDestroy(counted_);
     if (done_) (void)hipEventDestroy(done_);
 }
 
@@ -343,20 +344,19 @@ void BatchContext::launch_a(hipStream_t s) {
     }
     LAUNCH("count", s, launch_count(bq_, kn_, D, query_blocks(sh_.o, sh_.qch_cap, kn_.persistent), s));
     LAUNCH("scan_rows", s, launch_scan_rows(bq_, kn_, sh_.q_cap, s));
-    LAUNCH("publish", s, launch_copy16(hv.get(), back_.dev(), (int64_t)hv16_, s));
+    LAUNCH("publish", s, launch_publish(hv.get(), back_.dev(), (int64_t)hv16_,
+                                         reinterpret_cast<uint32_t *>(back_.dev()) + 4 * hv16_, s));
 }
 
-// (the counts are marked between the two parts, so the host reads them
-// while the fill runs)
+// (the host reads the counts as soon as they are published, while the
+// fill runs)
 void BatchContext::launch_ab(hipStream_t s) {
     launch_a(s);
-    FRNN_HIP(mark_event(counted_, s));
     launch_b_short(s);
 }
 
 void BatchContext::launch_abl(hipStream_t s) {
     launch_a(s);
-    FRNN_HIP(mark_event(counted_, s));
     launch_b_short(s);
     launch_b_long(s);
 }
@@ -432,25 +432,28 @@ void BatchContext::phase_ab(bool with_long, hipStream_t s) {
     }
 }
 
-void BatchContext::fetch_counts(hipStream_t s) {
-    last_s_ = s;
-    FRNN_HIP(hipEventRecord(counted_, s));
-}
+void BatchContext::fetch_counts(hipStream_t s) { last_s_ = s; }
 
+// Waits until the read-back block carries this run's number: polls the
+// flag word (the last store of graph A) for a while, then also asks the
+// stream, which fails on a device error and goes idle without the flag
+// only if the run did not publish.
 BatchCounts BatchContext::wait_counts() {
-    FRNN_HIP(hipEventSynchronize(counted_));
-    const char *p = back_.host();
-    // the block must carry this run's number; otherwise (a mark that did
-    // not wait for this run) wait for the stream and read it again
-    auto id_of = [&]() {
-        uint32_t id;
-        std::memcpy(&id, p + offsetof(Counters, run_id), sizeof(id));
-        return id;
-    };
-    if (id_of() != run_seq_) {
-        FRNN_HIP(hipStreamSynchronize(last_s_));
-        if (id_of() != run_seq_) throw Fail{FRNN_ERR_INTERNAL, "read-back block of another run"};
+    const volatile uint32_t *flag = reinterpret_cast<const volatile uint32_t *>(back_.host() + 16 * hv16_);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t n = 0; *flag != run_seq_; ++n) {
+        if ((n & 63u) != 63u || std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(1)) continue;
+        const hipError_t q = hipStreamQuery(last_s_);
+        if (*flag == run_seq_) break;
+        if (q == hipSuccess) throw Fail{FRNN_ERR_INTERNAL, "the run finished without publishing its counters"};
+        if (q != hipErrorNotReady) {
+            (void)hipGetLastError();
+            throw Fail{FRNN_ERR_HIP, std::string("count pass: ") + hipGetErrorString(q)};
+        }
+        std::this_thread::yield();
     }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    const char *p = back_.host();
     BatchCounts c;
     std::memcpy(&c.ctr, p, sizeof(Counters));
     Counters cb;
@@ -618,12 +621,12 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
         bool long_queued = false;
         if (spec) {
             long_queued = ctx->expect_long();
-            ctx->phase_ab(long_queued, s);  // marks the counts itself
+            ctx->phase_ab(long_queued, s);
             if (long_queued) own->long_ran = true;
         } else {
             ctx->phase_a(s);
-            ctx->fetch_counts(s);
         }
+        ctx->fetch_counts(s);
         BatchCounts c = ctx->wait_counts();
         if (c.build_status & kStatusNonfinitePts) {
             st = fail(FRNN_ERR_NONFINITE, "non-finite coordinate in the points");

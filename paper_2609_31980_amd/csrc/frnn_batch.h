@@ -72,11 +72,10 @@ public:
     //    the host-mapped read-back block (graph A)
     void phase_a(hipStream_t s);
     // 2+4. graph A followed by the short rows (and the long rows) in one
-    //    graph, for a run whose output was allocated from a guess; the
-    //    counts are marked between the parts (no fetch_counts needed)
+    //    graph, for a run whose output was allocated from a guess
     void phase_ab(bool with_long, hipStream_t s);
-    // 3. wait for phase A and read the counters (fetch_counts marks the
-    //    stream after the read-back, wait_counts waits for the mark)
+    // 3. wait for phase A's read-back and read the counters (fetch_counts
+    //    notes the stream, wait_counts polls the block's run number)
     BatchCounts read_counts(hipStream_t s);
     void fetch_counts(hipStream_t s);
     BatchCounts wait_counts();
@@ -134,7 +133,6 @@ private:
     MappedHost stage_;            // descriptors, host side, read by the first kernel
     size_t stage_cap_ = 0;        // bytes, the capacity of the descriptor block
     int64_t seen_pairs_ = -1, seen_long_ = 0;  // the previous run's output
-    hipEvent_t counted_ = nullptr;  // recorded after graph A (or A and B)
     uint32_t run_seq_ = 0;          // number of the latest run (BatchDesc::run_id)
     hipStream_t last_s_ = nullptr;  // stream of the latest run
     hipEvent_t done_ = nullptr;

@@ -1805,10 +1805,17 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
     }
 }
 
-// Copies n16 16-byte words (one block; the read-back of the counters and
-// event bases into device-mapped host memory, inside the recorded graph).
-__global__ void __launch_bounds__(256) k_copy16(const uint4 *src, uint4 *dst, int64_t n16) {
+// The read-back (one block): copies n16 16-byte words of counters and event
+// bases (the query counters first) into device-mapped host memory, then,
+// after a system-scope fence, stores the counters' run number into *flag,
+// which the host polls: once it reads this run's number the block is whole.
+__global__ void __launch_bounds__(256) k_publish(const uint4 *src, uint4 *dst, int64_t n16, uint32_t *flag) {
     for (int64_t i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(flag, reinterpret_cast<const Counters *>(src)->run_id, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Writes the output descriptor from kernel arguments (so the values are
@@ -1825,23 +1832,6 @@ __global__ void k_set_out(Bufs b, OutDesc v) { *b.out = v; }
 static thread_local GraphRecorder *t_rec = nullptr;
 
 void set_recorder(GraphRecorder *r) { t_rec = r; }
-
-// Records event ev on stream s, or, while this thread records a graph, an
-// event-record node after the recorder's last node.
-hipError_t mark_event(hipEvent_t ev, hipStream_t s) {
-    GraphRecorder *r = t_rec;
-    if (!r) return hipEventRecord(ev, s);
-    if (r->err != hipSuccess) return r->err;
-    hipGraphNode_t node = nullptr;
-    const hipError_t e = hipGraphAddEventRecordNode(&node, r->graph, r->last ? &r->last : nullptr, r->last ? 1 : 0, ev);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        r->err = e;
-        return e;
-    }
-    r->last = node;
-    return hipSuccess;
-}
 
 // One kernel launch on stream s, or, while this thread records, one kernel
 // node after the recorder's last (the argument values are copied into the
@@ -2099,9 +2089,9 @@ hipError_t launch_lpt(const Bufs &b, const Knobs &kn, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s) {
-    emit(k_copy16, dim3(1), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src), reinterpret_cast<uint4 *>(dst),
-         n16);
+hipError_t launch_publish(const void *src, void *dst, int64_t n16, uint32_t *flag, hipStream_t s) {
+    emit(k_publish, dim3(1), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src), reinterpret_cast<uint4 *>(dst),
+         n16, flag);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -21,8 +21,6 @@ struct GraphRecorder {
     hipError_t err = hipSuccess;  // first failure to add a node
 };
 void set_recorder(GraphRecorder *r);  // this thread's; null: launch again
-// hipEventRecord(ev, s), or an event-record node while recording
-hipError_t mark_event(hipEvent_t ev, hipStream_t s);
 
 // zeroes b.ctr (and `also`, when given); with src, also copies `bytes` of
 // descriptors from device-mapped host memory src to device memory dst (both
@@ -53,7 +51,8 @@ int count_resident_blocks(const Knobs &kn, int D);
 // work order of the persistent count pass (needs the grids and b.lpt)
 hipError_t launch_lpt(const Bufs &b, const Knobs &kn, hipStream_t s);
 hipError_t launch_set_out(const Bufs &b, const OutDesc &v, hipStream_t s);
-// n16 16-byte words from src to dst (both 16-byte aligned), one block
-hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s);
+// the read-back: n16 16-byte words from src (counters first) to dst, then
+// the counters' run number into *flag (all 16-byte aligned), one block
+hipError_t launch_publish(const void *src, void *dst, int64_t n16, uint32_t *flag, hipStream_t s);
 
 }  // namespace frnn
