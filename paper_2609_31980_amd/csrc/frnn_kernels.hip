@@ -41,6 +41,9 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 // by name, so its wait states are handled as for any other instruction).
 extern "C" __device__ int frnn_writelane_i32(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
+// global address space (a pointer made from an integer is otherwise generic)
+#define GLOBAL __attribute__((address_space(1)))
+
 __device__ __forceinline__ int64_t readlane64(int64_t v, int t) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, t);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), t);
@@ -1113,7 +1116,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         const uint32_t wdeg = (FILL && inw) ? b.deg[q_off + wperm] : 0u;
         const int64_t wrow = (FILL && inw) ? b.lofs[q_off + wperm] : 0;  // scratch row (fill pass)
         const int64_t woffs = (FILL && inw) ? b.offs[q_off + wperm] : 0;  // output row (fill pass)
-        const int64_t wst = (!FILL && inw) ? (q_off + wperm) * (int64_t)SC : 0;  // stash row (count pass)
+        // stash row address (count pass)
+        const int64_t wst = (!FILL && inw) ? (int64_t)(uintptr_t)(b.stash + (q_off + wperm) * (int64_t)SC) : 0;
         uint64_t need = ballot(inw);
         if (FILL) {
             need = ballot(inw && wdeg > SC);  // rows the stash did not hold
@@ -1348,7 +1352,12 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                                 // the first SC hit keys of each query go to its stash row
                                 const uint32_t slot = c + lanes_below(hm);
                                 if (hit && slot < SC) {
-                                    b.stash[readlane64(wst, t) + slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                                    // row address in scalar registers, the slot's byte
+                                    // offset in a 32-bit vector register (one add in the
+                                    // store's addressing instead of 64-bit arithmetic)
+                                    *(GLOBAL uint64_t *)((GLOBAL char *)(uintptr_t)readlane64(wst, t) +
+                                                         (uint32_t)(slot * 8u)) =
+                                        ((uint64_t)__float_as_uint(s) << 32) | j;
                                 }
                             }
                             // query t's count lives in lane t (t is scalar; every

@@ -199,7 +199,7 @@ extern "C" frnn_status frnn_tune(const float *points, int64_t N, int32_t D, floa
         int tried = 1, rejected = 0;
         // candidate values per parameter, tried in this order
         const int axes[] = {3, 4, 5, 6};
-        const float cpps[] = {0.5f, 1.f, 2.f, 4.f, 16.f};
+        const float cpps[] = {0.5f, 1.f, 2.f, 4.f, 16.f, 32.f};
         const int cpis[] = {1, 2, 4};
         const int qpis[] = {8, 16, 32, 64};
         const int stashes[] = {0, 8, 16, 32, 64, 128};
