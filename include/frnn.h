@@ -146,7 +146,10 @@ typedef struct {
  * costliest events first), the fixed pipeline is replayed as a HIP graph
  * when the same capacity recurs, and outs[e] is bit-identical to querying
  * event e alone.
- * All events share D, r, K and flags.  Synchronises the stream once.
+ * All events share D, r, K and flags.  The host waits once, for the counts
+ * (published by the device into host-mapped memory); the fill may still be
+ * running on the stream when the call returns, so the outputs are ready in
+ * stream order (frnn_csr_copy to the host synchronises the stream).
  * The outs[] share one allocation; release each of them.
  * Errors: INVALID_ARG, NONFINITE, OOM, HIP. */
 frnn_status frnn_query_batch(const frnn_event *events, int32_t E, int32_t D,

@@ -6,19 +6,21 @@
 // size from device memory, so it is recorded once as HIP graphs (built node
 // by node, no stream capture) and replayed for any batch of its class:
 //   graph A: bin the points of every event, count every query's neighbours,
-//            scan the capped counts        (then one 8-byte-per-event read-back)
+//            scan the capped counts, and publish the counters and event
+//            bases to a host-mapped block (then a flag the host polls)
 //   graph B: short rows and per-event offsets; then, only when some row is
 //            longer than the stash, the fill pass and the long-row sort
 // Run exactly, A and B are separated by the read-back that sizes the output.
 // Once a context has run, its next batch is run speculatively instead: the
-// output is allocated at a capacity guessed from the previous run, and B is
-// queued right behind A and the read-back, so the host checks the counts
-// while B runs; the fill kernels write nothing when the run does not fit,
-// and only then does the host allocate the exact size and replay B.
+// output is allocated at a capacity guessed from the previous run, and A
+// and B are one graph, so the host checks the counts while B runs; the fill
+// kernels write nothing when the run does not fit, and only then does the
+// host allocate the exact size and replay B.
 // The count and fill kernels take windows of sorted queries (runs of cell
 // blocks of one event) as work items: one wave per window from the
 // hardware's dispatch, or, persistent (frnn_opts.persistent), a resident
-// grid dealing per-XCD queues built costliest event first (k_lpt).
+// grid dealing per-XCD queues built costliest event first (by the plan
+// kernel's last block).
 #pragma once
 
 #include <condition_variable>
