@@ -1115,6 +1115,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
         if (DT <= 8 && lane < runs) wre = rtab[lane];
         const uint32_t wdeg = (FILL && inw) ? b.deg[q_off + wperm] : 0u;
         const int64_t wrow = (FILL && inw) ? b.lofs[q_off + wperm] : 0;  // scratch row (fill pass)
+        // its address (fill pass)
+        const int64_t wrp = FILL ? (int64_t)(uintptr_t)(long_keys + wrow) : 0;
         const int64_t woffs = (FILL && inw) ? b.offs[q_off + wperm] : 0;  // output row (fill pass)
         // stash row address (count pass)
         const int64_t wst = (!FILL && inw) ? (int64_t)(uintptr_t)(b.stash + (q_off + wperm) * (int64_t)SC) : 0;
@@ -1347,7 +1349,9 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                             if constexpr (FILL) {
                                 const uint32_t slot = c + lanes_below(hm);
                                 if (hit && slot < (uint32_t)__builtin_amdgcn_readlane((int)wdeg, t))
-                                    long_keys[readlane64(wrow, t) + slot] = ((uint64_t)__float_as_uint(s) << 32) | j;
+                                    *(GLOBAL uint64_t *)((GLOBAL char *)(uintptr_t)readlane64(wrp, t) +
+                                                         (uint32_t)(slot * 8u)) =
+                                        ((uint64_t)__float_as_uint(s) << 32) | j;
                             } else if (c < SC) {
                                 // the first SC hit keys of each query go to its stash row
                                 const uint32_t slot = c + lanes_below(hm);
@@ -1361,12 +1365,8 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                                 }
                             }
                             // query t's count lives in lane t (t is scalar; every
-                            // lane is active here); a single lane write measured
-                            // faster for rows of 12 floats or more, the same at 8
-                            if constexpr (DT >= kScalarWaveFrom)
-                                cntv = (uint32_t)frnn_writelane_i32((int)(c + (uint32_t)__popcll(hm)), t, (int)cntv);
-                            else
-                                cntv = lane == t ? c + (uint32_t)__popcll(hm) : cntv;
+                            // lane is active here), updated by a single lane write
+                            cntv = (uint32_t)frnn_writelane_i32((int)(c + (uint32_t)__popcll(hm)), t, (int)cntv);
                         }
                     } while (++t < te);
                 };
