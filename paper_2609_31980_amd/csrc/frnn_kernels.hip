@@ -42,7 +42,7 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 extern "C" __device__ int frnn_writelane_i32(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
 // global address space (a pointer made from an integer is otherwise generic)
-#define GLOBAL __attribute__((address_space(1)))
+#define FRNN_GLOBAL __attribute__((address_space(1)))
 
 __device__ __forceinline__ int64_t readlane64(int64_t v, int t) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, t);
@@ -1349,7 +1349,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                             if constexpr (FILL) {
                                 const uint32_t slot = c + lanes_below(hm);
                                 if (hit && slot < (uint32_t)__builtin_amdgcn_readlane((int)wdeg, t))
-                                    *(GLOBAL uint64_t *)((GLOBAL char *)(uintptr_t)readlane64(wrp, t) +
+                                    *(FRNN_GLOBAL uint64_t *)((FRNN_GLOBAL char *)(uintptr_t)readlane64(wrp, t) +
                                                          (uint32_t)(slot * 8u)) =
                                         ((uint64_t)__float_as_uint(s) << 32) | j;
                             } else if (c < SC) {
@@ -1359,7 +1359,7 @@ __device__ __forceinline__ void query_body(Bufs &b, Knobs &kn) {
                                     // row address in scalar registers, the slot's byte
                                     // offset in a 32-bit vector register (one add in the
                                     // store's addressing instead of 64-bit arithmetic)
-                                    *(GLOBAL uint64_t *)((GLOBAL char *)(uintptr_t)readlane64(wst, t) +
+                                    *(FRNN_GLOBAL uint64_t *)((FRNN_GLOBAL char *)(uintptr_t)readlane64(wst, t) +
                                                          (uint32_t)(slot * 8u)) =
                                         ((uint64_t)__float_as_uint(s) << 32) | j;
                                 }
