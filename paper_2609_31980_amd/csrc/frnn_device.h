@@ -15,7 +15,7 @@ constexpr int kGMax = 6;         // most grid axes
 constexpr int kDMax = 32;        // most coordinates per point
 constexpr int kRunsMax = 256;    // neighbour runs per work item (LDS table size)
 constexpr int kCandLds = 512;    // candidate positions listed in LDS per work item
-constexpr int kRowLds = 512;     // longest row one wave sorts on chip (rank count in LDS)
+constexpr int kRowLds = 512;     // longest row one wave sorts on chip (8 keys per lane in registers)
 constexpr int kChunkRows = 256;  // rows per chunk of the per-point kernels
 constexpr int kWavesPerBlock = 4;
 

@@ -892,113 +892,88 @@ struct WaveLds {
     int32_t cw[kGMax - 1][64];  // grid coordinates 1.. of each window query's cell
 };
 
-// Sorts the n <= 64*KS distinct keys h[0..n) of one row by rank and writes
-// the first keep places.  The keys are staged in LDS (buf: 64*KS keys,
-// 16-byte aligned; slots past n hold all-ones keys, which are smaller than
-// no key of the row) as KS blocks of 64; lane i takes keys i, 64+i, ...
-// A key's place is the number of smaller keys of the row (the keys of a row
-// are distinct).  With one block it is counted from LDS broadcasts, 8 keys a
-// step.  With two or four, each key is first ranked within its own block the
-// same way, the blocks are rewritten in sorted order, and the smaller keys of
-// each other block are counted by a binary search in it.  With eight (rare
-// rows; fewer live registers) each key is counted against the whole row, in
-// rounds of four keys per lane.
-template <int KS>
-__device__ __forceinline__ void rank_and_write(uint64_t *buf, const uint64_t *h, uint32_t n, uint32_t keep,
-                                               int32_t *idx, float *d2, int lane) {
-    if constexpr (KS > 4) {
-#pragma unroll
-        for (int k = 0; k < KS; ++k) {
-            const uint32_t e = (uint32_t)(k * 64 + lane);
-            buf[e] = e < n ? h[e] : ~0ull;
+// Lane (lane ^ j)'s 32-bit value, j a power of two below 64 (a constant
+// once the caller's loops are unrolled).  Inside a row of 16 lanes the move
+// is a DPP operand (no LDS traffic): xor 1 and 2 are quad permutations, xor
+// 4 a mirror of each 8 lanes followed by a reversal of each 4
+// (i ^ 7 ^ 3 = i ^ 4), xor 8 a rotation of the row by 8; xor 16 is a
+// swizzle in bitmask mode (and 31, xor 16) and xor 32 a permute.
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t v, int j) {
+    const int x = (int)v;
+    switch (j) {
+        case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, true);  // quad_perm 1,0,3,2
+        case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, true);  // quad_perm 2,3,0,1
+        case 4: {
+            const int t = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, true);        // row_half_mirror
+            return (uint32_t)__builtin_amdgcn_update_dpp(0, t, 0x1B, 0xf, 0xf, true);      // quad_perm 3,2,1,0
         }
-        wave_lds_sync();
-        const ulonglong2 *w2 = reinterpret_cast<const ulonglong2 *>(buf);
-#pragma unroll 1
-        for (int k0 = 0; k0 < KS; k0 += 4) {
-            uint64_t mine[4];
-            uint32_t rk[4];
+        case 8: return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x128, 0xf, 0xf, true);  // row_ror:8
+        case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401F);
+        default: return (uint32_t)__shfl_xor(x, j);
+    }
+}
+
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v, int j) {
+    return ((uint64_t)xor_lane32((uint32_t)(v >> 32), j) << 32) | xor_lane32((uint32_t)v, j);
+}
+
+// Sorts the n <= 64*KS keys h[0..n) of one row ascending with a bitonic
+// network held by the wave and writes the first keep.  Lane i holds
+// elements KS*i .. KS*i + KS-1 in registers 0..KS-1 (slots past n hold
+// all-ones keys, which compare above every key of a row and stay at the
+// end), so a compare-exchange whose partner distance j is below KS pairs two
+// registers of one lane and only the 21 stages with j >= KS read another
+// lane (lane i ^ j/KS, the same register).  After the network element e is
+// the row's e-th smallest key, and the first keep are written in order.
+template <int KS>
+__device__ __forceinline__ void sort_and_write(const uint64_t *h, uint32_t n, uint32_t keep, int32_t *idx,
+                                               float *d2, int lane) {
+    uint64_t v[KS];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                mine[k] = buf[(k0 + k) * 64 + lane];
-                rk[k] = 0;
-            }
-#pragma unroll 1
-            for (uint32_t i = 0; i < n; i += 8) {
-                ulonglong2 c[4];
+    for (int k = 0; k < KS; ++k) {
+        const uint32_t e = (uint32_t)(lane * KS + k);
+        v[k] = e < n ? h[e] : ~0ull;
+    }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) c[u] = w2[i / 2 + u];
+    for (int kk = 2; kk <= 64 * KS; kk <<= 1) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j < KS) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) rk[k] += (c[u].x < mine[k] ? 1u : 0u) + (c[u].y < mine[k] ? 1u : 0u);
-            }
+                for (int k = 0; k < KS; ++k) {
+                    const int l = k ^ j;
+                    if (l > k) {
+                        const bool asc = (((lane * KS) | k) & kk) == 0;
+                        const uint64_t a = v[k], c = v[l];
+                        const bool sw = asc ? (c < a) : (a < c);
+                        v[k] = sw ? c : a;
+                        v[l] = sw ? a : c;
+                    }
+                }
+            } else {
+                const int jl = j / KS;
+                // kk > j >= KS: the direction bit is in the lane number
+                const bool asc = ((lane * KS) & kk) == 0;
+                const bool lower = (lane & jl) == 0;
+                // the lower element of an ascending pair keeps the minimum
+                const bool take_min = lower == asc;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if ((uint32_t)((k0 + k) * 64 + lane) < n && rk[k] < keep) {
-                    idx[rk[k]] = (int32_t)(uint32_t)mine[k];
-                    if (d2) d2[rk[k]] = __uint_as_float((uint32_t)(mine[k] >> 32));
+                for (int k = 0; k < KS; ++k) {
+                    const uint64_t p = xor_lane64(v[k], jl);
+                    const bool less = p < v[k];
+                    v[k] = (less == take_min) ? p : v[k];
                 }
             }
         }
-        wave_lds_sync();
-        return;
-    }
-    uint64_t key[KS];
-    uint32_t rank[KS];
-#pragma unroll
-    for (int k = 0; k < KS; ++k) {
-        const uint32_t e = (uint32_t)(k * 64 + lane);
-        key[k] = e < n ? h[e] : ~0ull;
-        buf[e] = key[k];
-        rank[k] = 0;
-    }
-    wave_lds_sync();
-    const ulonglong2 *b2 = reinterpret_cast<const ulonglong2 *>(buf);
-    // rank within the key's own block (the whole row when KS == 1)
-#pragma unroll
-    for (int k = 0; k < KS; ++k) {
-        const uint32_t len = KS == 1 ? n : 64u;
-#pragma unroll 1
-        for (uint32_t i = 0; i < len; i += 8) {
-            ulonglong2 c[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) c[u] = b2[(k * 64 + i) / 2 + u];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) rank[k] += (c[u].x < key[k] ? 1u : 0u) + (c[u].y < key[k] ? 1u : 0u);
-        }
-    }
-    if constexpr (KS > 1) {
-        // each block in sorted order (the all-ones padding keys share one
-        // place; slots after it are never read)
-        wave_lds_sync();
-#pragma unroll
-        for (int k = 0; k < KS; ++k) buf[k * 64 + rank[k]] = key[k];
-        wave_lds_sync();
-#pragma unroll
-        for (int k = 0; k < KS; ++k) {
-#pragma unroll
-            for (int c = 0; c < KS; ++c) {
-                if (c == k) continue;
-                const int64_t rest = (int64_t)n - c * 64;
-                const uint32_t len = rest <= 0 ? 0u : (rest >= 64 ? 64u : (uint32_t)rest);
-                const uint64_t *blk = buf + c * 64;
-                uint32_t pos = 0;  // keys of block c smaller than key[k]
-#pragma unroll
-                for (uint32_t step = 64; step >= 1; step >>= 1)
-                    if (pos + step <= len && blk[pos + step - 1] < key[k]) pos += step;
-                rank[k] += pos;
-            }
-        }
     }
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
-        if ((uint32_t)(k * 64 + lane) < n && rank[k] < keep) {
-            idx[rank[k]] = (int32_t)(uint32_t)key[k];
-            if (d2) d2[rank[k]] = __uint_as_float((uint32_t)(key[k] >> 32));
+        const uint32_t e = (uint32_t)(lane * KS + k);
+        if (e < keep) {
+            idx[e] = (int32_t)(uint32_t)v[k];
+            if (d2) d2[e] = __uint_as_float((uint32_t)(v[k] >> 32));
         }
     }
-    wave_lds_sync();
 }
 
 // Position of candidate v (0 <= v < L) among the group's concatenated runs.
@@ -1740,11 +1715,11 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
 // ------------------------------------------------------------ long rows
 // Rows longer than the stash, listed by the fill pass with their keys in
 // their scratch rows, one wave per row: up to the on-chip limit (at most 512
-// keys) sorted by rank, longer rows sorted in place in global memory with the
-// all-ascending bitonic network (absent elements past n act as +infinity and
-// never move).  Either way the first min(n, K) are written.
+// keys) sorted in registers by a wave-wide bitonic network, longer rows
+// sorted in place in global memory with the all-ascending bitonic network
+// (absent elements past n act as +infinity and never move).  Either way the
+// first min(n, K) are written.
 __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
-    __shared__ __align__(16) uint64_t sbuf[kWavesPerBlock][kRowLds];
     if (!out_fits(b)) return;
     // the fill pass, which ran before this launch on the same stream, flags
     // a row whose recount differs; the output carries the flag to the host
@@ -1764,13 +1739,13 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
         if (n <= (uint64_t)kn.long_cap) {
             const uint32_t n32 = (uint32_t)n, k32 = (uint32_t)keep;
             if (n <= 64)
-                rank_and_write<1>(&sbuf[w][0], a, n32, k32, oi, od, lane);
+                sort_and_write<1>(a, n32, k32, oi, od, lane);
             else if (n <= 128)
-                rank_and_write<2>(&sbuf[w][0], a, n32, k32, oi, od, lane);
+                sort_and_write<2>(a, n32, k32, oi, od, lane);
             else if (n <= 256)
-                rank_and_write<4>(&sbuf[w][0], a, n32, k32, oi, od, lane);
+                sort_and_write<4>(a, n32, k32, oi, od, lane);
             else
-                rank_and_write<8>(&sbuf[w][0], a, n32, k32, oi, od, lane);
+                sort_and_write<8>(a, n32, k32, oi, od, lane);
             continue;
         }
         uint64_t P = 1;
