@@ -10,9 +10,9 @@ Default run (about two minutes):
   * paper-shaped: the 271,663-point 12-D self-join (r=0.12, K=1000, self
     pairs excluded) standing in for the paper's measured event;
   * density: 1,000,000 12-D references, 200,000 separate queries, K=64;
-  * batched: 64 uneven tracking events, one graph-replayed batch (one
-    launch per pipeline step over all events) vs 64 plain per-event
-    build+query calls (identical output checked);
+  * batched: 64 uneven tracking events in one batched call (one launch per
+    pipeline step over all events; also replayed as HIP graphs) vs 64 plain
+    per-event build+query calls (identical output checked);
   * serving: Poisson arrivals of log-normal-size events through the
     continuous-batching server vs a FIFO of plain per-event calls, with a
     load sweep, paired rounds and a tight memory budget.
@@ -145,11 +145,20 @@ def time_steps(step, steps, warmup):
 
 def bench_single(frnn, x, r, K, steps, warmup):
     """One step = the whole path for one event (bin, count, fill), input
-    resident in HBM.  Headline: the single-event launch sequence replayed as
-    a HIP graph (one synchronisation).  Beside it: the same kernels through
-    the build + query API (two synchronisations, eager launches)."""
-    def step_graph():
+    resident in HBM.  Headline: the batched call on one event (its launch
+    sequence, one synchronisation for the counts).  Beside it: the same
+    launch sequence replayed as a HIP graph (the graphs option), and the
+    same kernels through the build + query API (two synchronisations)."""
+    og = frnn.default_opts(graphs=1)
+
+    def step_batch():
         c = frnn.query_batch([x], r, K)[0]
+        n = c.nnz
+        c.release()
+        return n
+
+    def step_graph():
+        c = frnn.query_batch([x], r, K, opts=og)[0]
         n = c.nnz
         c.release()
         return n
@@ -162,20 +171,22 @@ def bench_single(frnn, x, r, K, steps, warmup):
         ix.close()
         return n
 
-    dt, nnz = time_steps(step_graph, steps, warmup)
+    dt, nnz = time_steps(step_batch, steps, warmup)
     stats = frnn.last_stats()
+    dt_graph, nnz_graph = time_steps(step_graph, steps, warmup)
+    assert nnz_graph == nnz
     dt_api, nnz_api = time_steps(step_api, steps, warmup)
     assert nnz_api == nnz
-    # a third pass with per-launch HIP events (eager launches) for the
-    # kernel durations of the same work
+    # a fourth pass with per-launch HIP events for the kernel durations of
+    # the same work
     frnn.profile_enable(True)
     frnn.profile_read(reset=True)
     for _ in range(steps):
-        step_graph()
+        step_batch()
     sync()
     prof = frnn.profile_read(reset=True)
     frnn.profile_enable(False)
-    return dt, dt_api, nnz, stats, prof
+    return dt, dt_graph, dt_api, nnz, stats, prof
 
 
 # ------------------------------------------------------------ CPU baseline
@@ -250,14 +261,14 @@ def bench_host(frnn, pts, r, K, steps=10, warmup=2):
 
 def bench_paper_shaped(frnn, steps=20, warmup=5):
     """The paper-shaped self-join (271,663 points, D=12, r=0.12, K=1000, self
-    pairs excluded): the same graph step and eager API as the headline.  The
+    pairs excluded): the same batched step and build + query API as the headline.  The
     paper's own per-event times on its GPU are quoted as context only."""
     import torch
     from paper_2609_31980_amd import inputs
     w = inputs.paper_shaped()
     x = torch.from_numpy(w.points).cuda()
 
-    def step_graph():
+    def step_batch():
         c = frnn.query_batch([x], w.r, w.K, exclude_self=True)[0]
         n = c.nnz
         c.release()
@@ -271,15 +282,15 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
         ix.close()
         return n
 
-    dt, nnz = time_steps(step_graph, steps, warmup)
+    dt, nnz = time_steps(step_batch, steps, warmup)
     stats = frnn.last_stats()
     dt_api, nnz_api = time_steps(step_api, steps, warmup)
     assert nnz_api == nnz
-    # per-launch HIP events (eager launches) for the kernel durations
+    # per-launch HIP events for the kernel durations
     frnn.profile_enable(True)
     frnn.profile_read(reset=True)
     for _ in range(5):
-        step_graph()
+        step_batch()
     sync()
     prof = frnn.profile_read(reset=True)
     frnn.profile_enable(False)
@@ -314,11 +325,16 @@ def bench_batched(frnn, rounds=30, tuned=None):
             ix.close()
         return outs
 
-    def per_event_graph():
+    og = frnn.default_opts(graphs=1)
+
+    def per_event_batch_call():
         return [frnn.query_batch([x], r, K)[0] for x in xs]
 
     def batched():
         return frnn.query_batch(xs, r, K)
+
+    def batched_graphs():
+        return frnn.query_batch(xs, r, K, opts=og)
 
     def batched_tuned():
         return frnn.query_batch(xs, r, K, opts=tuned)
@@ -335,7 +351,15 @@ def bench_batched(frnn, rounds=30, tuned=None):
         o.release()
     del a, b
     sync()
-    fns = {"per_event": per_event, "per_event_graph": per_event_graph, "batched": batched}
+    c = batched_graphs()
+    for e in range(len(xs)):   # graph replay == default batched output, event by event
+        ob, ib, db = c[e].torch()
+        oa, ia, da = frnn.query_batch([xs[e]], r, K)[0].torch()
+        assert torch.equal(oa, ob) and torch.equal(ia, ib) and torch.equal(da.view(torch.int32), db.view(torch.int32))
+    for o in c:
+        o.release()
+    fns = {"per_event": per_event, "per_event_batch_call": per_event_batch_call, "batched": batched,
+           "batched_graphs": batched_graphs}
     if tuned is not None:
         c = batched_tuned()
         for e in range(len(xs)):   # tuned == default batched output, event by event
@@ -353,30 +377,34 @@ def bench_batched(frnn, rounds=30, tuned=None):
             run(fn)()
     times = paired_rounds({k: run(f) for k, f in fns.items()}, rounds=rounds)
     E = len(xs)
-    tp, tg, tb = (float(np.median(times[k])) for k in ("per_event", "per_event_graph", "batched"))
+    tp, tg, tb, tbg = (float(np.median(times[k]))
+                       for k in ("per_event", "per_event_batch_call", "batched", "batched_graphs"))
     ms = {k: {kk: (v * 1e3 if kk == "median" else [u * 1e3 for u in v] if kk == "ci95" else v)
               for kk, v in boot_ci(times[k]).items()} for k in fns}
     res = {"events": E, "points": npts, "pairs": nnz,
-           "per_event_ms": tp * 1e3, "per_event_graph_ms": tg * 1e3, "batched_ms": tb * 1e3,
-           "per_event_events_per_s": E / tp, "per_event_graph_events_per_s": E / tg,
+           "per_event_ms": tp * 1e3, "per_event_batch_call_ms": tg * 1e3, "batched_ms": tb * 1e3,
+           "batched_graphs_ms": tbg * 1e3,
+           "per_event_events_per_s": E / tp, "per_event_batch_call_events_per_s": E / tg,
            "batched_events_per_s": E / tb, "batched_pairs_per_s": nnz / tb,
-           "speedup_vs_per_event": tp / tb, "speedup_vs_per_event_graph": tg / tb,
+           "speedup_vs_per_event": tp / tb, "speedup_vs_per_event_batch_call": tg / tb,
            "ms_median_ci95": ms,
            "sign_test_per_event_vs_batched": sign_test(times["per_event"], times["batched"]),
-           "sign_test_per_event_graph_vs_batched": sign_test(times["per_event_graph"], times["batched"]),
+           "sign_test_per_event_batch_call_vs_batched": sign_test(times["per_event_batch_call"], times["batched"]),
+           "sign_test_batched_vs_graphs": sign_test(times["batched"], times["batched_graphs"]),
            **({"batched_tuned_ms": float(np.median(times["batched_tuned"])) * 1e3,
                "batched_tuned_events_per_s": E / float(np.median(times["batched_tuned"])),
                "tuned_options": tuned.as_dict(),
                "sign_test_batched_vs_tuned": sign_test(times["batched"], times["batched_tuned"])}
               if tuned is not None else {}),
-           "protocol": f"10 warm-up rounds, then {rounds} rounds each timing the three paths once in a seeded "
+           "protocol": f"10 warm-up rounds, then {rounds} rounds each timing every path once in a seeded "
                        "random order, synchronised before and after each call; medians with 95% percentile "
                        "bootstrap intervals (10,000 resamples); exact two-sided sign tests",
            "identical_output": "batched == per-event API on the device, every event; every event also equals "
                                "the CPU oracle's CSR in the GPU tests (stored digests)",
            "per_event": "64 x (build + query API calls)",
-           "per_event_graph": "64 x single-event graph-replayed calls",
-           "batched": "one graph-replayed launch sequence over all 64 events"}
+           "per_event_batch_call": "64 x single-event batched calls",
+           "batched": "one launch sequence over all 64 events (kernels launched one by one)",
+           "batched_graphs": "the same launch sequence replayed as HIP graphs (graphs option)"}
     del xs
     torch.cuda.empty_cache()
     return res
@@ -650,7 +678,7 @@ def main():
     x = torch.from_numpy(w.points).cuda()
     D = w.points.shape[1]
     log("single event: timing")
-    dt, dt_api, nnz, stats, prof = bench_single(frnn, x, w.r, w.K, args.steps, args.warmup)
+    dt, dt_graph, dt_api, nnz, stats, prof = bench_single(frnn, x, w.r, w.K, args.steps, args.warmup)
     ms = dt / args.steps * 1e3
     kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1), "total_ms": v[1]} for k, v in prof.items()}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
@@ -697,6 +725,9 @@ def main():
                                   "K=256, queries = references", "N": 300000, "D": 8, "r": 0.1, "K": 256,
                       "parallelism": "1 GPU"},
            "events_per_s": args.steps / dt, "pairs_per_step": nnz,
+           "graphs_option": {"ms_per_step": dt_graph / args.steps * 1e3,
+                             "pairs_per_s": nnz * args.steps / dt_graph,
+                             "note": "the same step with its launch sequence replayed as a HIP graph"},
            "api_build_query": {"ms_per_step": dt_api / args.steps * 1e3,
                                "pairs_per_s": nnz * args.steps / dt_api,
                                "events_per_s": args.steps / dt_api},

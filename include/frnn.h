@@ -91,6 +91,9 @@ typedef struct {
     int32_t row_cap_lds;      /* rows longer than this sort in global memory (1..512) */
     int32_t stash_cap;        /* hits per query kept by the count pass (0, 8, 16, 32, 64, 128; default 64);
                                  the fill pass only re-evaluates rows longer than this */
+    int32_t graphs;           /* batched calls: 1 replays each launch sequence as a HIP graph
+                                 (recorded once per context), 0 (default) launches the kernels
+                                 one by one, which reached the first kernel sooner here */
 } frnn_opts;
 
 void frnn_opts_default(frnn_opts *opts);
@@ -143,9 +146,10 @@ typedef struct {
  * filled by single launches over all events (work items are windows of
  * sorted queries, i.e. runs of cell blocks of one event; with
  * opts->persistent the resident waves drain them from a per-XCD queue,
- * costliest events first), the fixed pipeline is replayed as a HIP graph
- * when the same capacity recurs, and outs[e] is bit-identical to querying
- * event e alone.
+ * costliest events first), the fixed launch sequence of a capacity class is
+ * launched kernel by kernel or, with opts->graphs, recorded once as HIP
+ * graphs and replayed when the same capacity recurs, and outs[e] is
+ * bit-identical to querying event e alone.
  * All events share D, r, K and flags.  The host waits once, for the counts
  * (published by the device into host-mapped memory); the fill may still be
  * running on the stream when the call returns, so the outputs are ready in
@@ -299,10 +303,10 @@ frnn_status frnn_server_memory(frnn_server s, int64_t *held_bytes, int64_t *peak
 void frnn_server_destroy(frnn_server s);
 
 /* ---------------------------------------------------------------- tuning
- * Times candidate frnn_opts on the given input (a batched self-query with K,
- * the graph-replayed path) by coordinate descent over the grid axes, cells
- * per point, cells and queries per work item, stash size and persistent
- * launch, and returns the fastest whose output is bit-identical to the
+ * Times candidate frnn_opts on the given input (a batched self-query with K)
+ * by coordinate descent over the grid axes, cells per point, cells and
+ * queries per work item, stash size, persistent launch, blocks per CU and
+ * graph replay, and returns the fastest whose output is bit-identical to the
  * default's.  The result is cached per (device, D, K, density class) in the
  * JSON file named by FRNN_TUNE_CACHE, if set; the density class is the pair
  * of half-octaves of the mean candidates and mean neighbours per query of

@@ -1,4 +1,5 @@
-// Batched pipeline with HIP-graph replay (see frnn_batch.h).
+// Batched pipeline, launched kernel by kernel or replayed as HIP graphs (see
+// frnn_batch.h).
 #include "frnn_batch.h"
 
 #include <hip/hip_runtime.h>
@@ -134,6 +135,7 @@ int64_t BatchContext::device_bytes() const {
 }
 
 BatchContext::BatchContext(const Shape &sh, hipStream_t s) : sh_(sh) {
+    graphs_enabled = sh.o.graphs != 0;
     const int D = sh.D;
     Dp_ = (D + 3) & ~3;
     const bool selfq = sh.flags & FRNN_SELF_QUERY;
@@ -435,7 +437,7 @@ void BatchContext::phase_ab(bool with_long, hipStream_t s) {
 void BatchContext::fetch_counts(hipStream_t s) { last_s_ = s; }
 
 // Waits until the read-back block carries this run's number: polls the
-// flag word (the last store of graph A) for a while, then also asks the
+// flag word (the last store of phase A) for a while, then also asks the
 // stream, which fails on a device error and goes idle without the flag
 // only if the run did not publish.
 BatchCounts BatchContext::wait_counts() {
@@ -614,7 +616,7 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
         // the output owner is freed here unless handed out
         std::unique_ptr<OutputOwner> own(bo.own);
         bo.own = nullptr;
-        // with a guessed output the fill is in the same graph as the count
+        // with a guessed output the fill is launched with the count
         // (its long-row part only when the previous run had long rows; else
         // after the counts, if needed: the two parts write different rows);
         // a fill whose output turns out too small writes nothing

@@ -3,19 +3,21 @@
 // A BatchContext owns device buffers sized for a capacity class (events,
 // points, queries, cells, chunks; rounded up so that similar batches share a
 // class).  Its launch sequence has fixed grid sizes and reads every actual
-// size from device memory, so it is recorded once as HIP graphs (built node
-// by node, no stream capture) and replayed for any batch of its class:
-//   graph A: bin the points of every event, count every query's neighbours,
+// size from device memory, so it is launched kernel by kernel (the default)
+// or, with the graphs option, recorded once as HIP graphs (built node by
+// node, no stream capture) and replayed for any batch of its class:
+//   phase A: bin the points of every event, count every query's neighbours,
 //            scan the capped counts, and publish the counters and event
 //            bases to a host-mapped block (then a flag the host polls)
-//   graph B: short rows and per-event offsets; then, only when some row is
+//   phase B: short rows and per-event offsets; then, only when some row is
 //            longer than the stash, the fill pass and the long-row sort
 // Run exactly, A and B are separated by the read-back that sizes the output.
 // Once a context has run, its next batch is run speculatively instead: the
 // output is allocated at a capacity guessed from the previous run, and A
-// and B are one graph, so the host checks the counts while B runs; the fill
-// kernels write nothing when the run does not fit, and only then does the
-// host allocate the exact size and replay B.
+// and B are launched together (one graph when replayed), so the host checks
+// the counts while B runs; the fill kernels write nothing when the run does
+// not fit, and only then does the host allocate the exact size and run B
+// again.
 // The count and fill kernels take windows of sorted queries (runs of cell
 // blocks of one event) as work items: one wave per window from the
 // hardware's dispatch, or, persistent (frnn_opts.persistent), a resident
@@ -71,17 +73,17 @@ public:
     void prepare(const frnn_event *ev, int E);
     void upload(hipStream_t s, const OutDesc *od);
     // 2. bin + count + scan, and the counters and event bases written to
-    //    the host-mapped read-back block (graph A)
+    //    the host-mapped read-back block (phase A)
     void phase_a(hipStream_t s);
-    // 2+4. graph A followed by the short rows (and the long rows) in one
-    //    graph, for a run whose output was allocated from a guess
+    // 2+4. phase A followed by the short rows (and the long rows) in one
+    //    sequence, for a run whose output was allocated from a guess
     void phase_ab(bool with_long, hipStream_t s);
     // 3. wait for phase A's read-back and read the counters (fetch_counts
     //    notes the stream, wait_counts polls the block's run number)
     BatchCounts read_counts(hipStream_t s);
     void fetch_counts(hipStream_t s);
     BatchCounts wait_counts();
-    // 4. fill into the given output (graph B: the short rows, then, when
+    // 4. fill into the given output (phase B: the short rows, then, when
     //    some row is longer than the stash, the long rows); the parts alone
     //    fill into the output descriptor given to upload
     void phase_b(const OutDesc &od, bool long_rows, hipStream_t s);
@@ -109,7 +111,7 @@ public:
     const std::vector<int64_t> &q_off() const { return qoff_; }
     const std::vector<int64_t> &n_q() const { return nq_; }
     int64_t total_q() const { return totq_; }
-    bool graphs_enabled = true;
+    bool graphs_enabled = false;  // the shape's graphs option (cleared if recording fails)
     int replays = 0;
 
 private:
@@ -130,7 +132,7 @@ private:
     DevBuf desc, hv, grid, cell_off, ext, xs, perm, key, rank,
         skey, cells, qs, qperm, qkey, qrank, sqkey, qcells, runs, deg, offs, lofs, lrows, lat, stash, flist, part,
         lpt;
-    MappedHost back_;  // read-back block, written by the last kernel of graph A
+    MappedHost back_;  // read-back block, written by the last kernel of phase A
     size_t hv16_ = 0;  // its size in 16-byte words
     MappedHost stage_;            // descriptors, host side, read by the first kernel
     size_t stage_cap_ = 0;        // bytes, the capacity of the descriptor block

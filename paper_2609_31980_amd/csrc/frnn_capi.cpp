@@ -79,6 +79,7 @@ void frnn_opts_default(frnn_opts *o) {
     o->blocks_per_cu = 8;
     o->row_cap_lds = kRowLds;
     o->stash_cap = 64;
+    o->graphs = 0;
 }
 
 const char *frnn_status_str(frnn_status s) {

@@ -336,6 +336,7 @@ frnn_status Opts::validate(std::string *why) const {
     if (o.stash_cap != 0 && o.stash_cap != 8 && o.stash_cap != 16 && o.stash_cap != 32 && o.stash_cap != 64 &&
         o.stash_cap != 128)
         return bad("stash_cap must be 0, 8, 16, 32, 64 or 128");
+    if (o.graphs != 0 && o.graphs != 1) return bad("graphs must be 0 or 1");
     return FRNN_OK;
 }
 

@@ -90,16 +90,16 @@ std::string cache_key(int D, int K, double cand_per_query, double pairs_per_quer
 
 const char *kFields[] = {"grid_axes_max", "cells_per_point", "cell_multiple", "cells_per_item",
                          "queries_per_item", "persistent", "blocks_per_cu", "row_cap_lds",
-                         "stash_cap"};
+                         "stash_cap", "graphs"};
 
 std::string opts_json(const frnn_opts &o) {
     char buf[512];
     std::snprintf(buf, sizeof buf,
                   "{\"grid_axes_max\": %d, \"cells_per_point\": %.9g, \"cell_multiple\": %d, "
                   "\"cells_per_item\": %d, \"queries_per_item\": %d, \"persistent\": %d, "
-                  "\"blocks_per_cu\": %d, \"row_cap_lds\": %d, \"stash_cap\": %d}",
+                  "\"blocks_per_cu\": %d, \"row_cap_lds\": %d, \"stash_cap\": %d, \"graphs\": %d}",
                   o.grid_axes_max, (double)o.cells_per_point, o.cell_multiple, o.cells_per_item,
-                  o.queries_per_item, o.persistent, o.blocks_per_cu, o.row_cap_lds, o.stash_cap);
+                  o.queries_per_item, o.persistent, o.blocks_per_cu, o.row_cap_lds, o.stash_cap, o.graphs);
     return buf;
 }
 
@@ -140,6 +140,7 @@ std::map<std::string, frnn_opts> read_cache(const std::string &path) {
             else if (!std::strcmp(fld, "blocks_per_cu")) o.blocks_per_cu = (int)v;
             else if (!std::strcmp(fld, "row_cap_lds")) o.row_cap_lds = (int)v;
             else if (!std::strcmp(fld, "stash_cap")) o.stash_cap = (int)v;
+            else if (!std::strcmp(fld, "graphs")) o.graphs = (int)v;
         }
         if (ok) m[key] = o;
         p = b1 + 1;
@@ -205,6 +206,7 @@ extern "C" frnn_status frnn_tune(const float *points, int64_t N, int32_t D, floa
         const int stashes[] = {0, 8, 16, 32, 64, 128};
         const int pers[] = {0, 1, 2};
         const int bpcs[] = {4, 8, 16};
+        const int graphs[] = {0, 1};
         auto consider = [&](frnn_opts cand) {
             if (std::memcmp(&cand, &cur, sizeof cand) == 0) return;
             Opts oo = Opts::from(&cand);
@@ -255,6 +257,11 @@ extern "C" frnn_status frnn_tune(const float *points, int64_t N, int32_t D, floa
         for (int v : bpcs) {
             frnn_opts c = cur;
             c.blocks_per_cu = v;
+            consider(c);
+        }
+        for (int v : graphs) {
+            frnn_opts c = cur;
+            c.graphs = v;
             consider(c);
         }
         *best = cur;

@@ -40,10 +40,11 @@ def test_batch_matches_oracle_and_single(orc, frnn):
 def test_batch_graph_replay_varies_inputs(orc, frnn):
     """The graph of a capacity class replays for different batches of it."""
     import torch
+    og = frnn.default_opts(graphs=1)
     for rep, seed in enumerate((50, 51, 52)):
         sizes = [4000 + 500 * rep, 2500, 6000 - 300 * rep]
         evs = [inputs.tracks(n, 8, seed=seed * 10 + i) for i, n in enumerate(sizes)]
-        outs = frnn.query_batch([dev(e) for e in evs], 0.1, 8)
+        outs = frnn.query_batch([dev(e) for e in evs], 0.1, 8, opts=og)
         torch.cuda.synchronize()
         for e, (x, o) in enumerate(zip(evs, outs)):
             pinlib.assert_csr_equal(_np(o), pinlib.as_tuple(orc.frnn(x, 0.1, 8)), f"replay {rep} event {e}")
@@ -67,17 +68,23 @@ def test_batch_separate_queries_and_exclusion(orc, frnn):
 
 
 def test_batch_eager_equals_graph(frnn):
-    """Per-launch timing forces eager launches; outputs must not change."""
+    """Graph replay (twice: recorded, then replayed), eager launches (the
+    default) and eager launches timed one by one give the same outputs."""
     evs = [inputs.tracks(n, 8, seed=80 + n) for n in (5000, 9000)]
-    a = [_np(o) for o in frnn.query_batch([dev(e) for e in evs], 0.1, 256)]
+    og = frnn.default_opts(graphs=1)
+    a = [_np(o) for o in frnn.query_batch([dev(e) for e in evs], 0.1, 256, opts=og)]
+    a2 = [_np(o) for o in frnn.query_batch([dev(e) for e in evs], 0.1, 256, opts=og)]
+    b = [_np(o) for o in frnn.query_batch([dev(e) for e in evs], 0.1, 256)]
     frnn.profile_enable(True)
     try:
-        b = [_np(o) for o in frnn.query_batch([dev(e) for e in evs], 0.1, 256)]
+        c = [_np(o) for o in frnn.query_batch([dev(e) for e in evs], 0.1, 256)]
     finally:
         frnn.profile_enable(False)
         frnn.profile_read()
-    for x, y in zip(a, b):
+    for x, x2, y, z in zip(a, a2, b, c):
+        pinlib.assert_csr_equal(x, x2, "graph recorded vs replayed")
         pinlib.assert_csr_equal(x, y, "graph vs eager")
+        pinlib.assert_csr_equal(x, z, "graph vs timed eager")
 
 
 def test_batch_rejects_nonfinite(frnn):
@@ -224,20 +231,14 @@ def test_batch_speculative_output_overflow(orc, frnn):
     want = {"sparse": pinlib.as_tuple(orc.frnn(sparse, r, 0)), "dense": pinlib.as_tuple(orc.frnn(dense, r, 0))}
     assert len(want["dense"][1]) > 20 * len(want["sparse"][1])
     assert np.diff(want["dense"][0]).max() > 512  # rows sorted in global memory
-    for eager in (False, True):
-        if eager:
-            frnn.profile_enable(True)
-        try:
-            for name in ("sparse", "dense", "dense", "sparse", "dense"):
-                x = sparse if name == "sparse" else dense
-                say(f"speculative batch {name} eager={eager}")
-                o = frnn.query_batch([dev(x)], r, 0)[0]
-                pinlib.assert_csr_equal(_np(o), want[name], f"{name} eager={eager}")
-                o.release()
-        finally:
-            if eager:
-                frnn.profile_enable(False)
-                frnn.profile_read()
+    for graphs in (1, 0):
+        o_g = frnn.default_opts(graphs=graphs)
+        for name in ("sparse", "dense", "dense", "sparse", "dense"):
+            x = sparse if name == "sparse" else dense
+            say(f"speculative batch {name} graphs={graphs}")
+            o = frnn.query_batch([dev(x)], r, 0, opts=o_g)[0]
+            pinlib.assert_csr_equal(_np(o), want[name], f"{name} graphs={graphs}")
+            o.release()
 
 
 def test_batch_long_rows_after_short_run(orc, frnn):
@@ -248,6 +249,7 @@ def test_batch_long_rows_after_short_run(orc, frnn):
     stash."""
     n, r = 6000, 0.0625
     o32 = frnn.default_opts(stash_cap=32)
+    o32g = frnn.default_opts(stash_cap=32, graphs=1)
     short = inputs.tracks(n, 8, track_size=20, sigma=0.002, noise_frac=0.0, seed=95)
     rng = np.random.default_rng(96)
     # two clusters of 40: 80 rows of 40 keys, 3,200 long-row keys (within the
@@ -260,17 +262,10 @@ def test_batch_long_rows_after_short_run(orc, frnn):
     assert np.diff(want["short"][0]).max() <= 32 < dm.max()
     assert dm[dm > 32].sum() <= 4096
     assert len(want["mixed"][1]) < len(want["short"][1])  # fits the capacity learned from "short"
-    for eager in (False, True):
-        if eager:
-            frnn.profile_enable(True)
-        try:
-            for name in ("short", "mixed", "short", "mixed", "mixed"):
-                x = short if name == "short" else mixed
-                say(f"long rows after short run: {name} eager={eager}")
-                o = frnn.query_batch([dev(x)], r, 0, opts=o32)[0]
-                pinlib.assert_csr_equal(_np(o), want[name], f"{name} eager={eager}")
-                o.release()
-        finally:
-            if eager:
-                frnn.profile_enable(False)
-                frnn.profile_read()
+    for graphs, oo in ((1, o32g), (0, o32)):
+        for name in ("short", "mixed", "short", "mixed", "mixed"):
+            x = short if name == "short" else mixed
+            say(f"long rows after short run: {name} graphs={graphs}")
+            o = frnn.query_batch([dev(x)], r, 0, opts=oo)[0]
+            pinlib.assert_csr_equal(_np(o), want[name], f"{name} graphs={graphs}")
+            o.release()

@@ -57,18 +57,18 @@ def batch64():
     return inputs.c3_events()
 
 
-@pytest.mark.parametrize("persistent", [0, 1], ids=["grid", "persistent"])
-def test_batch64_every_event_bit_exact(orc, frnn, batch64, persistent):
-    """All 64 events (about 14.4 million points) in one batched call, twice
-    (the second run replays the captured graphs), every event's CSR equal to
-    the oracle's; with the default launch and with the persistent work
-    queue."""
+@pytest.mark.parametrize("persistent,graphs", [(0, 0), (1, 1)], ids=["grid", "persistent-graphs"])
+def test_batch64_every_event_bit_exact(orc, frnn, batch64, persistent, graphs):
+    """All 64 events (about 14.4 million points) in one batched call, twice,
+    every event's CSR equal to the oracle's: with the default launch
+    (kernels launched one by one), and with the persistent work queue
+    replayed as HIP graphs (the second run replays the recorded graphs)."""
     import torch
     want = load("batch64_hashes.json", 64)
     xs = [dev(x) for x in batch64]
-    opts = frnn.default_opts(persistent=persistent)
+    opts = frnn.default_opts(persistent=persistent, graphs=graphs)
     for rep in range(2):
-        say(f"batch of 64 (persistent={persistent}): run {rep}")
+        say(f"batch of 64 (persistent={persistent}, graphs={graphs}): run {rep}")
         outs = frnn.query_batch(xs, R, K, opts=opts)
         for e, o in enumerate(outs):
             check_event(orc, batch64[e], o.numpy(), want[e], f"batch64 event {e} run {rep}")
@@ -105,15 +105,17 @@ def test_stream40_served_events_bit_exact(orc, frnn):
 
 def test_stream40_served_under_tight_budget_bit_exact(orc, frnn):
     """The same stream under a 512 MiB budget with two workers: admission
-    waits, idle workers drop their contexts and new ones are captured into
-    graphs while the other worker runs and the client copies and releases
-    results; every served CSR still equals the oracle's."""
+    waits, idle workers drop their contexts and new ones are recorded into
+    graphs (the graphs option) while the other worker runs and the client
+    copies and releases results; every served CSR still equals the
+    oracle's."""
     want = load("stream40_hashes.json", 40)
     tr = inputs.c5_trace(40, rate=1.0)
     say("stream of 40, tight budget: generating")
     evs = [inputs.c5_event(a) for a in tr]
     budget = 512 << 20
-    srv = frnn.Server(8, R, K, hbm_budget_bytes=budget, max_batch_events=64, max_inflight=2)
+    srv = frnn.Server(8, R, K, hbm_budget_bytes=budget, max_batch_events=64, max_inflight=2,
+                      opts=frnn.default_opts(graphs=1))
     try:
         tickets = [srv.submit(x) for x in evs]
         batches = set()

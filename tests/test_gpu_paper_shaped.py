@@ -45,13 +45,15 @@ def test_paper_shaped_full_size(orc, frnn):
 
 
 def test_paper_shaped_batched_matches_single(frnn):
-    """The same event through the batched graph path gives the same CSR."""
+    """The same event through the batched path (the default launches, then
+    replayed as HIP graphs) gives the same CSR."""
     import torch
     w = inputs.paper_shaped()
     single = gpu_csr(w.points, w.r, w.K, exclude_self=True)
     x = torch.from_numpy(w.points).cuda()
-    c = frnn.query_batch([x], w.r, w.K, exclude_self=True)[0]
-    off, idx, d2 = c.numpy()
-    c.release()
-    assert np.array_equal(off, single[0]) and np.array_equal(idx, single[1])
-    assert np.array_equal(d2.view(np.uint32), single[2].view(np.uint32))
+    for graphs in (0, 1, 1):
+        c = frnn.query_batch([x], w.r, w.K, exclude_self=True, opts=frnn.default_opts(graphs=graphs))[0]
+        off, idx, d2 = c.numpy()
+        c.release()
+        assert np.array_equal(off, single[0]) and np.array_equal(idx, single[1]), f"graphs={graphs}"
+        assert np.array_equal(d2.view(np.uint32), single[2].view(np.uint32)), f"graphs={graphs}"

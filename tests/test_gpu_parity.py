@@ -190,9 +190,11 @@ def test_radius_above_index(frnn):
 def test_tracking_event_300k(orc, frnn):
     """The 300,000-point tracking event at full size, every row against the
     oracle's complete CSR (offsets, indices and dist2 bits), through the
-    eager build + query calls and through the batched graph path the
-    benchmark times (run twice, so the second run replays its graphs), plus
-    properties that hold at any size."""
+    eager build + query calls, through the batched path the benchmark times
+    (kernels launched one by one, run twice: the second run sizes its output
+    from the first) and through the same path replayed as HIP graphs (run
+    twice: recorded, then replayed), plus properties that hold at any
+    size."""
     import torch
     w = inputs.c2()
     say("tracks-300k: oracle, all 300,000 rows")
@@ -202,11 +204,13 @@ def test_tracking_event_300k(orc, frnn):
     check_csr_invariants(got, len(w.points), w.K)
     pinlib.assert_csr_equal(got, want, "tracks-300k eager API")
     xd = dev(w.points)
-    for rep in range(2):
-        say(f"tracks-300k: GPU, graph path run {rep}")
-        c = frnn.query_batch([xd], w.r, w.K)[0]
-        pinlib.assert_csr_equal(c.numpy(), want, f"tracks-300k graph path run {rep}")
-        c.release()
+    for graphs in (0, 1):
+        og = frnn.default_opts(graphs=graphs)
+        for rep in range(2):
+            say(f"tracks-300k: GPU, batched path graphs={graphs} run {rep}")
+            c = frnn.query_batch([xd], w.r, w.K, opts=og)[0]
+            pinlib.assert_csr_equal(c.numpy(), want, f"tracks-300k batched graphs={graphs} run {rep}")
+            c.release()
     torch.cuda.synchronize()
     # K=256 never binds here (max degree ~ 12): the relation is symmetric
     off, idx, d2 = got
@@ -271,7 +275,7 @@ def test_stash_sizes_rows_of_every_length(orc, frnn):
 def test_unaligned_point_arrays(orc, frnn, D):
     """Point arrays that start off a 16-byte boundary (a view one float into
     its storage) take the scalar row loads and give the same lists, through
-    the eager API and the batched graph path."""
+    the eager API and the batched path replayed as HIP graphs."""
     import torch
     X = inputs.tracks(5000, D, seed=300 + D)
     Q = inputs.tracks(700, D, seed=400 + D)
@@ -292,11 +296,12 @@ def test_unaligned_point_arrays(orc, frnn, D):
         pinlib.assert_csr_equal(c.numpy(), w, f"unaligned D={D} api {what}")
         c.release()
     ix.close()
+    og = frnn.default_opts(graphs=1)
     for _ in range(2):  # the second run replays the graphs
-        o = frnn.query_batch([xd], 0.1, 32)[0]
+        o = frnn.query_batch([xd], 0.1, 32, opts=og)[0]
         pinlib.assert_csr_equal(o.numpy(), want, f"unaligned D={D} batch self")
         o.release()
-        o = frnn.query_batch([xd], 0.1, 32, queries=[qd])[0]
+        o = frnn.query_batch([xd], 0.1, 32, queries=[qd], opts=og)[0]
         pinlib.assert_csr_equal(o.numpy(), want_q, f"unaligned D={D} batch queries")
         o.release()
     torch.cuda.synchronize()
