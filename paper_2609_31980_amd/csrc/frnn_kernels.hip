@@ -917,39 +917,33 @@ __device__ __forceinline__ uint64_t xor_lane64(uint64_t v, int j) {
     return ((uint64_t)xor_lane32((uint32_t)(v >> 32), j) << 32) | xor_lane32((uint32_t)v, j);
 }
 
-// Sorts the n <= 64*KS keys h[0..n) of one row ascending with a bitonic
-// network held by the wave and writes the first keep.  Lane i holds
-// elements KS*i .. KS*i + KS-1 in registers 0..KS-1 (slots past n hold
-// all-ones keys, which compare above every key of a row and stay at the
-// end), so a compare-exchange whose partner distance j is below KS pairs two
-// registers of one lane and only the 21 stages with j >= KS read another
-// lane (lane i ^ j/KS, the same register).  After the network element e is
-// the row's e-th smallest key, and the first keep are written in order.
-template <int KS>
-__device__ __forceinline__ void sort_and_write(const uint64_t *h, uint32_t n, uint32_t keep, int32_t *idx,
-                                               float *d2, int lane) {
-    uint64_t v[KS];
-#pragma unroll
-    for (int k = 0; k < KS; ++k) {
-        const uint32_t e = (uint32_t)(lane * KS + k);
-        v[k] = e < n ? h[e] : ~0ull;
-    }
+// Sorts R independent sets of the wave's 64*KS keys ascending with a
+// bitonic network, stage by stage for all R (independent work in flight
+// while each cross-lane move completes): lane i holds elements
+// KS*i .. KS*i + KS-1 of set r in v[r][0..KS-1], so a compare-exchange whose
+// partner distance j is below KS pairs two registers of one lane and only
+// the 21 stages with j >= KS read another lane (lane i ^ j/KS, the same
+// register).  Afterwards element e of each set is its e-th smallest key.
+template <int KS, int R>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&v)[R][KS], int lane) {
 #pragma unroll
     for (int kk = 2; kk <= 64 * KS; kk <<= 1) {
 #pragma unroll
         for (int j = kk >> 1; j > 0; j >>= 1) {
             if (j < KS) {
 #pragma unroll
-                for (int k = 0; k < KS; ++k) {
-                    const int l = k ^ j;
-                    if (l > k) {
-                        const bool asc = (((lane * KS) | k) & kk) == 0;
-                        const uint64_t a = v[k], c = v[l];
-                        const bool sw = asc ? (c < a) : (a < c);
-                        v[k] = sw ? c : a;
-                        v[l] = sw ? a : c;
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int k = 0; k < KS; ++k) {
+                        const int l = k ^ j;
+                        if (l > k) {
+                            const bool asc = (((lane * KS) | k) & kk) == 0;
+                            const uint64_t a = v[r][k], c = v[r][l];
+                            const bool sw = asc ? (c < a) : (a < c);
+                            v[r][k] = sw ? c : a;
+                            v[r][l] = sw ? a : c;
+                        }
                     }
-                }
             } else {
                 const int jl = j / KS;
                 // kk > j >= KS: the direction bit is in the lane number
@@ -958,20 +952,37 @@ __device__ __forceinline__ void sort_and_write(const uint64_t *h, uint32_t n, ui
                 // the lower element of an ascending pair keeps the minimum
                 const bool take_min = lower == asc;
 #pragma unroll
-                for (int k = 0; k < KS; ++k) {
-                    const uint64_t p = xor_lane64(v[k], jl);
-                    const bool less = p < v[k];
-                    v[k] = (less == take_min) ? p : v[k];
-                }
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int k = 0; k < KS; ++k) {
+                        const uint64_t p = xor_lane64(v[r][k], jl);
+                        const bool less = p < v[r][k];
+                        v[r][k] = (less == take_min) ? p : v[r][k];
+                    }
             }
         }
     }
+}
+
+// Sorts the n <= 64*KS keys h[0..n) of one row (slots past n hold all-ones
+// keys, which compare above every key of a row and stay at the end) and
+// writes the first keep in order, coalesced.
+template <int KS>
+__device__ __forceinline__ void sort_and_write(const uint64_t *h, uint32_t n, uint32_t keep, int32_t *idx,
+                                               float *d2, int lane) {
+    uint64_t v[1][KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const uint32_t e = (uint32_t)(lane * KS + k);
+        v[0][k] = e < n ? h[e] : ~0ull;
+    }
+    wave_bitonic<KS, 1>(v, lane);
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const uint32_t e = (uint32_t)(lane * KS + k);
         if (e < keep) {
-            idx[e] = (int32_t)(uint32_t)v[k];
-            if (d2) d2[e] = __uint_as_float((uint32_t)(v[k] >> 32));
+            idx[e] = (int32_t)(uint32_t)v[0][k];
+            if (d2) d2[e] = __uint_as_float((uint32_t)(v[0][k] >> 32));
         }
     }
 }
@@ -1515,16 +1526,16 @@ __device__ __forceinline__ void sort_regs(uint64_t (&v)[N]) {
 // Every row's per-event offset, and the rows the count pass kept whole
 // (0 < length <= SC): one lane per query row, in output order, sorts the
 // row's keys in registers (rows of up to 16 keys); rows of 17..SC keys (the
-// 32-, 64- and 128-key stashes) are ranked by the whole wave.  The query chunks partition
+// 32-, 64- and 128-key stashes) are sorted by the whole wave with the
+// bitonic network of the long-row sort.  The query chunks partition
 // each event's rows, so
 // chunk c covers global rows r0..r1-1 of one event and its output is the
 // contiguous range offs[r0]..offs[r1]; one block per chunk.  When that range
 // fits in LDS the rows are assembled there and written out coalesced; the
 // places of longer rows receive filler that the fill pass, which runs later
 // on the same stream, overwrites.
-// Staged output pairs per block: with the mid-row list and the four rank
-// buffers (64 keys each, 128 for the 128-key stash) the block stays within
-// 32 KB of LDS (five blocks per CU).
+// Staged output pairs per block: with the mid-row list the block stays
+// within 32 KB of LDS (five blocks per CU).
 constexpr int short_stage(int sc) { return sc > 64 ? kChunkRows * 27 / 2 : kChunkRows * 29 / 2; }
 
 template <int N>
@@ -1552,13 +1563,11 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
     // rows of up to LM keys: one lane per row; longer stash rows (up to SC):
     // one wave per row, ranked
     constexpr int LM = SC < 16 ? SC : 16;
-    constexpr int KP = SC > 64 ? 2 : 1;  // keys per lane in the wave rank
     constexpr int kShortStage = short_stage(SC);
     __shared__ uint32_t sidx[SC > 0 ? kShortStage : 1];
     __shared__ float sd2[SC > 0 ? kShortStage : 1];
     __shared__ uint16_t s_mid[SC > LM ? kChunkRows : 1];  // rows of LM+1..SC keys
-    __shared__ __align__(16) uint64_t s_rank[SC > LM ? kChunkRows / 64 : 1][64 * KP];  // one row per wave
-    __shared__ uint32_t s_nmid;
+    __shared__ uint32_t s_nmid, s_nbig;
     if (!out_fits(b)) return;
     if (blockIdx.x == 0)  // each event's leading offset, the one entry no row writes
         for (int e = threadIdx.x; e < b.bd->E; e += blockDim.x) b.out->offsets[b.ev[e].q_off + e] = 0;
@@ -1614,91 +1623,97 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
             }
         }
         if constexpr (SC > LM) {
-            // stash rows of LM+1..SC keys: the block lists them in LDS and its
-            // waves take them in turn (a block of dense rows keeps all four
-            // busy); a wave ranks one row at a time, lane i holding keys i
-            // (and 64 + i for the 128-key stash) and counting the smaller
-            // keys of the row from LDS broadcasts, eight a step (keys of a
-            // row are distinct, so the counts are places)
+            // stash rows of LM+1..SC keys: the block lists them in LDS (rows
+            // of up to 64 keys from the front of the list, longer ones from
+            // the back) and its waves take them in turn, RB at a time (a
+            // block of dense rows keeps all four busy); lane i holds keys
+            // KS*i .. KS*i + KS-1 of each row (KS = 1 up to 64 keys, else 2;
+            // slots past a row's length read as all ones) and the wave sorts
+            // the RB rows together with the wave-wide bitonic network (rows
+            // past the list are all ones and are not written)
             const int lane = lane_id(), wv = threadIdx.x >> 6;
-            if (threadIdx.x == 0) s_nmid = 0;
+            if (threadIdx.x == 0) {
+                s_nmid = 0;
+                s_nbig = 0;
+            }
             __syncthreads();
             const bool midr = row && dq > (uint32_t)LM && dq <= (uint32_t)SC;
-            const uint64_t mm = ballot(midr);
+            const bool big = midr && dq > 64u;
+            const uint64_t mm = ballot(midr && !big), mb = ballot(big);
             if (mm) {
                 uint32_t at = 0;
                 if (lane == 0) at = atomicAdd(&s_nmid, (uint32_t)__popcll(mm));
                 at = uniform((uint32_t)__shfl((int)at, 0));
-                if (midr) s_mid[at + lanes_below(mm)] = (uint16_t)threadIdx.x;
+                if (midr && !big) s_mid[at + lanes_below(mm)] = (uint16_t)threadIdx.x;
+            }
+            if (mb) {
+                uint32_t at = 0;
+                if (lane == 0) at = atomicAdd(&s_nbig, (uint32_t)__popcll(mb));
+                at = uniform((uint32_t)__shfl((int)at, 0));
+                if (big) s_mid[kChunkRows - 1 - (at + lanes_below(mb))] = (uint16_t)threadIdx.x;
             }
             __syncthreads();
-            const uint32_t nmid = s_nmid;
-            uint64_t *rb = &s_rank[wv][0];
-            const ulonglong2 *rb2 = reinterpret_cast<const ulonglong2 *>(rb);
-            // RB rows per round, their lengths, offsets and keys loaded
-            // together (a key past SC is not read: the stash row ends there)
-            constexpr int RB = KP == 1 ? 4 : 2;
-            constexpr uint32_t NW = kChunkRows / 64;
-            for (uint32_t m0 = wv; m0 < nmid; m0 += RB * NW) {
-                uint32_t n[RB];
-                int64_t ot[RB];
-                uint64_t key[RB][KP];
+            auto sort_rows = [&](auto ks, uint32_t nlist, bool from_back) {
+                // RB rows per round, their lengths, offsets and keys loaded
+                // together (the stash row has SC >= 64*KS slots)
+                constexpr int KS = decltype(ks)::value;
+                constexpr int RB = KS == 1 ? 4 : 2;
+                constexpr uint32_t NW = kChunkRows / 64;
+                for (uint32_t m0 = wv; m0 < nlist; m0 += RB * NW) {
+                    uint32_t n[RB];
+                    int64_t ot[RB];
+                    uint64_t v[RB][KS];
 #pragma unroll
-                for (int k = 0; k < RB; ++k) {
-                    const uint32_t m = m0 + k * NW;
-                    n[k] = 0;
-                    ot[k] = 0;
+                    for (int k = 0; k < RB; ++k) {
+                        const uint32_t m = m0 + k * NW;
+                        n[k] = 0;
+                        ot[k] = 0;
 #pragma unroll
-                    for (int p = 0; p < KP; ++p) key[k][p] = ~0ull;
-                    if (m < nmid) {
-                        const int64_t qr = ch.r0 + (int64_t)uniform((uint32_t)s_mid[m]);
-                        n[k] = b.deg[qr];
-                        ot[k] = b.offs[qr];
-#pragma unroll
-                        for (int p = 0; p < KP; ++p)
-                            if (lane + 64 * p < SC) key[k][p] = b.stash[qr * SC + lane + 64 * p];
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < RB; ++k) {
-                    if (n[k] == 0) break;
-                    uint64_t kk[KP];
-                    uint32_t rank[KP];
-#pragma unroll
-                    for (int p = 0; p < KP; ++p) {
-                        kk[p] = (uint32_t)(lane + 64 * p) < n[k] ? key[k][p] : ~0ull;
-                        rb[lane + 64 * p] = kk[p];
-                        rank[p] = 0;
-                    }
-                    wave_lds_sync();
-                    for (uint32_t i = 0; i < n[k]; i += 8) {
-                        ulonglong2 c[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) c[u] = rb2[i / 2 + u];
-#pragma unroll
-                        for (int p = 0; p < KP; ++p)
-#pragma unroll
-                            for (int u = 0; u < 4; ++u)
-                                rank[p] += (c[u].x < kk[p] ? 1u : 0u) + (c[u].y < kk[p] ? 1u : 0u);
-                    }
-                    wave_lds_sync();
-                    const uint32_t keep = (kn.K > 0 && n[k] > (uint32_t)kn.K) ? (uint32_t)kn.K : n[k];
-#pragma unroll
-                    for (int p = 0; p < KP; ++p) {
-                        if ((uint32_t)(lane + 64 * p) < n[k] && rank[p] < keep) {
-                            const uint32_t j = (uint32_t)kk[p];
-                            const float d = __uint_as_float((uint32_t)(kk[p] >> 32));
-                            if (staged) {
-                                sidx[ot[k] - base + rank[p]] = j;
-                                sd2[ot[k] - base + rank[p]] = d;
+                        for (int p = 0; p < KS; ++p) v[k][p] = ~0ull;
+                        if (m < nlist) {
+                            const uint32_t slot = from_back ? kChunkRows - 1 - m : m;
+                            const int64_t qr = ch.r0 + (int64_t)uniform((uint32_t)s_mid[slot]);
+                            n[k] = b.deg[qr];
+                            ot[k] = b.offs[qr];
+                            const uint64_t *sr = b.stash + qr * SC + lane * KS;
+                            if constexpr (KS == 2) {
+                                const ulonglong2 t = *reinterpret_cast<const ulonglong2 *>(sr);
+                                v[k][0] = t.x;
+                                v[k][1] = t.y;
                             } else {
-                                b.out->indices[ot[k] + rank[p]] = (int32_t)j;
-                                if (b.out->dist2) b.out->dist2[ot[k] + rank[p]] = d;
+                                v[k][0] = sr[0];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < RB; ++k)
+#pragma unroll
+                        for (int p = 0; p < KS; ++p)
+                            if ((uint32_t)(lane * KS + p) >= n[k]) v[k][p] = ~0ull;
+                    wave_bitonic<KS, RB>(v, lane);
+#pragma unroll
+                    for (int k = 0; k < RB; ++k) {
+                        const uint32_t keep = (kn.K > 0 && n[k] > (uint32_t)kn.K) ? (uint32_t)kn.K : n[k];
+#pragma unroll
+                        for (int p = 0; p < KS; ++p) {
+                            const uint32_t e = (uint32_t)(lane * KS + p);
+                            if (e < keep) {
+                                const uint32_t jj = (uint32_t)v[k][p];
+                                const float d = __uint_as_float((uint32_t)(v[k][p] >> 32));
+                                if (staged) {
+                                    sidx[ot[k] - base + e] = jj;
+                                    sd2[ot[k] - base + e] = d;
+                                } else {
+                                    b.out->indices[ot[k] + e] = (int32_t)jj;
+                                    if (b.out->dist2) b.out->dist2[ot[k] + e] = d;
+                                }
                             }
                         }
                     }
                 }
-            }
+            };
+            sort_rows(std::integral_constant<int, 1>{}, s_nmid, false);
+            if constexpr (SC > 64) sort_rows(std::integral_constant<int, 2>{}, s_nbig, true);
         }
         if (staged) {
             __syncthreads();
