@@ -268,8 +268,8 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
     w = inputs.paper_shaped()
     x = torch.from_numpy(w.points).cuda()
 
-    def step_batch():
-        c = frnn.query_batch([x], w.r, w.K, exclude_self=True)[0]
+    def step_batch(opts=None):
+        c = frnn.query_batch([x], w.r, w.K, exclude_self=True, opts=opts)[0]
         n = c.nnz
         c.release()
         return n
@@ -284,6 +284,9 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
 
     dt, nnz = time_steps(step_batch, steps, warmup)
     stats = frnn.last_stats()
+    o128 = frnn.default_opts(stash_cap=128)
+    dt128, nnz128 = time_steps(lambda: step_batch(o128), steps, warmup)
+    assert nnz128 == nnz
     dt_api, nnz_api = time_steps(step_api, steps, warmup)
     assert nnz_api == nnz
     # per-launch HIP events for the kernel durations
@@ -301,6 +304,7 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
             "ms_per_step": dt / steps * 1e3, "pairs_per_step": nnz,
             "pairs_per_s": nnz * steps / dt, "events_per_s": steps / dt,
             "api_ms_per_step": dt_api / steps * 1e3,
+            "stash128_ms_per_step": dt128 / steps * 1e3,
             "candidates_per_pair": stats["candidates"] / max(nnz, 1),
             "kernels_us": {k: round(v[1] / max(v[0], 1) * 1e3, 1) for k, v in prof.items()},
             "paper_context": {"exact_device_p50_ms": 267.829, "rerun_device_p50_ms": 207.299,
@@ -599,13 +603,16 @@ def bench_density(frnn, steps=10, warmup=3):
     x = torch.from_numpy(w.points).cuda()
     q = torch.from_numpy(w.queries).cuda()
 
-    def step():
-        c = frnn.query_batch([x], w.r, w.K, queries=[q])[0]
+    def step(opts=None):
+        c = frnn.query_batch([x], w.r, w.K, queries=[q], opts=opts)[0]
         n = c.nnz
         c.release()
         return n
     dt, nnz = time_steps(step, steps, warmup)
     stats = frnn.last_stats()
+    o128 = frnn.default_opts(stash_cap=128)
+    dt128, nnz128 = time_steps(lambda: step(o128), steps, warmup)
+    assert nnz128 == nnz
     frnn.profile_enable(True)
     frnn.profile_read(reset=True)
     for _ in range(3):
@@ -623,6 +630,7 @@ def bench_density(frnn, steps=10, warmup=3):
             "ms_per_step": dt / steps * 1e3, "pairs_per_step": nnz, "pairs_per_s": nnz * steps / dt,
             "queries_per_s": 200_000 * steps / dt, "candidates_per_pair": cand / max(nnz, 1),
             "kernels_us": kus,
+            "stash128_ms_per_step": dt128 / steps * 1e3,
             "count_roofline": {"achieved": ops / cnt_s / 1e12 if cnt_s else None, "peak": VALU_PEAK_OPS / 1e12,
                                "unit": "TFLOP/s", "frac": (ops / cnt_s) / VALU_PEAK_OPS if cnt_s else None,
                                "ops_per_launch": ops, "candidates": cand}}
