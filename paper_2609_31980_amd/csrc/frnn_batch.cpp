@@ -327,7 +327,11 @@ void BatchContext::upload(hipStream_t, const OutDesc *od) {
     if (od) std::memcpy(stage_.host() + kOutOff, od, sizeof(OutDesc));
 }
 
-void BatchContext::launch_a(hipStream_t s) {
+Publish BatchContext::publish_args() {
+    return Publish{hv.get(), back_.dev(), (int64_t)hv16_, reinterpret_cast<uint32_t *>(back_.dev()) + 4 * hv16_};
+}
+
+void BatchContext::launch_a(hipStream_t s, bool publish) {
     const bool selfq = sh_.flags & FRNN_SELF_QUERY;
     const int D = sh_.D;
     // build and query counters in one launch
@@ -346,25 +350,27 @@ void BatchContext::launch_a(hipStream_t s) {
     }
     LAUNCH("count", s, launch_count(bq_, kn_, D, query_blocks(sh_.o, sh_.qch_cap, kn_.persistent), s));
     LAUNCH("scan_rows", s, launch_scan_rows(bq_, kn_, sh_.q_cap, s));
-    LAUNCH("publish", s, launch_publish(hv.get(), back_.dev(), (int64_t)hv16_,
-                                         reinterpret_cast<uint32_t *>(back_.dev()) + 4 * hv16_, s));
+    if (publish) LAUNCH("publish", s, launch_publish(publish_args(), s));
 }
 
 // (the host reads the counts as soon as they are published, while the
 // fill runs)
+// (the short-row pass, launched right after the row scan, performs the
+// read-back in its first block: one launch less)
 void BatchContext::launch_ab(hipStream_t s) {
-    launch_a(s);
-    launch_b_short(s);
+    launch_a(s, false);
+    launch_b_short(s, true);
 }
 
 void BatchContext::launch_abl(hipStream_t s) {
-    launch_a(s);
-    launch_b_short(s);
+    launch_a(s, false);
+    launch_b_short(s, true);
     launch_b_long(s);
 }
 
-void BatchContext::launch_b_short(hipStream_t s) {
-    LAUNCH("short_rows", s, launch_short_rows(bq_, kn_, sh_.qch_cap, s));
+void BatchContext::launch_b_short(hipStream_t s, bool publish) {
+    const Publish p = publish_args();
+    LAUNCH("short_rows", s, launch_short_rows(bq_, kn_, sh_.qch_cap, s, publish ? &p : nullptr));
 }
 
 void BatchContext::launch_b_long(hipStream_t s) {

@@ -14,10 +14,11 @@
 // Run exactly, A and B are separated by the read-back that sizes the output.
 // Once a context has run, its next batch is run speculatively instead: the
 // output is allocated at a capacity guessed from the previous run, and A
-// and B are launched together (one graph when replayed), so the host checks
-// the counts while B runs; the fill kernels write nothing when the run does
-// not fit, and only then does the host allocate the exact size and run B
-// again.
+// and B are launched together (one graph when replayed; the first block of
+// the short-row pass then publishes the counts, one launch less), so the
+// host checks the counts while B runs; the fill kernels write nothing when
+// the run does not fit, and only then does the host allocate the exact size
+// and run B again.
 // The count and fill kernels take windows of sorted queries (runs of cell
 // blocks of one event) as work items: one wave per window from the
 // hardware's dispatch, or, persistent (frnn_opts.persistent), a resident
@@ -115,8 +116,9 @@ public:
     int replays = 0;
 
 private:
-    void launch_a(hipStream_t s);
-    void launch_b_short(hipStream_t s);
+    void launch_a(hipStream_t s, bool publish = true);
+    void launch_b_short(hipStream_t s, bool publish = false);
+    Publish publish_args();
     void launch_b_long(hipStream_t s);
     void launch_ab(hipStream_t s);
     void launch_abl(hipStream_t s);

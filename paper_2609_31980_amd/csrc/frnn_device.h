@@ -109,6 +109,17 @@ struct OutDesc {
                            // recount of a row differed from the count pass
 };
 
+// The read-back of a run's counts (passed by value to the kernel that
+// performs it): n16 16-byte words from src (the counters first, then the
+// event bases) to dst, device-mapped host memory, then the counters' run
+// number into *flag.  All 16-byte aligned; flag null: no read-back.
+struct Publish {
+    const void *src;
+    void *dst;
+    int64_t n16;
+    uint32_t *flag;
+};
+
 // Per-run scalars passed by value.
 struct Knobs {
     float r2;              // fl32(r*r), computed on the host

@@ -1558,8 +1558,11 @@ __device__ __forceinline__ void place_row(uint64_t (&v)[N], uint32_t keep, bool 
     }
 }
 
+__device__ __forceinline__ void publish_block(const Publish &p);
+
 template <int SC>
-__global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu(5))) k_short_rows(Bufs b, Knobs kn) {
+__global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu(5))) k_short_rows(Bufs b, Knobs kn,
+                                                                                                   Publish pub) {
     // rows of up to LM keys: one lane per row; longer stash rows (up to SC):
     // one wave per row, ranked
     constexpr int LM = SC < 16 ? SC : 16;
@@ -1568,6 +1571,9 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
     __shared__ float sd2[SC > 0 ? kShortStage : 1];
     __shared__ uint16_t s_mid[SC > LM ? kChunkRows : 1];  // rows of LM+1..SC keys
     __shared__ uint32_t s_nmid, s_nbig;
+    // the read-back of the counts when this launch follows the count pass
+    // directly (the host needs them whether or not the output fits)
+    if (pub.flag && blockIdx.x == 0) publish_block(pub);
     if (!out_fits(b)) return;
     if (blockIdx.x == 0)  // each event's leading offset, the one entry no row writes
         for (int e = threadIdx.x; e < b.bd->E; e += blockDim.x) b.out->offsets[b.ev[e].q_off + e] = 0;
@@ -1808,14 +1814,18 @@ __global__ void __launch_bounds__(256) k_long_sort(Bufs b, Knobs kn) {
 // bases (the query counters first) into device-mapped host memory, then,
 // after a system-scope fence, stores the counters' run number into *flag,
 // which the host polls: once it reads this run's number the block is whole.
-__global__ void __launch_bounds__(256) k_publish(const uint4 *src, uint4 *dst, int64_t n16, uint32_t *flag) {
-    for (int64_t i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+__device__ __forceinline__ void publish_block(const Publish &p) {
+    const uint4 *src = static_cast<const uint4 *>(p.src);
+    uint4 *dst = static_cast<uint4 *>(p.dst);
+    for (int64_t i = threadIdx.x; i < p.n16; i += blockDim.x) dst[i] = src[i];
     __threadfence_system();
     __syncthreads();
     if (threadIdx.x == 0)
-        __hip_atomic_store(flag, reinterpret_cast<const Counters *>(src)->run_id, __ATOMIC_RELEASE,
+        __hip_atomic_store(p.flag, static_cast<const Counters *>(p.src)->run_id, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_SYSTEM);
 }
+
+__global__ void __launch_bounds__(256) k_publish(Publish p) { publish_block(p); }
 
 // Writes the output descriptor from kernel arguments (so the values are
 // captured at launch time, unlike a copy from host memory).
@@ -2060,16 +2070,17 @@ hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStr
     return launch_query_t<true>(b, kn, D, blocks, s);
 }
 
-hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s) {
+hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s, const Publish *pub) {
     static_assert(kChunkRows == 256, "one block per chunk");
     dim3 grid(std::max(1, nqchunks)), block(kChunkRows);
+    const Publish p = pub ? *pub : Publish{};
     switch (kn.stash_cap) {
-    case 0: emit(k_short_rows<0>, grid, block, 0, s, b, kn); break;
-    case 8: emit(k_short_rows<8>, grid, block, 0, s, b, kn); break;
-    case 16: emit(k_short_rows<16>, grid, block, 0, s, b, kn); break;
-    case 32: emit(k_short_rows<32>, grid, block, 0, s, b, kn); break;
-    case 64: emit(k_short_rows<64>, grid, block, 0, s, b, kn); break;
-    case 128: emit(k_short_rows<128>, grid, block, 0, s, b, kn); break;
+    case 0: emit(k_short_rows<0>, grid, block, 0, s, b, kn, p); break;
+    case 8: emit(k_short_rows<8>, grid, block, 0, s, b, kn, p); break;
+    case 16: emit(k_short_rows<16>, grid, block, 0, s, b, kn, p); break;
+    case 32: emit(k_short_rows<32>, grid, block, 0, s, b, kn, p); break;
+    case 64: emit(k_short_rows<64>, grid, block, 0, s, b, kn, p); break;
+    case 128: emit(k_short_rows<128>, grid, block, 0, s, b, kn, p); break;
     default: return hipErrorInvalidValue;
     }
     FRNN_CHECK_LAUNCH();
@@ -2088,9 +2099,8 @@ hipError_t launch_lpt(const Bufs &b, const Knobs &kn, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t launch_publish(const void *src, void *dst, int64_t n16, uint32_t *flag, hipStream_t s) {
-    emit(k_publish, dim3(1), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src), reinterpret_cast<uint4 *>(dst),
-         n16, flag);
+hipError_t launch_publish(const Publish &p, hipStream_t s) {
+    emit(k_publish, dim3(1), dim3(256), 0, s, p);
     FRNN_CHECK_LAUNCH();
     return hipSuccess;
 }

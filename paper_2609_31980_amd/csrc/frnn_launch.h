@@ -41,8 +41,10 @@ hipError_t launch_scatter(const Bufs &b, int nchunks, bool queries, hipStream_t 
 hipError_t launch_count(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
 hipError_t launch_scan_rows(const Bufs &b, const Knobs &kn, int64_t total_q, hipStream_t s);
 // rows of at most stash_cap pairs, and every row's per-event offset: one
-// block per query chunk
-hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s);
+// block per query chunk; with pub, its first block also performs that
+// read-back of the counts (in place of launch_publish)
+hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipStream_t s,
+                             const Publish *pub = nullptr);
 // the windows listed by the count pass; any grid size is correct
 hipError_t launch_fill(const Bufs &b, const Knobs &kn, int D, int blocks, hipStream_t s);
 hipError_t launch_long_sort(const Bufs &b, const Knobs &kn, int blocks, hipStream_t s);
@@ -51,8 +53,7 @@ int count_resident_blocks(const Knobs &kn, int D);
 // work order of the persistent count pass (needs the grids and b.lpt)
 hipError_t launch_lpt(const Bufs &b, const Knobs &kn, hipStream_t s);
 hipError_t launch_set_out(const Bufs &b, const OutDesc &v, hipStream_t s);
-// the read-back: n16 16-byte words from src (counters first) to dst, then
-// the counters' run number into *flag (all 16-byte aligned), one block
-hipError_t launch_publish(const void *src, void *dst, int64_t n16, uint32_t *flag, hipStream_t s);
+// the read-back (one block): see Publish
+hipError_t launch_publish(const Publish &p, hipStream_t s);
 
 }  // namespace frnn
