@@ -304,9 +304,10 @@ void frnn_server_destroy(frnn_server s);
 
 /* ---------------------------------------------------------------- tuning
  * Times candidate frnn_opts on the given input (a batched self-query with K)
- * by coordinate descent over the grid axes, cells per point, cells and
- * queries per work item, stash size, persistent launch, blocks per CU and
- * graph replay, and returns the fastest whose output is bit-identical to the
+ * by coordinate descent (a second pass when the first changed anything)
+ * over the grid axes, cells per point, cells and queries per work item,
+ * stash size, persistent launch, blocks per CU and graph replay, and
+ * returns the fastest whose output is bit-identical to the
  * default's.  The result is cached per (device, D, K, density class) in the
  * JSON file named by FRNN_TUNE_CACHE, if set; the density class is the pair
  * of half-octaves of the mean candidates and mean neighbours per query of

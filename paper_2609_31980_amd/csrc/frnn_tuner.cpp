@@ -2,7 +2,7 @@
 //
 // Coordinate descent from the defaults: each parameter in turn takes each of
 // its candidate values with the others held, and the fastest setting is
-// kept.  A candidate is timed as one batched self-query of the event (the
+// kept; a second pass runs when the first changed anything.  A candidate is timed as one batched self-query of the event (the
 // graph-replayed path, the user's wall time including the count read-back)
 // over a few repetitions, and its CSR must be bit-identical to the default
 // setting's; a mismatch is counted as rejected and never chosen.  Winners
@@ -224,45 +224,52 @@ extern "C" frnn_status frnn_tune(const float *points, int64_t N, int32_t D, floa
                 cur = cand;
             }
         };
-        for (int v : axes) {
-            frnn_opts c = cur;
-            c.grid_axes_max = std::min<int>(v, D);
-            consider(c);
-        }
-        for (float v : cpps) {
-            frnn_opts c = cur;
-            c.cells_per_point = v;
-            consider(c);
-        }
-        for (int v : cpis) {
-            frnn_opts c = cur;
-            c.cells_per_item = v;
-            consider(c);
-        }
-        for (int v : qpis) {
-            frnn_opts c = cur;
-            c.queries_per_item = v;
-            consider(c);
-        }
-        for (int v : stashes) {
-            frnn_opts c = cur;
-            c.stash_cap = v;
-            consider(c);
-        }
-        for (int v : pers) {
-            frnn_opts c = cur;
-            c.persistent = v;
-            consider(c);
-        }
-        for (int v : bpcs) {
-            frnn_opts c = cur;
-            c.blocks_per_cu = v;
-            consider(c);
-        }
-        for (int v : graphs) {
-            frnn_opts c = cur;
-            c.graphs = v;
-            consider(c);
+        // two passes over the parameters (the second only when the first
+        // moved): a setting that pays only beside another one (a larger
+        // stash with smaller windows, say) is reached from either side
+        for (int pass = 0; pass < 2; ++pass) {
+            const frnn_opts start = cur;
+            for (int v : axes) {
+                frnn_opts c = cur;
+                c.grid_axes_max = std::min<int>(v, D);
+                consider(c);
+            }
+            for (float v : cpps) {
+                frnn_opts c = cur;
+                c.cells_per_point = v;
+                consider(c);
+            }
+            for (int v : cpis) {
+                frnn_opts c = cur;
+                c.cells_per_item = v;
+                consider(c);
+            }
+            for (int v : qpis) {
+                frnn_opts c = cur;
+                c.queries_per_item = v;
+                consider(c);
+            }
+            for (int v : stashes) {
+                frnn_opts c = cur;
+                c.stash_cap = v;
+                consider(c);
+            }
+            for (int v : pers) {
+                frnn_opts c = cur;
+                c.persistent = v;
+                consider(c);
+            }
+            for (int v : bpcs) {
+                frnn_opts c = cur;
+                c.blocks_per_cu = v;
+                consider(c);
+            }
+            for (int v : graphs) {
+                frnn_opts c = cur;
+                c.graphs = v;
+                consider(c);
+            }
+            if (std::memcmp(&start, &cur, sizeof cur) == 0) break;
         }
         *best = cur;
         if (report) {
