@@ -259,6 +259,12 @@ def bench_host(frnn, pts, r, K, steps=10, warmup=2):
             "bytes_in": int(pts.nbytes), "bytes_out": int(out_bytes)}
 
 
+# settings for dense rows, timed beside the defaults (every setting gives the
+# same output; the larger stashes cost 8 bytes per query and key)
+DENSE_SETTINGS = {"stash128": dict(stash_cap=128), "stash256": dict(stash_cap=256),
+                  "stash256_one_cell_window16": dict(stash_cap=256, cells_per_item=1, queries_per_item=16)}
+
+
 def bench_paper_shaped(frnn, steps=20, warmup=5):
     """The paper-shaped self-join (271,663 points, D=12, r=0.12, K=1000, self
     pairs excluded): the same batched step and build + query API as the headline.  The
@@ -284,9 +290,12 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
 
     dt, nnz = time_steps(step_batch, steps, warmup)
     stats = frnn.last_stats()
-    o128 = frnn.default_opts(stash_cap=128)
-    dt128, nnz128 = time_steps(lambda: step_batch(o128), steps, warmup)
-    assert nnz128 == nnz
+    dense = {}
+    for name, kw in DENSE_SETTINGS.items():
+        od = frnn.default_opts(**kw)
+        dtd, nnzd = time_steps(lambda: step_batch(od), steps, warmup)
+        assert nnzd == nnz
+        dense[name] = {"options": kw, "ms_per_step": dtd / steps * 1e3}
     # the autotuner on this event (a self-query of its points; its parity
     # gate compares every candidate with the default setting's output)
     otun, rep = frnn.tune(x, w.r, w.K)
@@ -309,7 +318,7 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
             "ms_per_step": dt / steps * 1e3, "pairs_per_step": nnz,
             "pairs_per_s": nnz * steps / dt, "events_per_s": steps / dt,
             "api_ms_per_step": dt_api / steps * 1e3,
-            "stash128_ms_per_step": dt128 / steps * 1e3,
+            "dense_settings": dense,
             "tuned": {"ms_per_step": dtt / steps * 1e3, "options": otun.as_dict(),
                       "tuner_default_ms": rep["default_ms"], "tuner_best_ms": rep["best_ms"],
                       "tried": rep["candidates_tried"], "density_class": rep["density_class"]},
@@ -618,9 +627,12 @@ def bench_density(frnn, steps=10, warmup=3):
         return n
     dt, nnz = time_steps(step, steps, warmup)
     stats = frnn.last_stats()
-    o128 = frnn.default_opts(stash_cap=128)
-    dt128, nnz128 = time_steps(lambda: step(o128), steps, warmup)
-    assert nnz128 == nnz
+    dense = {}
+    for name, kw in DENSE_SETTINGS.items():
+        od = frnn.default_opts(**kw)
+        dtd, nnzd = time_steps(lambda: step(od), steps, warmup)
+        assert nnzd == nnz
+        dense[name] = {"options": kw, "ms_per_step": dtd / steps * 1e3}
     # the autotuner on the references (it times self-queries; the queries
     # are drawn from the same clusters), applied to the query step
     log("density: tuning on the references")
@@ -644,7 +656,7 @@ def bench_density(frnn, steps=10, warmup=3):
             "ms_per_step": dt / steps * 1e3, "pairs_per_step": nnz, "pairs_per_s": nnz * steps / dt,
             "queries_per_s": 200_000 * steps / dt, "candidates_per_pair": cand / max(nnz, 1),
             "kernels_us": kus,
-            "stash128_ms_per_step": dt128 / steps * 1e3,
+            "dense_settings": dense,
             "tuned": {"ms_per_step": dtt / steps * 1e3, "options": otun.as_dict(),
                       "tuned_on": "self-query of the 1,000,000 references",
                       "tuner_default_ms": rep["default_ms"], "tuner_best_ms": rep["best_ms"],

@@ -89,7 +89,8 @@ typedef struct {
                                  when the windows are at most twice the resident waves */
     int32_t blocks_per_cu;    /* cap on resident blocks per CU of a persistent pass (1..16) */
     int32_t row_cap_lds;      /* rows longer than this sort in global memory (1..512) */
-    int32_t stash_cap;        /* hits per query kept by the count pass (0, 8, 16, 32, 64, 128; default 64);
+    int32_t stash_cap;        /* hits per query kept by the count pass (0, 8, 16, 32, 64, 128, 256;
+                                 default 64; 8 bytes per query each);
                                  the fill pass only re-evaluates rows longer than this */
     int32_t graphs;           /* batched calls: 1 replays each launch sequence as a HIP graph
                                  (recorded once per context), 0 (default) launches the kernels

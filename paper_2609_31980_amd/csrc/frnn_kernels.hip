@@ -1526,7 +1526,7 @@ __device__ __forceinline__ void sort_regs(uint64_t (&v)[N]) {
 // Every row's per-event offset, and the rows the count pass kept whole
 // (0 < length <= SC): one lane per query row, in output order, sorts the
 // row's keys in registers (rows of up to 16 keys); rows of 17..SC keys (the
-// 32-, 64- and 128-key stashes) are sorted by the whole wave with the
+// 32-, 64-, 128- and 256-key stashes) are sorted by the whole wave with the
 // bitonic network of the long-row sort.  The query chunks partition
 // each event's rows, so
 // chunk c covers global rows r0..r1-1 of one event and its output is the
@@ -1536,7 +1536,9 @@ __device__ __forceinline__ void sort_regs(uint64_t (&v)[N]) {
 // on the same stream, overwrites.
 // Staged output pairs per block: with the mid-row list the block stays
 // within 32 KB of LDS (five blocks per CU).
-constexpr int short_stage(int sc) { return sc > 64 ? kChunkRows * 27 / 2 : kChunkRows * 29 / 2; }
+constexpr int short_stage(int sc) {
+    return sc > 128 ? kChunkRows * 13 : sc > 64 ? kChunkRows * 27 / 2 : kChunkRows * 29 / 2;
+}
 
 template <int N>
 __device__ __forceinline__ void place_row(uint64_t (&v)[N], uint32_t keep, bool staged, int64_t rel,
@@ -1569,8 +1571,9 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
     constexpr int kShortStage = short_stage(SC);
     __shared__ uint32_t sidx[SC > 0 ? kShortStage : 1];
     __shared__ float sd2[SC > 0 ? kShortStage : 1];
-    __shared__ uint16_t s_mid[SC > LM ? kChunkRows : 1];  // rows of LM+1..SC keys
-    __shared__ uint32_t s_nmid, s_nbig;
+    __shared__ uint16_t s_mid[SC > LM ? kChunkRows : 1];  // rows of LM+1..min(SC, 128) keys
+    __shared__ uint16_t s_huge[SC > 128 ? kChunkRows : 1];  // rows of 129..SC keys
+    __shared__ uint32_t s_nmid, s_nbig, s_nhuge;
     // the read-back of the counts when this launch follows the count pass
     // directly (the host needs them whether or not the output fits)
     if (pub.flag && blockIdx.x == 0) publish_block(pub);
@@ -1630,27 +1633,30 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
         }
         if constexpr (SC > LM) {
             // stash rows of LM+1..SC keys: the block lists them in LDS (rows
-            // of up to 64 keys from the front of the list, longer ones from
-            // the back) and its waves take them in turn, RB at a time (a
-            // block of dense rows keeps all four busy); lane i holds keys
-            // KS*i .. KS*i + KS-1 of each row (KS = 1 up to 64 keys, else 2;
-            // slots past a row's length read as all ones) and the wave sorts
-            // the RB rows together with the wave-wide bitonic network (rows
-            // past the list are all ones and are not written)
+            // of up to 64 keys from the front of one list, 65..128 keys from
+            // its back, longer ones in a second list) and its waves take them
+            // in turn, RB at a time (a block of dense rows keeps all four
+            // busy); lane i holds keys KS*i .. KS*i + KS-1 of each row (KS =
+            // 1 up to 64 keys, 2 up to 128, else 4; slots past a row's length
+            // read as all ones) and the wave sorts the RB rows together with
+            // the wave-wide bitonic network (rows past the list are all ones
+            // and are not written)
             const int lane = lane_id(), wv = threadIdx.x >> 6;
             if (threadIdx.x == 0) {
                 s_nmid = 0;
                 s_nbig = 0;
+                s_nhuge = 0;
             }
             __syncthreads();
             const bool midr = row && dq > (uint32_t)LM && dq <= (uint32_t)SC;
-            const bool big = midr && dq > 64u;
-            const uint64_t mm = ballot(midr && !big), mb = ballot(big);
+            const bool huge = midr && dq > 128u;
+            const bool big = midr && dq > 64u && !huge;
+            const uint64_t mm = ballot(midr && dq <= 64u), mb = ballot(big);
             if (mm) {
                 uint32_t at = 0;
                 if (lane == 0) at = atomicAdd(&s_nmid, (uint32_t)__popcll(mm));
                 at = uniform((uint32_t)__shfl((int)at, 0));
-                if (midr && !big) s_mid[at + lanes_below(mm)] = (uint16_t)threadIdx.x;
+                if (midr && dq <= 64u) s_mid[at + lanes_below(mm)] = (uint16_t)threadIdx.x;
             }
             if (mb) {
                 uint32_t at = 0;
@@ -1658,8 +1664,17 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
                 at = uniform((uint32_t)__shfl((int)at, 0));
                 if (big) s_mid[kChunkRows - 1 - (at + lanes_below(mb))] = (uint16_t)threadIdx.x;
             }
+            if constexpr (SC > 128) {
+                const uint64_t mh = ballot(huge);
+                if (mh) {
+                    uint32_t at = 0;
+                    if (lane == 0) at = atomicAdd(&s_nhuge, (uint32_t)__popcll(mh));
+                    at = uniform((uint32_t)__shfl((int)at, 0));
+                    if (huge) s_huge[at + lanes_below(mh)] = (uint16_t)threadIdx.x;
+                }
+            }
             __syncthreads();
-            auto sort_rows = [&](auto ks, uint32_t nlist, bool from_back) {
+            auto sort_rows = [&](auto ks, uint32_t nlist, const uint16_t *list, bool from_back) {
                 // RB rows per round, their lengths, offsets and keys loaded
                 // together (the stash row has SC >= 64*KS slots)
                 constexpr int KS = decltype(ks)::value;
@@ -1678,14 +1693,17 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
                         for (int p = 0; p < KS; ++p) v[k][p] = ~0ull;
                         if (m < nlist) {
                             const uint32_t slot = from_back ? kChunkRows - 1 - m : m;
-                            const int64_t qr = ch.r0 + (int64_t)uniform((uint32_t)s_mid[slot]);
+                            const int64_t qr = ch.r0 + (int64_t)uniform((uint32_t)list[slot]);
                             n[k] = b.deg[qr];
                             ot[k] = b.offs[qr];
                             const uint64_t *sr = b.stash + qr * SC + lane * KS;
-                            if constexpr (KS == 2) {
-                                const ulonglong2 t = *reinterpret_cast<const ulonglong2 *>(sr);
-                                v[k][0] = t.x;
-                                v[k][1] = t.y;
+                            if constexpr (KS >= 2) {
+#pragma unroll
+                                for (int p = 0; p < KS; p += 2) {
+                                    const ulonglong2 t = *reinterpret_cast<const ulonglong2 *>(sr + p);
+                                    v[k][p] = t.x;
+                                    v[k][p + 1] = t.y;
+                                }
                             } else {
                                 v[k][0] = sr[0];
                             }
@@ -1718,8 +1736,9 @@ __global__ void __launch_bounds__(kChunkRows) __attribute__((amdgpu_waves_per_eu
                     }
                 }
             };
-            sort_rows(std::integral_constant<int, 1>{}, s_nmid, false);
-            if constexpr (SC > 64) sort_rows(std::integral_constant<int, 2>{}, s_nbig, true);
+            sort_rows(std::integral_constant<int, 1>{}, s_nmid, s_mid, false);
+            if constexpr (SC > 64) sort_rows(std::integral_constant<int, 2>{}, s_nbig, s_mid, true);
+            if constexpr (SC > 128) sort_rows(std::integral_constant<int, 4>{}, s_nhuge, s_huge, false);
         }
         if (staged) {
             __syncthreads();
@@ -2081,6 +2100,7 @@ hipError_t launch_short_rows(const Bufs &b, const Knobs &kn, int nqchunks, hipSt
     case 32: emit(k_short_rows<32>, grid, block, 0, s, b, kn, p); break;
     case 64: emit(k_short_rows<64>, grid, block, 0, s, b, kn, p); break;
     case 128: emit(k_short_rows<128>, grid, block, 0, s, b, kn, p); break;
+    case 256: emit(k_short_rows<256>, grid, block, 0, s, b, kn, p); break;
     default: return hipErrorInvalidValue;
     }
     FRNN_CHECK_LAUNCH();

@@ -334,8 +334,8 @@ frnn_status Opts::validate(std::string *why) const {
     if (o.persistent < 0 || o.persistent > 2) return bad("persistent must be 0, 1 or 2");
     if (o.row_cap_lds < 1 || o.row_cap_lds > kRowLds) return bad("row_cap_lds out of 1..512");
     if (o.stash_cap != 0 && o.stash_cap != 8 && o.stash_cap != 16 && o.stash_cap != 32 && o.stash_cap != 64 &&
-        o.stash_cap != 128)
-        return bad("stash_cap must be 0, 8, 16, 32, 64 or 128");
+        o.stash_cap != 128 && o.stash_cap != 256)
+        return bad("stash_cap must be 0, 8, 16, 32, 64, 128 or 256");
     if (o.graphs != 0 && o.graphs != 1) return bad("graphs must be 0 or 1");
     return FRNN_OK;
 }

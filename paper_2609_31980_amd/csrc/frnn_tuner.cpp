@@ -203,7 +203,7 @@ extern "C" frnn_status frnn_tune(const float *points, int64_t N, int32_t D, floa
         const float cpps[] = {0.5f, 1.f, 2.f, 4.f, 16.f, 32.f};
         const int cpis[] = {1, 2, 4};
         const int qpis[] = {8, 16, 32, 64};
-        const int stashes[] = {0, 8, 16, 32, 64, 128};
+        const int stashes[] = {0, 8, 16, 32, 64, 128, 256};
         const int pers[] = {0, 1, 2};
         const int bpcs[] = {4, 8, 16};
         const int graphs[] = {0, 1};

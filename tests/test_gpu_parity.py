@@ -157,7 +157,8 @@ def test_grid_options_same_output(orc, frnn):
                dict(cell_multiple=2, grid_axes_max=4), dict(cell_multiple=3, grid_axes_max=3),
                dict(cells_per_item=4), dict(queries_per_item=1), dict(queries_per_item=64),
                dict(persistent=0), dict(blocks_per_cu=1), dict(stash_cap=0), dict(stash_cap=8),
-               dict(stash_cap=32), dict(stash_cap=64), dict(stash_cap=128), dict(stash_cap=0, persistent=0),
+               dict(stash_cap=32), dict(stash_cap=64), dict(stash_cap=128), dict(stash_cap=256),
+               dict(stash_cap=0, persistent=0),
                dict(queries_per_item=8, persistent=1),
                dict(queries_per_item=2, cells_per_item=3)):
         got = gpu_csr(X, 0.1, 256, opts=frnn.default_opts(**kw))
@@ -246,8 +247,8 @@ def test_dense_ball_rows_far_above_k(orc, frnn):
 
 def test_stash_sizes_rows_of_every_length(orc, frnn):
     """Clustered 12-D points with rows of every length class (empty, up to
-    8, 16, 32, 64, 128 and up to ~480 keys): each stash size splits them
-    differently between the stash rows (lane-sorted up to 16 keys, wave-ranked
+    8, 16, 32, 64, 128, 256 and up to ~480 keys): each stash size splits them
+    differently between the stash rows (lane-sorted up to 16 keys, wave-sorted
     up to the stash size) and the fill pass; all must give the oracle's CSR,
     uncapped and with a cap between the stash sizes, on the single-event and
     the batched path."""
@@ -256,10 +257,10 @@ def test_stash_sizes_rows_of_every_length(orc, frnn):
     r = float(np.float32(0.12))
     want = {K: pinlib.as_tuple(orc.frnn(X, r, K, exclude_self=True)) for K in (1000, 40)}
     deg = np.diff(want[1000][0])
-    for lo, hi in ((0, 0), (1, 8), (9, 16), (17, 32), (33, 64), (65, 128), (129, 10**9)):
+    for lo, hi in ((0, 0), (1, 8), (9, 16), (17, 32), (33, 64), (65, 128), (129, 256), (257, 10**9)):
         assert np.any((deg >= lo) & (deg <= hi)), f"no row of length {lo}..{hi}"
     xd = torch.from_numpy(X).cuda()
-    for sc in (0, 8, 16, 32, 64, 128):
+    for sc in (0, 8, 16, 32, 64, 128, 256):
         o = frnn.default_opts(stash_cap=sc)
         for K in (1000, 40):
             say(f"stash {sc} K={K}")
