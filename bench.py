@@ -289,7 +289,7 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
         return n
 
     dt, nnz = time_steps(step_batch, steps, warmup)
-    stats = frnn.last_stats()
+    stats = frnn.last_stats()   # (the default options adapt to dense rows after the first run)
     dense = {}
     for name, kw in DENSE_SETTINGS.items():
         od = frnn.default_opts(**kw)
@@ -318,6 +318,7 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
             "ms_per_step": dt / steps * 1e3, "pairs_per_step": nnz,
             "pairs_per_s": nnz * steps / dt, "events_per_s": steps / dt,
             "api_ms_per_step": dt_api / steps * 1e3,
+            "default_run": {"stash_cap": stats["stash_cap"], "adapted": stats["adapted"]},
             "dense_settings": dense,
             "tuned": {"ms_per_step": dtt / steps * 1e3, "options": otun.as_dict(),
                       "tuner_default_ms": rep["default_ms"], "tuner_best_ms": rep["best_ms"],
@@ -626,7 +627,7 @@ def bench_density(frnn, steps=10, warmup=3):
         c.release()
         return n
     dt, nnz = time_steps(step, steps, warmup)
-    stats = frnn.last_stats()
+    stats = frnn.last_stats()   # (the default options adapt to dense rows after the first run)
     dense = {}
     for name, kw in DENSE_SETTINGS.items():
         od = frnn.default_opts(**kw)
@@ -656,6 +657,7 @@ def bench_density(frnn, steps=10, warmup=3):
             "ms_per_step": dt / steps * 1e3, "pairs_per_step": nnz, "pairs_per_s": nnz * steps / dt,
             "queries_per_s": 200_000 * steps / dt, "candidates_per_pair": cand / max(nnz, 1),
             "kernels_us": kus,
+            "default_run": {"stash_cap": stats["stash_cap"], "adapted": stats["adapted"]},
             "dense_settings": dense,
             "tuned": {"ms_per_step": dtt / steps * 1e3, "options": otun.as_dict(),
                       "tuned_on": "self-query of the 1,000,000 references",

@@ -95,6 +95,12 @@ typedef struct {
     int32_t graphs;           /* batched calls: 1 replays each launch sequence as a HIP graph
                                  (recorded once per context), 0 (default) launches the kernels
                                  one by one, which reached the first kernel sooner here */
+    int32_t adapt;            /* batched calls with stash_cap, cells_per_item and queries_per_item at
+                                 their defaults: 1 (default) lets a capacity class whose run had
+                                 long rows (keys of rows longer than the stash at least an eighth
+                                 of the stash slots) use, from its next batch on, a 256-key stash
+                                 (128 or 64 when the stash would exceed 4 GiB), one cell per work
+                                 item and windows of 16 queries; 0 keeps the options as given */
 } frnn_opts;
 
 void frnn_opts_default(frnn_opts *opts);
@@ -352,6 +358,8 @@ typedef struct {
     int64_t work_items;
     int64_t pairs;        /* output pairs (after the cap) */
     int64_t long_row_keys; /* keys of the rows longer than the stash (scratch rows of the fill pass) */
+    int32_t stash_cap;    /* the stash size the run used */
+    int32_t adapted;      /* 1 when frnn_opts.adapt chose the run's dense-row setting */
 } frnn_stats;
 
 frnn_status frnn_last_stats(frnn_stats *out);

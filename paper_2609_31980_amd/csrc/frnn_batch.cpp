@@ -602,9 +602,57 @@ void hand_out(const BatchContext &ctx, const BatchCounts &c, BatchOutput &bo, fr
     bo.own = nullptr;
 }
 
+// Dense-row adaptation (frnn_opts.adapt): capacity classes, keyed by their
+// shape under the options as given, whose run had long rows.  Their later
+// batches use a larger stash, one cell per work item and windows of 16
+// queries (every setting gives the same output; measured faster on inputs
+// whose rows outgrow the default stash, slower on short rows).
+namespace {
+std::mutex g_dense_mu;
+std::vector<BatchContext::Shape> g_dense;
+constexpr size_t kDenseMax = 64;          // classes remembered (oldest dropped)
+constexpr int64_t kDenseStashMax = 4ll << 30;  // bytes of stash a class may take
+
+bool adapt_eligible(const Opts &o) {
+    frnn_opts d;
+    frnn_opts_default(&d);
+    return o.o.adapt && o.o.stash_cap == d.stash_cap && o.o.cells_per_item == d.cells_per_item &&
+           o.o.queries_per_item == d.queries_per_item;
+}
+
+bool is_dense(const BatchContext::Shape &sh) {
+    std::lock_guard<std::mutex> g(g_dense_mu);
+    return std::find(g_dense.begin(), g_dense.end(), sh) != g_dense.end();
+}
+
+void mark_dense(const BatchContext::Shape &sh) {
+    std::lock_guard<std::mutex> g(g_dense_mu);
+    if (std::find(g_dense.begin(), g_dense.end(), sh) != g_dense.end()) return;
+    if (g_dense.size() >= kDenseMax) g_dense.erase(g_dense.begin());
+    g_dense.push_back(sh);
+}
+
+Opts dense_opts(const Opts &o, int64_t q_cap) {
+    Opts a = o;
+    a.o.stash_cap = 64;
+    for (int sc : {256, 128})
+        if (q_cap * sc * (int64_t)sizeof(uint64_t) <= kDenseStashMax) {
+            a.o.stash_cap = sc;
+            break;
+        }
+    a.o.cells_per_item = 1;
+    a.o.queries_per_item = 16;
+    return a;
+}
+}  // namespace
+
 frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32_t flags,
                       const Opts &o, hipStream_t s, frnn_csr *outs) {
-    BatchContext::Shape need = BatchContext::shape_for(ev, E, D, r, K, flags, o);
+    const BatchContext::Shape base = BatchContext::shape_for(ev, E, D, r, K, flags, o);
+    const bool eligible = adapt_eligible(o);
+    const bool adapted = eligible && is_dense(base);
+    const BatchContext::Shape need =
+        adapted ? BatchContext::shape_for(ev, E, D, r, K, flags, dense_opts(o, base.q_cap)) : base;
     std::unique_ptr<BatchContext> ctx = acquire_context(need, s);
     const bool want_d2 = flags & FRNN_WANT_DIST2;
     frnn_status st = FRNN_OK;
@@ -645,6 +693,11 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
         } else {
             ctx->learn(c);
             const bool long_rows = c.ctr.long_total > 0;
+            // long-row keys at least an eighth of the stash slots: the
+            // class's later batches take the dense-row setting
+            if (eligible && !adapted &&
+                (int64_t)c.ctr.long_total * 8 >= ctx->total_q() * (int64_t)std::max(1, need.o.stash_cap))
+                mark_dense(base);
             if (!spec || (int64_t)c.ctr.nnz > cap_pairs || (int64_t)c.ctr.long_total > cap_long) {
                 // exact size; a speculative fill (if any) wrote nothing
                 own.reset();
@@ -664,6 +717,8 @@ frnn_status batch_run(const frnn_event *ev, int E, int D, float r, int K, uint32
             stt.work_items = c.ctr.n_groups;
             stt.pairs = (int64_t)c.ctr.nnz;
             stt.long_row_keys = (int64_t)c.ctr.long_total;
+            stt.stash_cap = need.o.stash_cap;
+            stt.adapted = adapted ? 1 : 0;
             record_stats(stt);
         }
     } catch (...) {

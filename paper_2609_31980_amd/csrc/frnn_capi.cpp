@@ -80,6 +80,7 @@ void frnn_opts_default(frnn_opts *o) {
     o->row_cap_lds = kRowLds;
     o->stash_cap = 64;
     o->graphs = 0;
+    o->adapt = 1;
 }
 
 const char *frnn_status_str(frnn_status s) {

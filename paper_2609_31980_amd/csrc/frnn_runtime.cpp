@@ -337,6 +337,7 @@ frnn_status Opts::validate(std::string *why) const {
         o.stash_cap != 128 && o.stash_cap != 256)
         return bad("stash_cap must be 0, 8, 16, 32, 64, 128 or 256");
     if (o.graphs != 0 && o.graphs != 1) return bad("graphs must be 0 or 1");
+    if (o.adapt != 0 && o.adapt != 1) return bad("adapt must be 0 or 1");
     return FRNN_OK;
 }
 
@@ -678,6 +679,7 @@ frnn_status run_query(Index &ix, const QueryArgs &qa, hipStream_t s, frnn_csr *o
     st.work_items = c.n_groups;
     st.pairs = nnz;
     st.long_row_keys = (int64_t)c.long_total;
+    st.stash_cap = op.o.stash_cap;
     if (stats) *stats = st;
     record_stats(st);
     return FRNN_OK;

@@ -90,16 +90,18 @@ std::string cache_key(int D, int K, double cand_per_query, double pairs_per_quer
 
 const char *kFields[] = {"grid_axes_max", "cells_per_point", "cell_multiple", "cells_per_item",
                          "queries_per_item", "persistent", "blocks_per_cu", "row_cap_lds",
-                         "stash_cap", "graphs"};
+                         "stash_cap", "graphs", "adapt"};
 
 std::string opts_json(const frnn_opts &o) {
     char buf[512];
     std::snprintf(buf, sizeof buf,
                   "{\"grid_axes_max\": %d, \"cells_per_point\": %.9g, \"cell_multiple\": %d, "
                   "\"cells_per_item\": %d, \"queries_per_item\": %d, \"persistent\": %d, "
-                  "\"blocks_per_cu\": %d, \"row_cap_lds\": %d, \"stash_cap\": %d, \"graphs\": %d}",
+                  "\"blocks_per_cu\": %d, \"row_cap_lds\": %d, \"stash_cap\": %d, \"graphs\": %d, "
+                  "\"adapt\": %d}",
                   o.grid_axes_max, (double)o.cells_per_point, o.cell_multiple, o.cells_per_item,
-                  o.queries_per_item, o.persistent, o.blocks_per_cu, o.row_cap_lds, o.stash_cap, o.graphs);
+                  o.queries_per_item, o.persistent, o.blocks_per_cu, o.row_cap_lds, o.stash_cap, o.graphs,
+                  o.adapt);
     return buf;
 }
 
@@ -141,6 +143,7 @@ std::map<std::string, frnn_opts> read_cache(const std::string &path) {
             else if (!std::strcmp(fld, "row_cap_lds")) o.row_cap_lds = (int)v;
             else if (!std::strcmp(fld, "stash_cap")) o.stash_cap = (int)v;
             else if (!std::strcmp(fld, "graphs")) o.graphs = (int)v;
+            else if (!std::strcmp(fld, "adapt")) o.adapt = (int)v;
         }
         if (ok) m[key] = o;
         p = b1 + 1;
@@ -176,6 +179,7 @@ extern "C" frnn_status frnn_tune(const float *points, int64_t N, int32_t D, floa
         const char *cpath = std::getenv("FRNN_TUNE_CACHE");
         frnn_opts cur;
         frnn_opts_default(&cur);
+        cur.adapt = 0;  // every candidate runs as given
         HostCSR ref;
         const double t_def = time_opts(points, N, D, r, K, flags, cur, s, &ref);
         const frnn_stats st0 = last_stats();

@@ -36,7 +36,7 @@ class Opts(ctypes.Structure):
                 ("cell_multiple", ctypes.c_int32), ("cells_per_item", ctypes.c_int32),
                 ("queries_per_item", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("row_cap_lds", ctypes.c_int32),
-                ("stash_cap", ctypes.c_int32), ("graphs", ctypes.c_int32)]
+                ("stash_cap", ctypes.c_int32), ("graphs", ctypes.c_int32), ("adapt", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,7 +73,8 @@ class IndexInfo(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int64), ("work_items", ctypes.c_int64),
-                ("pairs", ctypes.c_int64), ("long_row_keys", ctypes.c_int64)]
+                ("pairs", ctypes.c_int64), ("long_row_keys", ctypes.c_int64),
+                ("stash_cap", ctypes.c_int32), ("adapted", ctypes.c_int32)]
 
 
 class KernelTime(ctypes.Structure):

@@ -41,7 +41,7 @@ def test_pure_host_calls():
     from paper_2609_31980_amd import frnn
     o = frnn.default_opts()
     assert o.grid_axes_max == 6 and o.queries_per_item == 32 and o.row_cap_lds == 512 and o.persistent == 2
-    assert o.cells_per_item == 2 and o.stash_cap == 64 and o.graphs == 0
+    assert o.cells_per_item == 2 and o.stash_cap == 64 and o.graphs == 0 and o.adapt == 1
     lib = frnn._lib
     assert lib.frnn_status_str(0) == b"ok"
     assert lib.frnn_status_str(5).startswith(b"query radius")

@@ -232,13 +232,41 @@ def test_batch_speculative_output_overflow(orc, frnn):
     assert len(want["dense"][1]) > 20 * len(want["sparse"][1])
     assert np.diff(want["dense"][0]).max() > 512  # rows sorted in global memory
     for graphs in (1, 0):
-        o_g = frnn.default_opts(graphs=graphs)
+        # (adapt off: the sequence must stay in one capacity class's context)
+        o_g = frnn.default_opts(graphs=graphs, adapt=0)
         for name in ("sparse", "dense", "dense", "sparse", "dense"):
             x = sparse if name == "sparse" else dense
             say(f"speculative batch {name} graphs={graphs}")
             o = frnn.query_batch([dev(x)], r, 0, opts=o_g)[0]
             pinlib.assert_csr_equal(_np(o), want[name], f"{name} graphs={graphs}")
             o.release()
+
+
+def test_batch_dense_rows_adapt(orc, frnn):
+    """With the default options, a capacity class whose run had long rows
+    runs its later batches with the dense-row setting (256-key stash, one
+    cell per work item, windows of 16); every run equals the oracle, and
+    with adapt = 0 the options stay as given."""
+    X, _ = inputs.clustered(12345, 0, 12, 0.022, 5)
+    r = float(np.float32(0.12))
+    want = pinlib.as_tuple(orc.frnn(X, r, 0, exclude_self=True))
+    xd = dev(X)
+    seen = []
+    for rep in range(3):
+        o = frnn.query_batch([xd], r, 0, exclude_self=True)[0]
+        pinlib.assert_csr_equal(_np(o), want, f"adapt run {rep}")
+        o.release()
+        st = frnn.last_stats()
+        seen.append((st["adapted"], st["stash_cap"]))
+    say(f"dense-row adaptation: {seen}")
+    assert seen[1] == (1, 256) and seen[2] == (1, 256)
+    o0 = frnn.default_opts(adapt=0)
+    for rep in range(2):
+        o = frnn.query_batch([xd], r, 0, exclude_self=True, opts=o0)[0]
+        pinlib.assert_csr_equal(_np(o), want, f"adapt=0 run {rep}")
+        o.release()
+        st = frnn.last_stats()
+        assert (st["adapted"], st["stash_cap"]) == (0, 64)
 
 
 def test_batch_long_rows_after_short_run(orc, frnn):
