@@ -155,8 +155,10 @@ typedef struct {
  * opts->persistent the resident waves drain them from a per-XCD queue,
  * costliest events first), the fixed launch sequence of a capacity class is
  * launched kernel by kernel or, with opts->graphs, recorded once as HIP
- * graphs and replayed when the same capacity recurs, and outs[e] is
- * bit-identical to querying event e alone.
+ * graphs and replayed when the same capacity recurs (with opts->adapt, a
+ * class whose rows outgrew the stash runs its later batches with the
+ * dense-row setting), and outs[e] is bit-identical to querying event e
+ * alone.
  * All events share D, r, K and flags.  The host waits once, for the counts
  * (published by the device into host-mapped memory); the fill may still be
  * running on the stream when the call returns, so the outputs are ready in
