@@ -265,7 +265,7 @@ DENSE_SETTINGS = {"stash128": dict(stash_cap=128), "stash256": dict(stash_cap=25
                   "stash256_one_cell_window16": dict(stash_cap=256, cells_per_item=1, queries_per_item=16)}
 
 
-def bench_paper_shaped(frnn, steps=20, warmup=5):
+def bench_paper_shaped(frnn, steps=20, warmup=5, tune=True):
     """The paper-shaped self-join (271,663 points, D=12, r=0.12, K=1000, self
     pairs excluded): the same batched step and build + query API as the headline.  The
     paper's own per-event times on its GPU are quoted as context only."""
@@ -298,9 +298,14 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
         dense[name] = {"options": kw, "ms_per_step": dtd / steps * 1e3}
     # the autotuner on this event (a self-query of its points; its parity
     # gate compares every candidate with the default setting's output)
-    otun, rep = frnn.tune(x, w.r, w.K)
-    dtt, nnzt = time_steps(lambda: step_batch(otun), steps, warmup)
-    assert nnzt == nnz
+    tuned = None
+    if tune:
+        otun, rep = frnn.tune(x, w.r, w.K)
+        dtt, nnzt = time_steps(lambda: step_batch(otun), steps, warmup)
+        assert nnzt == nnz
+        tuned = {"ms_per_step": dtt / steps * 1e3, "options": otun.as_dict(),
+                 "tuner_default_ms": rep["default_ms"], "tuner_best_ms": rep["best_ms"],
+                 "tried": rep["candidates_tried"], "density_class": rep["density_class"]}
     dt_api, nnz_api = time_steps(step_api, steps, warmup)
     assert nnz_api == nnz
     # per-launch HIP events for the kernel durations
@@ -320,9 +325,7 @@ def bench_paper_shaped(frnn, steps=20, warmup=5):
             "api_ms_per_step": dt_api / steps * 1e3,
             "default_run": {"stash_cap": stats["stash_cap"], "adapted": stats["adapted"]},
             "dense_settings": dense,
-            "tuned": {"ms_per_step": dtt / steps * 1e3, "options": otun.as_dict(),
-                      "tuner_default_ms": rep["default_ms"], "tuner_best_ms": rep["best_ms"],
-                      "tried": rep["candidates_tried"], "density_class": rep["density_class"]},
+            "tuned": tuned,
             "candidates_per_pair": stats["candidates"] / max(nnz, 1),
             "kernels_us": {k: round(v[1] / max(v[0], 1) * 1e3, 1) for k, v in prof.items()},
             "paper_context": {"exact_device_p50_ms": 267.829, "rerun_device_p50_ms": 207.299,
@@ -610,7 +613,7 @@ def bench_tuning(frnn):
     return out
 
 
-def bench_density(frnn, steps=10, warmup=3):
+def bench_density(frnn, steps=10, warmup=3, tune=True):
     """The density workload: 1,000,000 12-D references in Zipf-sized
     clusters, 200,000 separate queries, r=0.15 (mean degree about 100), K=64;
     one step = bin the references and the queries, count, fill."""
@@ -636,10 +639,16 @@ def bench_density(frnn, steps=10, warmup=3):
         dense[name] = {"options": kw, "ms_per_step": dtd / steps * 1e3}
     # the autotuner on the references (it times self-queries; the queries
     # are drawn from the same clusters), applied to the query step
-    log("density: tuning on the references")
-    otun, rep = frnn.tune(x, w.r, w.K)
-    dtt, nnzt = time_steps(lambda: step(otun), steps, warmup)
-    assert nnzt == nnz
+    tuned = None
+    if tune:
+        log("density: tuning on the references")
+        otun, rep = frnn.tune(x, w.r, w.K)
+        dtt, nnzt = time_steps(lambda: step(otun), steps, warmup)
+        assert nnzt == nnz
+        tuned = {"ms_per_step": dtt / steps * 1e3, "options": otun.as_dict(),
+                 "tuned_on": "self-query of the 1,000,000 references",
+                 "tuner_default_ms": rep["default_ms"], "tuner_best_ms": rep["best_ms"],
+                 "tried": rep["candidates_tried"], "density_class": rep["density_class"]}
     frnn.profile_enable(True)
     frnn.profile_read(reset=True)
     for _ in range(3):
@@ -659,10 +668,7 @@ def bench_density(frnn, steps=10, warmup=3):
             "kernels_us": kus,
             "default_run": {"stash_cap": stats["stash_cap"], "adapted": stats["adapted"]},
             "dense_settings": dense,
-            "tuned": {"ms_per_step": dtt / steps * 1e3, "options": otun.as_dict(),
-                      "tuned_on": "self-query of the 1,000,000 references",
-                      "tuner_default_ms": rep["default_ms"], "tuner_best_ms": rep["best_ms"],
-                      "tried": rep["candidates_tried"], "density_class": rep["density_class"]},
+            "tuned": tuned,
             "count_roofline": {"achieved": ops / cnt_s / 1e12 if cnt_s else None, "peak": VALU_PEAK_OPS / 1e12,
                                "unit": "TFLOP/s", "frac": (ops / cnt_s) / VALU_PEAK_OPS if cnt_s else None,
                                "ops_per_launch": ops, "candidates": cand}}
@@ -697,10 +703,11 @@ def main():
     from paper_2609_31980_amd import frnn, inputs
 
     if args.paper_only:
-        print(json.dumps({"paper_shaped": bench_paper_shaped(frnn, args.steps, args.warmup)}), flush=True)
+        print(json.dumps({"paper_shaped": bench_paper_shaped(frnn, args.steps, args.warmup, not args.no_tune)}),
+              flush=True)
         return
     if args.only:
-        fn = {"density": lambda: bench_density(frnn, args.steps, args.warmup),
+        fn = {"density": lambda: bench_density(frnn, args.steps, args.warmup, not args.no_tune),
               "batched": lambda: bench_batched(frnn, rounds=args.steps),
               "serving": lambda: bench_serving(frnn, args.serve_events, sweep_events=100, rounds=3)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
@@ -783,11 +790,11 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_paper:
         log("paper-shaped")
-        out["paper_shaped"] = bench_paper_shaped(frnn)
+        out["paper_shaped"] = bench_paper_shaped(frnn, tune=not args.no_tune)
         torch.cuda.empty_cache()
     if not args.no_density:
         log("density")
-        out["density"] = bench_density(frnn)
+        out["density"] = bench_density(frnn, tune=not args.no_tune)
         torch.cuda.empty_cache()
     tuned = None
     if not args.no_tune:
